@@ -1,0 +1,224 @@
+/*
+ * stag.h -- C ABI of the MI355X (gfx950) staggered-fermion RHMC library.
+ *
+ * The library implements the hot path of two-flavour staggered RHMC as set
+ * out in Gupta & Majumdar, arXiv:1710.09178: the even-odd staggered Dirac
+ * operator (Sec. 3.2), the multi-shift conjugate gradient for the
+ * partial-fraction rational functions of eq. (ratapprx) (Sec. 4), the
+ * pseudofermion and gauge forces and the leapfrog molecular dynamics of the
+ * HMC trajectory (Sec. 3.1), with the Metropolis test on the rational action.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: dims = {Nx, Ny, Nz, Nt}, all even and >= 2.  Site (x,y,z,t) has the
+ *   0-based lexicographic address l = x + Nx*(y + Ny*(z + Nz*t)) (Sec. 2) and
+ *   checkerboard parity (x+y+z+t) mod 2 (0 = even).  V = Nx*Ny*Nz*Nt, Vh = V/2.
+ * Operator: M = 2m + D (Sec. 3.2); D carries the Kogut-Susskind phases
+ *   eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z) and an
+ *   antiperiodic time boundary; the stored links are plain SU(3) matrices and
+ *   the signs are applied on the fly.  A = (M^dag M)_ee = 4m^2 - D_eo D_oe.
+ * Canonical (boundary) formats, little-endian IEEE doubles, C order:
+ *   gauge     complex128 U[t][z][y][x][mu][3][3]           (V*4*9*16 bytes)
+ *   half vec  complex128 psi[k][3], k = rank of the site among the sites of
+ *             one parity in lexicographic order              (Vh*3*16 bytes)
+ *   momentum  float64 P[t][z][y][x][mu][8], coordinates of sum_a P_a lambda_a/2
+ * Internal formats (what the compute entry points take): structure-of-arrays
+ *   device buffers sized by stag_field_bytes(); convert with the *_import /
+ *   *_export calls.  Their byte layout is private to the library.
+ * Pointers: every array argument is a DEVICE pointer (hipMalloc / torch CUDA
+ *   tensor), at least 16-byte aligned, owned by the caller, unless the
+ *   parameter says "host".  Host arrays are read during the call only.
+ * Streams: all work is ordered after prior work on the stream given to
+ *   stag_create and later work on that stream sees its results.  Calls that
+ *   return host-side numbers (solve info, actions, trajectory info) block until
+ *   those numbers are ready; the others return without waiting.
+ * Errors: every call returns a stag_status.  Arguments are validated before
+ *   any work is enqueued; on error nothing is modified and stag_last_error()
+ *   describes the problem.  STAG_ERR_NOT_CONVERGED is non-fatal: outputs hold
+ *   the last iterate and the info structure is filled.
+ * Threading: a handle must not be used by two threads at once.
+ * Memory: the library allocates its workspace in stag_create, stag_set_gauge
+ *   and on the first solve that needs more shift vectors than any earlier one;
+ *   it never allocates inside an iteration.
+ */
+#ifndef STAG_H
+#define STAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stag_ctx* stag_handle;
+
+typedef enum {
+    STAG_OK = 0,
+    STAG_ERR_INVALID_ARG = -1,   /* bad pointer, size, dims, parity, pole list */
+    STAG_ERR_NO_GAUGE = -2,      /* a compute call before stag_set_gauge */
+    STAG_ERR_NOT_CONVERGED = -3, /* solver hit maxiter; info is filled */
+    STAG_ERR_NONFINITE = -4,     /* NaN/Inf met in a reduction */
+    STAG_ERR_HIP = -6,           /* a HIP runtime call failed */
+    STAG_ERR_OOM = -7            /* device allocation failed */
+} stag_status;
+
+typedef enum {
+    STAG_FIELD_HALF_VEC = 0,        /* internal half-lattice colour vector */
+    STAG_FIELD_MOM = 1,             /* internal momentum / force field */
+    STAG_FIELD_CANON_HALF_VEC = 2,  /* canonical complex128 [Vh][3] */
+    STAG_FIELD_CANON_GAUGE = 3,     /* canonical complex128 [V][4][3][3] */
+    STAG_FIELD_CANON_MOM = 4        /* canonical float64 [V][4][8] */
+} stag_field_kind;
+
+/* Rational function r(x) = c0 + sum_k residue[k] / (x + pole[k])
+ * (eq. ratapprx).  pole[k] >= 0, at most STAG_MAX_POLES terms; host arrays. */
+#define STAG_MAX_POLES 48
+typedef struct {
+    int n;
+    double c0;
+    const double* residue;
+    const double* pole;
+} stag_rational;
+
+/* Filled by the solver entry points.  true_resid / iters_per_pole may be NULL;
+ * otherwise they are host arrays of length n (the number of poles). */
+typedef struct {
+    int iters;                  /* multi-shift iterations run */
+    int n;                      /* number of poles */
+    double* true_resid;         /* |b - (A + pole_k) x_k| / |b| per pole, FP64 */
+    int* iters_per_pole;        /* iteration at which pole k was frozen */
+    double seconds;             /* wall time of the call */
+} stag_solve_info;
+
+/* ---- lifecycle -------------------------------------------------------- */
+
+/* Create a handle for one lattice.  dims: host int[4] {Nx,Ny,Nz,Nt}, all even
+ * and >= 2, V < 2^31.  hip_stream: a hipStream_t (NULL = the null stream).
+ * Allocates the gauge field and the fixed workspace on the current device. */
+stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream);
+stag_status stag_destroy(stag_handle h);
+/* Message of the last failed call on h (or of the last failed stag_create when
+ * h is NULL).  The string lives until the next call on h. */
+const char* stag_last_error(stag_handle h);
+/* Bytes of one field of the given kind for this handle's lattice. */
+size_t stag_field_bytes(stag_handle h, int kind);
+
+/* ---- fields (Sec. 2 layouts) --------------------------------------------- */
+
+/* Copy a canonical gauge field into the handle (converted to the internal
+ * layout).  The links are used as given; they should be SU(3). */
+stag_status stag_set_gauge(stag_handle h, const double* U_canon);
+/* Write the handle's gauge field in the canonical layout. */
+stag_status stag_get_gauge(stag_handle h, double* U_canon_out);
+/* Convert a canonical half vector of parity 0/1 to the internal layout and back. */
+stag_status stag_vec_import(stag_handle h, void* out_internal, const double* canon_in, int parity);
+stag_status stag_vec_export(stag_handle h, double* canon_out, const void* in_internal, int parity);
+/* Convert a canonical momentum field to the internal layout and back. */
+stag_status stag_mom_import(stag_handle h, void* out_internal, const double* canon_in);
+stag_status stag_mom_export(stag_handle h, double* canon_out, const void* in_internal);
+
+/* ---- operators (Sec. 3.2) ----------------------------------------------- */
+
+/* out = D_oe in (out_parity = 1, in even) or D_eo in (out_parity = 0, in odd).
+ * in and out must not overlap. */
+stag_status stag_dslash(stag_handle h, void* out, const void* in, int out_parity);
+/* out_even = A in_even = (4 m^2 - D_eo D_oe) in_even.  in and out must not overlap. */
+stag_status stag_mdagm(stag_handle h, void* out_even, const void* in_even, double mass);
+
+/* ---- multi-shift CG (Sec. 4, eq. ratapprx) ------------------------------- */
+
+/* Solve (A + pole_k) x_k = b for all poles of r with one Krylov space, base
+ * system = smallest pole; pole k is frozen when its recursive residual falls
+ * below tol*|b|.  x_even: NULL or n internal even vectors (device pointers,
+ * held in a host array) receiving x_k.  sum_even: NULL or an internal even
+ * vector receiving r(A) b = c0 b + sum_k residue_k x_k.  b may not alias any
+ * output.  info may be NULL.  Returns NOT_CONVERGED if maxiter is reached. */
+stag_status stag_multishift_solve(stag_handle h, double mass, const stag_rational* r, double tol,
+                                  int maxiter, const void* b_even, void* const* x_even,
+                                  void* sum_even, stag_solve_info* info);
+
+/* ---- actions and forces (eq. pfact; Sec. 3.1) ---------------------------- */
+
+/* S_f = phi^dag r(A) phi with r the action's rational function (host out). */
+stag_status stag_fermion_action(stag_handle h, double mass, const stag_rational* r, double tol,
+                                int maxiter, const void* phi_even, double* S_out,
+                                stag_solve_info* info);
+/* Pseudofermion force F = -dS_f/dw for S_f = phi^dag r(A) phi, per link in
+ * algebra coordinates.  dt == 0: mom = F; otherwise mom += dt * F. */
+stag_status stag_fermion_force(stag_handle h, double mass, const stag_rational* r, double tol,
+                               int maxiter, const void* phi_even, void* mom, double dt,
+                               stag_solve_info* info);
+/* Wilson gauge force for S_g = beta sum_{x,mu<nu} (1 - Re tr P/3); same dt rule. */
+stag_status stag_gauge_force(stag_handle h, double beta, void* mom, double dt);
+/* S_g of the handle's links and the mean plaquette <Re tr P / 3> (host outs, may be NULL). */
+stag_status stag_gauge_action(stag_handle h, double beta, double* S_out, double* plaq_out);
+/* K = (1/2) sum over links and a of mom_a^2 (host out). */
+stag_status stag_kinetic_energy(stag_handle h, const void* mom, double* K_out);
+/* U <- exp(i dt p) U for every link, then projection back to SU(3)
+ * (Gram-Schmidt of rows 0,1; row 2 = conj(row0 x row1)). */
+stag_status stag_link_update(stag_handle h, const void* mom, double dt);
+
+/* ---- random fields (Philox4x32-10, Box-Muller) --------------------------- */
+
+/* Gaussian momenta, each coordinate N(0,1).  Stream: key = seed, counter =
+ * (draw index, field 0, traj); link 4l+mu uses draws 4(4l+mu)+q, q = 0..3. */
+stag_status stag_random_momentum(stag_handle h, uint64_t seed, uint64_t traj, void* mom_out);
+/* Gaussian even half vector with density exp(-xi^dag xi) (field 1; site k,
+ * colour q uses draw 3k+q, real/imag parts N(0,1/2)). */
+stag_status stag_random_source(stag_handle h, uint64_t seed, uint64_t traj, void* xi_even_out);
+/* Raw Philox4x32-10 words: out[4i..4i+3] = philox(ctr + (i,0,0,0), key) for
+ * i < n (ctr word 0 wraps mod 2^32).  ctr, key: host arrays. */
+stag_status stag_philox(const uint32_t ctr[4], const uint32_t key[2], size_t n, uint32_t* out_dev,
+                        void* hip_stream);
+
+/* ---- one RHMC trajectory (Sec. 3.1) -------------------------------------- */
+
+typedef struct {
+    double beta, mass, tau;
+    int n_steps;                  /* leapfrog steps, dt = tau / n_steps */
+    stag_rational r_md;           /* force: approximates x^(-1/2) */
+    stag_rational r_action;       /* action: approximates x^(-1/2) */
+    stag_rational r_heatbath;     /* heat bath: approximates x^(+1/4) */
+    double tol_md, tol_action;
+    int maxiter;
+    uint64_t seed, traj_index;    /* random stream of this trajectory */
+    const void* inject_mom;       /* NULL or internal momentum used instead of the RNG */
+    const void* inject_xi;        /* NULL or internal even vector used instead of the RNG */
+    double inject_u;              /* Metropolis uniform in [0,1), or < 0 to draw it */
+    int no_fermions;              /* 1: pure gauge trajectory (tests) */
+} stag_hmc_params;
+
+typedef struct {
+    double dH;
+    double K_old, Sg_old, Sf_old;
+    double K_new, Sg_new, Sf_new;
+    double plaquette;             /* of the configuration kept */
+    int accepted;
+    int cg_iters_total;
+    int n_solves;
+    double seconds;
+} stag_traj_info;
+
+/* Heat bath, leapfrog integration and Metropolis test on the handle's gauge
+ * field; on rejection the field is restored.  info may be NULL. */
+stag_status stag_md_trajectory(stag_handle h, const stag_hmc_params* p, stag_traj_info* info);
+
+/* ---- measurement and tuning (not part of the method) ---------------------- */
+
+/* Record a pair of hipEvents around each Dslash and shift-update launch of the
+ * following solves on h (at most max_launches launches in one solve); 0 turns
+ * recording off.  Resets the accumulated times. */
+stag_status stag_profile_enable(stag_handle h, int max_launches);
+/* Accumulated kernel milliseconds and launch counts since stag_profile_enable:
+ * index 0 = D_oe (odd <- even), 1 = D_eo with the fused CG epilogue,
+ * 2 = fused multi-shift vector update.  Host arrays of length 3, may be NULL. */
+stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
+/* Dslash work split: tps = threads cooperating on one output site (1, 2 or 4);
+ * chunk = solver iterations enqueued between two convergence polls (>= 1). */
+stag_status stag_tune(stag_handle h, int tps, int chunk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STAG_H */
