@@ -1,0 +1,214 @@
+"""Benchmark: FP64 multi-shift CG with the staggered Dslash at 32^3x8.
+
+One step = one complete multi-shift solve of (A + pole_k) x_k = b for the 12
+poles of the minimax x^(-1/4) approximation on [m^2, 64], m = 0.005,
+tolerance 1e-10, with all 12 solutions written out.  Inputs (links
+exp(i 0.2 H) projected to SU(3), Gaussian source) are synthetic, seeded, and
+resident in HBM before timing starts.
+
+value    = algorithmic HBM bytes of the whole solve / wall time of the solve
+           (GB/s; bytes counted per kernel from the data each one must move).
+roofline = the D_oe Dslash kernel inside the solve: 1248 algorithmic bytes per
+           output site / its average launch duration (hipEvents around every
+           launch of one extra profiled solve), against 8 TB/s.
+Also reported: the other solver kernels, iterations, true residuals, and the
+seconds per RHMC trajectory at 16^3x8 (20 leapfrog steps, exact force).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (32, 32, 32, 8)
+MASS = 0.005
+TOL = 1e-10
+TABLE = "xm025_n12_m0.005"
+# algorithmic bytes per output site (FP64, 18-real links)
+B_DOE = 1248            # 8 links x 144 B + in 48 B + out 48 B
+B_DEO_CG = 1344         # D_eo 1248 + read p and r (96) for the fused mass term and dots
+B_UPD_FIXED = 336       # r (rw) 96, Ap 48, p (rw) 96, x_base (rw) 96
+B_UPD_SHIFT = 192       # per active shifted system: x_k and p_k read and written
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def solve_bytes(vh, iters, ipp, base):
+    """Algorithmic bytes of one solve from the per-pole freeze iterations."""
+    total = 0
+    for it in range(1, iters + 1):
+        active = sum(1 for k, f in enumerate(ipp) if k != base and f >= it)
+        base_on = ipp[base] >= it
+        upd = B_UPD_FIXED - (0 if base_on else 96) + B_UPD_SHIFT * active
+        total += (B_DOE + B_DEO_CG + upd) * vh
+    return total
+
+
+def cpu_baseline(U, b, rat, vh, target_s=20.0):
+    """Time the CPU oracle's multi-shift CG on the same workload for a bounded
+    number of iterations and express it in the same unit (GB/s of algorithmic
+    solver traffic)."""
+    import numpy as np
+    from oracle import dirac
+    from oracle.solvers import multishift_cg
+    op = lambda v: dirac.apply_A(U, v, DIMS, MASS)
+    t0 = time.perf_counter()
+    multishift_cg(op, b, rat["pole"], 1e-30, maxiter=1)
+    one = time.perf_counter() - t0
+    iters = max(2, int(target_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    multishift_cg(op, b, rat["pole"], 1e-30, maxiter=iters)
+    dt = time.perf_counter() - t0
+    per_iter = (B_DOE + B_DEO_CG + B_UPD_FIXED + B_UPD_SHIFT * (len(rat["pole"]) - 1)) * vh
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": per_iter * iters / dt / 1e9, "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} multi-shift CG iterations of the same 32^3x8 12-pole solve (all shifts active), "
+                      f"{dt:.1f} s; numpy element-wise code runs on one core ({cores} available)",
+            "seconds": dt, "iterations": iters}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tps", type=int, default=0, help="Dslash threads per site (0 = library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-trajectory", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the domain-decomposed design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice
+
+    torch.cuda.set_device(0)
+    rng = synth.make_rng(1, 0)
+    U = synth.random_su3_near_identity(DIMS, 0.2, rng)
+    b = synth.gaussian_half_vector(DIMS, synth.make_rng(1, 1))
+    rat = synth.load_rational(TABLE)
+    n = len(rat["pole"])
+    base = int(np.argmin(rat["pole"]))
+    lat = Lattice(DIMS)
+    if args.tps:
+        lat.tune(args.tps, 16)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    bd = lat.vec_import(torch.from_numpy(b).cuda(), 0)
+    xs = [lat.new_vec() for _ in range(n)]
+    vh = lat.Vh
+
+    def step(resid=False):
+        return lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=resid)
+
+    log(f"warmup {args.warmup} solves")
+    info = None
+    for _ in range(args.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} solves")
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    bytes_total = sum(solve_bytes(vh, i["iters"], i["iters_per_pole"], base) for i in infos)
+    value = bytes_total / elapsed / 1e9
+
+    # one more solve: true residuals, and hipEvents around every kernel launch
+    log("profiled solve")
+    lat.profile_enable(3 * (infos[0]["iters"] + 64))
+    chk = step(resid=True)
+    ms, cnt = lat.profile_read()
+    lat.profile_enable(0)
+    avg_us = [1e3 * ms[i] / max(cnt[i], 1) for i in range(3)]
+    doe_gbs = B_DOE * vh / (avg_us[0] * 1e-6) / 1e9
+    deo_gbs = B_DEO_CG * vh / (avg_us[1] * 1e-6) / 1e9
+    upd_bytes = solve_bytes(vh, chk["iters"], chk["iters_per_pole"], base) - (B_DOE + B_DEO_CG) * vh * chk["iters"]
+    upd_gbs = upd_bytes / max(cnt[2], 1) / (avg_us[2] * 1e-6) / 1e9
+
+    traj = None
+    if not args.no_trajectory:
+        log("RHMC trajectory at 16^3x8")
+        traj = trajectory_timing()
+
+    out = {
+        "metric": "multishift-CG Dslash GB/s (% HBM peak) at 32^3x8; sec/RHMC trajectory",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fp64 multi-shift CG, staggered even-odd operator, 32^3x8, 12 poles of x^(-1/4), "
+                               "m=0.005, tol=1e-10",
+                   "lattice": list(DIMS), "poles": n, "mass": MASS, "tol": TOL, "links": "exp(i 0.2 H) in SU(3)"},
+        "roofline": {"bound": "hbm", "kernel": "D_oe Dslash (in the multi-shift CG)",
+                     "achieved": round(doe_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(doe_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(avg_us[0], 3), "algorithmic_bytes_per_launch": B_DOE * vh},
+        "kernels": {"dslash_oe": {"avg_us": round(avg_us[0], 3), "GB/s": round(doe_gbs, 1), "launches": cnt[0]},
+                    "dslash_eo_cg": {"avg_us": round(avg_us[1], 3), "GB/s": round(deo_gbs, 1), "launches": cnt[1]},
+                    "shift_update": {"avg_us": round(avg_us[2], 3), "GB/s": round(upd_gbs, 1), "launches": cnt[2]}},
+        "iterations": infos[0]["iters"],
+        "true_resid_max": max(chk["true_resid"]),
+        "dslash_gflops": round(570 * vh * 1e-9 / (avg_us[0] * 1e-6), 1),
+    }
+    if traj:
+        out["sec_per_trajectory"] = traj
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(U, b, rat, vh, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def trajectory_timing():
+    """Seconds per exact-force RHMC trajectory: 16^3x8, beta 5.4, m 0.02, 12-pole
+    x^(-1/2) / x^(1/4) tables, tau 1, 20 leapfrog steps, tol 1e-10 (MD 1e-8)."""
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice
+    dims = (16, 16, 16, 8)
+    U = synth.random_su3_near_identity(dims, 0.2, synth.make_rng(4, 0))
+    lat = Lattice(dims)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    r_f = synth.load_rational("xm050_n12_m0.02")
+    r_h = synth.load_rational("xp025_n12_m0.02")
+    kw = dict(tol_md=1e-8, tol_action=1e-10, seed=7)
+    lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, traj_index=0, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, traj_index=i + 1, **kw) for i in range(2)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 2
+    return {"seconds": round(dt, 4), "lattice": list(dims), "beta": 5.4, "mass": 0.02, "n_steps": 20, "tau": 1.0,
+            "cg_iters_per_traj": res[-1]["cg_iters_total"], "dH": [r["dH"] for r in res],
+            "accepted": [r["accepted"] for r in res]}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,843 @@
+// extern "C" entry points of libstag: handle management, argument checks,
+// field conversions, the multi-shift CG driver (Sec. 4), forces and the RHMC
+// trajectory (Sec. 3.1).  All device work goes to one internal stream that is
+// ordered after / before the caller's stream with events.
+#include <chrono>
+#include <cstddef>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace stag;
+
+struct stag_ctx {
+    Geom g{};
+    int dims[4]{};
+    int device = 0;
+    hipStream_t user = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t chunk_ev[2]{};
+    double2* links = nullptr;
+    double2* links_backup = nullptr;
+    double* mom = nullptr;
+    double2 *r = nullptr, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
+    double2 *xi = nullptr, *phi = nullptr;
+    double2* pool_x = nullptr;   // n_cap even vectors: solutions
+    double2* pool_p = nullptr;   // n_cap even vectors: shifted search directions
+    double2* pool_y = nullptr;   // n_cap odd vectors: D_oe x_k for the force
+    int n_cap = 0;
+    MsState* st = nullptr;
+    MsState* st_host = nullptr;  // pinned
+    double* dpart = nullptr;      // CG dot partials of the D_eo kernel (3 x blocks)
+    double* qpart[2] = {nullptr, nullptr};  // <r,r> partials, alternating by iteration parity
+    double* gpart = nullptr;      // partials of the other reductions
+    double* scal = nullptr;       // device scalars for reductions
+    double* scal_host = nullptr;  // pinned
+    int* done_host = nullptr;     // pinned [2]
+    bool has_gauge = false;
+    int tps = 2;                  // threads per site in the Dslash
+    int chunk = 16;               // iterations enqueued between convergence polls
+    // profiling of the Dslash launches inside the solver (hipEvent pairs)
+    int prof_on = 0;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+    double prof_ms[3] = {0, 0, 0};   // D_oe, D_eo+CG epilogue, shift update
+    long prof_cnt[3] = {0, 0, 0};
+    std::string err;
+    int last_iters = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+size_t half_bytes(const Geom& g) { return (size_t)3 * g.vh * sizeof(double2); }
+
+stag_status fail(stag_ctx* c, stag_status code, const std::string& msg) {
+    if (c)
+        c->err = msg;
+    else
+        g_create_err = msg;
+    return code;
+}
+
+#define HIP_OR_FAIL(c, expr)                                                                   \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail((c), STAG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool aligned16(const void* p) { return p && ((uintptr_t)p % 16 == 0); }
+
+stag_status check_rational(stag_ctx* c, const stag_rational* r, double mass) {
+    if (!r) return fail(c, STAG_ERR_INVALID_ARG, "rational function is NULL");
+    if (r->n < 1 || r->n > STAG_MAX_POLES)
+        return fail(c, STAG_ERR_INVALID_ARG, "number of poles must be in [1, " + std::to_string(STAG_MAX_POLES) + "]");
+    if (!r->pole || !r->residue) return fail(c, STAG_ERR_INVALID_ARG, "pole/residue arrays are NULL");
+    double mn = 1e300;
+    for (int k = 0; k < r->n; ++k) {
+        if (!std::isfinite(r->pole[k]) || r->pole[k] < 0.0)
+            return fail(c, STAG_ERR_INVALID_ARG, "poles must be finite and >= 0");
+        if (!std::isfinite(r->residue[k])) return fail(c, STAG_ERR_INVALID_ARG, "residues must be finite");
+        mn = std::min(mn, r->pole[k]);
+    }
+    if (!std::isfinite(r->c0)) return fail(c, STAG_ERR_INVALID_ARG, "c0 must be finite");
+    if (!(4.0 * mass * mass + mn > 0.0))
+        return fail(c, STAG_ERR_INVALID_ARG, "4 m^2 + smallest pole must be > 0 (operator would be singular)");
+    return STAG_OK;
+}
+
+stag_status check_common(stag_ctx* c, bool need_gauge) {
+    if (!c) return fail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
+    if (need_gauge && !c->has_gauge) return fail(c, STAG_ERR_NO_GAUGE, "no gauge field set (call stag_set_gauge)");
+    return STAG_OK;
+}
+
+// order the internal stream after the caller's stream
+stag_status enter(stag_ctx* c) {
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    HIP_OR_FAIL(c, hipEventRecord(c->ev_in, c->user));
+    HIP_OR_FAIL(c, hipStreamWaitEvent(c->s, c->ev_in, 0));
+    return STAG_OK;
+}
+
+// order the caller's stream after the internal stream
+stag_status leave(stag_ctx* c) {
+    HIP_OR_FAIL(c, hipGetLastError());
+    HIP_OR_FAIL(c, hipEventRecord(c->ev_out, c->s));
+    HIP_OR_FAIL(c, hipStreamWaitEvent(c->user, c->ev_out, 0));
+    return STAG_OK;
+}
+
+template <class T>
+stag_status dmalloc(stag_ctx* c, T** p, size_t bytes) {
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, STAG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return STAG_OK;
+}
+
+stag_status ensure_pool(stag_ctx* c, int n) {
+    if (n <= c->n_cap) return STAG_OK;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    hipFree(c->pool_x);
+    hipFree(c->pool_p);
+    hipFree(c->pool_y);
+    c->pool_x = c->pool_p = c->pool_y = nullptr;
+    c->n_cap = 0;
+    const size_t hb = half_bytes(c->g);
+    stag_status st;
+    if ((st = dmalloc(c, &c->pool_x, hb * n)) != STAG_OK) return st;
+    if ((st = dmalloc(c, &c->pool_p, hb * n)) != STAG_OK) return st;
+    if ((st = dmalloc(c, &c->pool_y, hb * n)) != STAG_OK) return st;
+    c->n_cap = n;
+    return STAG_OK;
+}
+
+double2* pool_vec(double2* pool, const Geom& g, int k) { return pool + (size_t)k * 3 * g.vh; }
+
+// ---- profiling helpers: events around kernels inside the solver loop
+void prof_begin(stag_ctx* c, hipEvent_t* a) {
+    if (!c->prof_on) return;
+    if (c->prof_used + 2 > c->prof_ev.size()) {
+        *a = nullptr;
+        return;
+    }
+    *a = c->prof_ev[c->prof_used];
+    hipEventRecord(*a, c->s);
+}
+void prof_end(stag_ctx* c, hipEvent_t a, int kind, std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>& rec) {
+    if (!c->prof_on || !a) return;
+    hipEvent_t b = c->prof_ev[c->prof_used + 1];
+    hipEventRecord(b, c->s);
+    c->prof_used += 2;
+    rec.push_back({{a, b}, kind});
+}
+
+struct SolveResult {
+    int iters = 0;
+    int nonfinite = 0;
+    int converged = 1;
+};
+
+// Multi-shift CG on A + pole_k.  x[k] receive the solutions.  The host only
+// enqueues kernels and polls the device "done" flag once per chunk of
+// iterations; two chunks are kept in flight so the GPU never waits.
+stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter, const double2* b,
+                     double2* const* x, bool want_resid, double* resid_out, int* ipp_out, SolveResult& res) {
+    const Geom& g = c->g;
+    const int n = r->n;
+    stag_status e = ensure_pool(c, n);
+    if (e != STAG_OK) return e;
+    int base = 0;
+    for (int k = 1; k < n; ++k)
+        if (r->pole[k] < r->pole[base]) base = k;
+    const double s0 = r->pole[base];
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));  // st_host is reused
+    MsState* h = c->st_host;
+    std::memset(h, 0, sizeof(MsState));
+    h->n = n;
+    h->base = base;
+    h->maxiter = maxiter;
+    h->tol2 = tol * tol;
+    h->mass_term = 4.0 * mass * mass + s0;
+    h->c0 = r->c0;
+    for (int k = 0; k < n; ++k) {
+        h->shift[k] = r->pole[k] - s0;
+        h->coef[k] = r->residue[k];
+        h->it[0].zeta[k] = h->it[0].zeta_old[k] = 1.0;
+        h->it[0].active[k] = 1;
+    }
+    h->it[0].alpha_old = 1.0;
+    h->it[0].beta_old = 0.0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
+    VecPtrs X{}, P{};
+    for (int k = 0; k < n; ++k) {
+        X.p[k] = x[k];
+        P.p[k] = pool_vec(c->pool_p, g, k);
+    }
+    launch_ms_init(g, b, c->r, c->p, X, P, c->st, c->qpart[0], c->s);
+
+    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> rec;
+    c->prof_used = 0;
+    const double mt = h->mass_term;
+    const int nb2 = dslash_grid(g, c->tps);
+    int it_issued = 0;
+    auto issue_chunk = [&](int slot) {
+        for (int it = 0; it < c->chunk; ++it, ++it_issued) {
+            const int par = it_issued & 1;
+            hipEvent_t a;
+            prof_begin(c, &a);
+            launch_dslash_gated(g, c->links, c->p, c->w_o, 1, c->tps, c->st, c->s);
+            prof_end(c, a, 0, rec);
+            prof_begin(c, &a);
+            launch_dslash_cg(g, c->links, c->w_o, c->p, c->r, c->Ap, c->st, c->dpart, c->tps, c->s, mt);
+            prof_end(c, a, 1, rec);
+            prof_begin(c, &a);
+            launch_ms_step(g, c->r, c->Ap, c->p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
+                           c->s);
+            prof_end(c, a, 2, rec);
+        }
+        hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->s);
+        hipEventRecord(c->chunk_ev[slot], c->s);
+    };
+    issue_chunk(0);
+    issue_chunk(1);
+    int cur = 0;
+    for (;;) {
+        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
+        if (c->done_host[cur]) break;
+        issue_chunk(cur);
+        cur ^= 1;
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    if (want_resid) {
+        const int nbr = dslash_grid(g, c->tps);
+        for (int k = 0; k < n; ++k) {
+            launch_dslash(g, c->links, x[k], c->tmp_o, 1, c->tps, c->s);
+            launch_dslash_resid(g, c->links, c->tmp_o, x[k], b, 4.0 * mass * mass + r->pole[k], c->gpart, c->tps,
+                                c->s);
+            double* slot = (double*)((char*)c->st + offsetof(MsState, true_res2)) + k;
+            launch_finalize(c->gpart, nbr, 1, slot, c->s);
+        }
+    }
+    HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    const MsIter& f = h->fin;
+    // kernel times: iterations 0..iter (the last one only detects convergence
+    // in its step kernel, after full Dslash launches)
+    {
+        long seen[3] = {0, 0, 0};
+        const long lim[3] = {f.iter + 1, f.iter + 1, f.iter};
+        for (auto& q : rec) {
+            const int kind = q.second;
+            if (seen[kind]++ >= lim[kind]) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, q.first.first, q.first.second) == hipSuccess) {
+                c->prof_ms[kind] += ms;
+                c->prof_cnt[kind] += 1;
+            }
+        }
+    }
+    res.iters = f.iter;
+    res.nonfinite = f.nonfinite;
+    res.converged = 1;
+    for (int k = 0; k < n; ++k)
+        if (f.active[k]) res.converged = 0;
+    const double bb = f.bb;
+    for (int k = 0; k < n; ++k) {
+        if (resid_out) resid_out[k] = (want_resid && bb > 0) ? std::sqrt(h->true_res2[k] / bb) : -1.0;
+        if (ipp_out) ipp_out[k] = f.iters_per_pole[k];
+    }
+    c->last_iters = f.iter;
+    return STAG_OK;
+}
+
+stag_status finish_solve_status(stag_ctx* c, const SolveResult& res) {
+    if (res.nonfinite) return fail(c, STAG_ERR_NONFINITE, "non-finite value in the solver (NaN/Inf in the input?)");
+    if (!res.converged) return fail(c, STAG_ERR_NOT_CONVERGED, "multi-shift CG reached maxiter before convergence");
+    return STAG_OK;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+stag_status reduce_to_host(stag_ctx* c, double* out) {
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    *out = c->scal_host[0];
+    return STAG_OK;
+}
+
+// S_f = Re <phi, r(A) phi>; uses tmp_e
+stag_status fermion_action_impl(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
+                                const double2* phi, double* S, SolveResult& res) {
+    stag_status e = ensure_pool(c, r->n);
+    if (e != STAG_OK) return e;
+    std::vector<double2*> xs(r->n);
+    for (int k = 0; k < r->n; ++k) xs[k] = pool_vec(c->pool_x, c->g, k);
+    if ((e = ms_solve(c, mass, r, tol, maxiter, phi, xs.data(), false, nullptr, nullptr, res)) != STAG_OK) return e;
+    VecPtrs X{};
+    for (int k = 0; k < r->n; ++k) X.p[k] = xs[k];
+    launch_rational_sum(c->g, phi, X, c->st, c->tmp_e, c->s);
+    launch_dot_re(c->g, phi, c->tmp_e, c->gpart, c->s);
+    launch_finalize(c->gpart, dot_grid(c->g), 1, c->scal, c->s);
+    return reduce_to_host(c, S);
+}
+
+// mom = F (dt == 0) or mom += dt F
+stag_status fermion_force_impl(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
+                               const double2* phi, double* mom, double dt, SolveResult& res) {
+    stag_status e = ensure_pool(c, r->n);
+    if (e != STAG_OK) return e;
+    const Geom& g = c->g;
+    std::vector<double2*> xs(r->n);
+    for (int k = 0; k < r->n; ++k) xs[k] = pool_vec(c->pool_x, g, k);
+    if ((e = ms_solve(c, mass, r, tol, maxiter, phi, xs.data(), false, nullptr, nullptr, res)) != STAG_OK) return e;
+    VecPtrs X{}, Y{};
+    for (int k = 0; k < r->n; ++k) {
+        X.p[k] = xs[k];
+        Y.p[k] = pool_vec(c->pool_y, g, k);
+        launch_dslash(g, c->links, X.p[k], Y.p[k], 1, c->tps, c->s);
+    }
+    const double* coef = (const double*)((const char*)c->st + offsetof(MsState, coef));
+    launch_fermion_force(g, c->links, X, Y, coef, r->n, mom, dt, c->s);
+    return STAG_OK;
+}
+
+stag_status gauge_action_impl(stag_ctx* c, double beta, double* S, double* plaq) {
+    const int nb = launch_plaquette(c->g, c->links, c->gpart, c->s);
+    launch_finalize(c->gpart, nb, 1, c->scal, c->s);
+    double sum = 0.0;
+    stag_status e = reduce_to_host(c, &sum);
+    if (e != STAG_OK) return e;
+    const double V = 2.0 * c->g.vh;
+    if (S) *S = beta * (6.0 * V - sum / 3.0);
+    if (plaq) *plaq = sum / (3.0 * 6.0 * V);
+    return STAG_OK;
+}
+
+stag_status kinetic_impl(stag_ctx* c, const double* mom, double* K) {
+    const int nb = launch_kinetic(c->g, mom, c->gpart, c->s);
+    launch_finalize(c->gpart, nb, 1, c->scal, c->s);
+    double sum = 0.0;
+    stag_status e = reduce_to_host(c, &sum);
+    if (e != STAG_OK) return e;
+    *K = 0.5 * sum;
+    return STAG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
+    if (!out || !dims) return fail(nullptr, STAG_ERR_INVALID_ARG, "out/dims is NULL");
+    *out = nullptr;
+    long long V = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (dims[i] < 2 || dims[i] % 2)
+            return fail(nullptr, STAG_ERR_INVALID_ARG, "every lattice extent must be even and >= 2");
+        V *= dims[i];
+    }
+    if (V >= (1LL << 31) / 8) return fail(nullptr, STAG_ERR_INVALID_ARG, "lattice too large for 32-bit indexing");
+    stag_ctx* c = new stag_ctx();
+    for (int i = 0; i < 4; ++i) c->dims[i] = dims[i];
+    c->g = Geom{dims[0], dims[1], dims[2], dims[3], dims[0] / 2, (int)(V / 2)};
+    if (const char* e = std::getenv("STAG_TPS")) c->tps = std::atoi(e);
+    if (c->tps != 1 && c->tps != 2 && c->tps != 4) c->tps = 2;
+    if (const char* e = std::getenv("STAG_CHUNK")) c->chunk = std::max(1, std::atoi(e));
+    c->user = (hipStream_t)hip_stream;
+    auto bail = [&](stag_status s) {
+        g_create_err = c->err;
+        stag_destroy(c);
+        return s;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(nullptr, STAG_ERR_HIP, "no HIP device available");
+    }
+    if (hipStreamCreateWithFlags(&c->s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->chunk_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->chunk_ev[1], hipEventDisableTiming) != hipSuccess) {
+        c->err = "stream/event creation failed";
+        return bail(STAG_ERR_HIP);
+    }
+    const Geom& g = c->g;
+    const size_t hb = half_bytes(g);
+    const size_t lb = (size_t)2 * 4 * 9 * g.vh * sizeof(double2);
+    const size_t mb = (size_t)2 * 4 * 8 * g.vh * sizeof(double);
+    stag_status s;
+    if ((s = dmalloc(c, &c->links, lb)) || (s = dmalloc(c, &c->links_backup, lb)) || (s = dmalloc(c, &c->mom, mb)) ||
+        (s = dmalloc(c, &c->r, hb)) || (s = dmalloc(c, &c->p, hb)) || (s = dmalloc(c, &c->Ap, hb)) ||
+        (s = dmalloc(c, &c->w_o, hb)) || (s = dmalloc(c, &c->tmp_e, hb)) || (s = dmalloc(c, &c->tmp_o, hb)) ||
+        (s = dmalloc(c, &c->xi, hb)) || (s = dmalloc(c, &c->phi, hb)) || (s = dmalloc(c, &c->st, sizeof(MsState))) ||
+        (s = dmalloc(c, &c->scal, 64)))
+        return bail(s);
+    // one partial per block of the largest reduction grid (Dslash with 64 sites
+    // per block, or the element-wise kernels with 256 elements per block)
+    const size_t nparts = std::max<size_t>(4096, (size_t)g.vh / 32 + 16);
+    if ((s = dmalloc(c, &c->dpart, nparts * 3 * sizeof(double))) ||
+        (s = dmalloc(c, &c->qpart[0], nparts * sizeof(double))) ||
+        (s = dmalloc(c, &c->qpart[1], nparts * sizeof(double))) ||
+        (s = dmalloc(c, &c->gpart, nparts * 3 * sizeof(double))))
+        return bail(s);
+    if (hipHostMalloc((void**)&c->st_host, sizeof(MsState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->scal_host, 64, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->done_host, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        c->err = "pinned host allocation failed";
+        return bail(STAG_ERR_OOM);
+    }
+    launch_fill_zero(c->mom, mb, c->s);
+    if (hipStreamSynchronize(c->s) != hipSuccess) {
+        c->err = "initialisation kernels failed";
+        return bail(STAG_ERR_HIP);
+    }
+    *out = c;
+    return STAG_OK;
+}
+
+stag_status stag_destroy(stag_handle c) {
+    if (!c) return STAG_OK;
+    if (c->s) hipStreamSynchronize(c->s);
+    void* bufs[] = {c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
+                    c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
+                    c->gpart, c->scal};
+    for (void* b : bufs)
+        if (b) hipFree(b);
+    if (c->st_host) hipHostFree(c->st_host);
+    if (c->scal_host) hipHostFree(c->scal_host);
+    if (c->done_host) hipHostFree(c->done_host);
+    for (auto ev : c->prof_ev) hipEventDestroy(ev);
+    hipEvent_t evs[] = {c->ev_in, c->ev_out, c->chunk_ev[0], c->chunk_ev[1]};
+    for (auto ev : evs)
+        if (ev) hipEventDestroy(ev);
+    if (c->s) hipStreamDestroy(c->s);
+    delete c;
+    return STAG_OK;
+}
+
+const char* stag_last_error(stag_handle c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+size_t stag_field_bytes(stag_handle c, int kind) {
+    if (!c) return 0;
+    const size_t vh = c->g.vh, V = 2 * vh;
+    switch (kind) {
+        case STAG_FIELD_HALF_VEC: return 3 * vh * 16;
+        case STAG_FIELD_MOM: return 64 * vh * 8;
+        case STAG_FIELD_CANON_HALF_VEC: return 3 * vh * 16;
+        case STAG_FIELD_CANON_GAUGE: return V * 4 * 9 * 16;
+        case STAG_FIELD_CANON_MOM: return V * 4 * 8 * 8;
+        default: return 0;
+    }
+}
+
+stag_status stag_set_gauge(stag_handle c, const double* U) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(U)) return fail(c, STAG_ERR_INVALID_ARG, "gauge pointer is NULL or not 16-byte aligned");
+    if ((e = enter(c))) return e;
+    launch_gauge_to_internal(c->g, (const double2*)U, c->links, c->s);
+    c->has_gauge = true;
+    return leave(c);
+}
+
+stag_status stag_get_gauge(stag_handle c, double* U) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(U)) return fail(c, STAG_ERR_INVALID_ARG, "gauge pointer is NULL or not 16-byte aligned");
+    if ((e = enter(c))) return e;
+    launch_gauge_to_canon(c->g, c->links, (double2*)U, c->s);
+    return leave(c);
+}
+
+stag_status stag_vec_import(stag_handle c, void* out, const double* in, int parity) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in)) return fail(c, STAG_ERR_INVALID_ARG, "vector pointer NULL or misaligned");
+    if (parity != 0 && parity != 1) return fail(c, STAG_ERR_INVALID_ARG, "parity must be 0 or 1");
+    if (out == (const void*)in) return fail(c, STAG_ERR_INVALID_ARG, "in and out must differ");
+    if ((e = enter(c))) return e;
+    launch_vec_to_internal(c->g, (const double2*)in, (double2*)out, c->s);
+    return leave(c);
+}
+
+stag_status stag_vec_export(stag_handle c, double* out, const void* in, int parity) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in)) return fail(c, STAG_ERR_INVALID_ARG, "vector pointer NULL or misaligned");
+    if (parity != 0 && parity != 1) return fail(c, STAG_ERR_INVALID_ARG, "parity must be 0 or 1");
+    if ((const void*)out == in) return fail(c, STAG_ERR_INVALID_ARG, "in and out must differ");
+    if ((e = enter(c))) return e;
+    launch_vec_to_canon(c->g, (const double2*)in, (double2*)out, c->s);
+    return leave(c);
+}
+
+stag_status stag_mom_import(stag_handle c, void* out, const double* in) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in) || out == (const void*)in)
+        return fail(c, STAG_ERR_INVALID_ARG, "momentum pointers NULL, misaligned or equal");
+    if ((e = enter(c))) return e;
+    launch_mom_to_internal(c->g, in, (double*)out, 0, c->s);
+    return leave(c);
+}
+
+stag_status stag_mom_export(stag_handle c, double* out, const void* in) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in) || (const void*)out == in)
+        return fail(c, STAG_ERR_INVALID_ARG, "momentum pointers NULL, misaligned or equal");
+    if ((e = enter(c))) return e;
+    launch_mom_to_canon(c->g, (const double*)in, out, c->s);
+    return leave(c);
+}
+
+stag_status stag_dslash(stag_handle c, void* out, const void* in, int out_parity) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in) || out == in)
+        return fail(c, STAG_ERR_INVALID_ARG, "vector pointers NULL, misaligned or equal");
+    if (out_parity != 0 && out_parity != 1) return fail(c, STAG_ERR_INVALID_ARG, "parity must be 0 or 1");
+    if ((e = enter(c))) return e;
+    launch_dslash(c->g, c->links, (const double2*)in, (double2*)out, out_parity, c->tps, c->s);
+    return leave(c);
+}
+
+stag_status stag_mdagm(stag_handle c, void* out, const void* in, double mass) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in) || out == in)
+        return fail(c, STAG_ERR_INVALID_ARG, "vector pointers NULL, misaligned or equal");
+    if (!std::isfinite(mass)) return fail(c, STAG_ERR_INVALID_ARG, "mass must be finite");
+    if ((e = enter(c))) return e;
+    launch_dslash(c->g, c->links, (const double2*)in, c->tmp_o, 1, c->tps, c->s);
+    launch_dslash_axpy(c->g, c->links, c->tmp_o, (const double2*)in, 4.0 * mass * mass, (double2*)out, c->tps, c->s);
+    return leave(c);
+}
+
+stag_status stag_multishift_solve(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
+                                  const void* b, void* const* x, void* sum, stag_solve_info* info) {
+    const double t0 = now_s();
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if ((e = check_rational(c, r, mass))) return e;
+    if (!(tol > 0.0) || maxiter < 1) return fail(c, STAG_ERR_INVALID_ARG, "need tol > 0 and maxiter >= 1");
+    if (!aligned16(b)) return fail(c, STAG_ERR_INVALID_ARG, "source pointer NULL or misaligned");
+    if (x)
+        for (int k = 0; k < r->n; ++k) {
+            if (!aligned16(x[k])) return fail(c, STAG_ERR_INVALID_ARG, "solution pointer NULL or misaligned");
+            if (x[k] == b || x[k] == sum) return fail(c, STAG_ERR_INVALID_ARG, "outputs must not alias the source");
+            for (int j = 0; j < k; ++j)
+                if (x[j] == x[k]) return fail(c, STAG_ERR_INVALID_ARG, "solution pointers must be distinct");
+        }
+    if (sum && (!aligned16(sum) || sum == b)) return fail(c, STAG_ERR_INVALID_ARG, "sum pointer misaligned or aliases b");
+    if ((e = enter(c))) return e;
+    if ((e = ensure_pool(c, r->n))) return e;
+    std::vector<double2*> xs(r->n);
+    for (int k = 0; k < r->n; ++k) xs[k] = x ? (double2*)x[k] : pool_vec(c->pool_x, c->g, k);
+    SolveResult res;
+    const bool want_resid = info && info->true_resid;
+    e = ms_solve(c, mass, r, tol, maxiter, (const double2*)b, xs.data(), want_resid, info ? info->true_resid : nullptr,
+                 info ? info->iters_per_pole : nullptr, res);
+    if (e) return e;
+    if (sum) {
+        VecPtrs X{};
+        for (int k = 0; k < r->n; ++k) X.p[k] = xs[k];
+        launch_rational_sum(c->g, (const double2*)b, X, c->st, (double2*)sum, c->s);
+    }
+    if ((e = leave(c))) return e;
+    if (sum) HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    if (info) {
+        info->iters = res.iters;
+        info->n = r->n;
+        info->seconds = now_s() - t0;
+    }
+    return finish_solve_status(c, res);
+}
+
+stag_status stag_fermion_action(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
+                                const void* phi, double* S, stag_solve_info* info) {
+    const double t0 = now_s();
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if ((e = check_rational(c, r, mass))) return e;
+    if (!(tol > 0.0) || maxiter < 1) return fail(c, STAG_ERR_INVALID_ARG, "need tol > 0 and maxiter >= 1");
+    if (!aligned16(phi) || !S) return fail(c, STAG_ERR_INVALID_ARG, "phi NULL/misaligned or S_out NULL");
+    if ((e = enter(c))) return e;
+    SolveResult res;
+    if ((e = fermion_action_impl(c, mass, r, tol, maxiter, (const double2*)phi, S, res))) return e;
+    if ((e = leave(c))) return e;
+    if (info) {
+        info->iters = res.iters;
+        info->n = r->n;
+        info->seconds = now_s() - t0;
+    }
+    return finish_solve_status(c, res);
+}
+
+stag_status stag_fermion_force(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
+                               const void* phi, void* mom, double dt, stag_solve_info* info) {
+    const double t0 = now_s();
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if ((e = check_rational(c, r, mass))) return e;
+    if (!(tol > 0.0) || maxiter < 1) return fail(c, STAG_ERR_INVALID_ARG, "need tol > 0 and maxiter >= 1");
+    if (!aligned16(phi) || !aligned16(mom)) return fail(c, STAG_ERR_INVALID_ARG, "phi/mom NULL or misaligned");
+    if (!std::isfinite(dt)) return fail(c, STAG_ERR_INVALID_ARG, "dt must be finite");
+    if ((e = enter(c))) return e;
+    SolveResult res;
+    if ((e = fermion_force_impl(c, mass, r, tol, maxiter, (const double2*)phi, (double*)mom, dt, res))) return e;
+    if ((e = leave(c))) return e;
+    if (info) {
+        info->iters = res.iters;
+        info->n = r->n;
+        info->seconds = now_s() - t0;
+    }
+    return finish_solve_status(c, res);
+}
+
+stag_status stag_gauge_force(stag_handle c, double beta, void* mom, double dt) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(mom) || !std::isfinite(beta) || !std::isfinite(dt))
+        return fail(c, STAG_ERR_INVALID_ARG, "mom NULL/misaligned or beta/dt not finite");
+    if ((e = enter(c))) return e;
+    launch_gauge_force(c->g, c->links, beta, (double*)mom, dt, c->s);
+    return leave(c);
+}
+
+stag_status stag_gauge_action(stag_handle c, double beta, double* S, double* plaq) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if ((e = enter(c))) return e;
+    if ((e = gauge_action_impl(c, beta, S, plaq))) return e;
+    return leave(c);
+}
+
+stag_status stag_kinetic_energy(stag_handle c, const void* mom, double* K) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(mom) || !K) return fail(c, STAG_ERR_INVALID_ARG, "mom NULL/misaligned or K_out NULL");
+    if ((e = enter(c))) return e;
+    if ((e = kinetic_impl(c, (const double*)mom, K))) return e;
+    return leave(c);
+}
+
+stag_status stag_link_update(stag_handle c, const void* mom, double dt) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(mom) || !std::isfinite(dt)) return fail(c, STAG_ERR_INVALID_ARG, "mom NULL/misaligned or dt not finite");
+    if ((e = enter(c))) return e;
+    launch_link_update(c->g, c->links, (const double*)mom, dt, c->s);
+    return leave(c);
+}
+
+stag_status stag_random_momentum(stag_handle c, uint64_t seed, uint64_t traj, void* mom) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(mom)) return fail(c, STAG_ERR_INVALID_ARG, "mom NULL or misaligned");
+    if ((e = enter(c))) return e;
+    launch_random_momentum(c->g, seed, traj, (double*)mom, c->s);
+    return leave(c);
+}
+
+stag_status stag_random_source(stag_handle c, uint64_t seed, uint64_t traj, void* xi) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!aligned16(xi)) return fail(c, STAG_ERR_INVALID_ARG, "xi NULL or misaligned");
+    if ((e = enter(c))) return e;
+    launch_random_source(c->g, seed, traj, (double2*)xi, c->s);
+    return leave(c);
+}
+
+stag_status stag_philox(const uint32_t ctr[4], const uint32_t key[2], size_t n, uint32_t* out, void* stream) {
+    if (!ctr || !key || !out || ((uintptr_t)out % 4)) return fail(nullptr, STAG_ERR_INVALID_ARG, "bad philox arguments");
+    if (n == 0) return STAG_OK;
+    if (n > ((size_t)1 << 31)) return fail(nullptr, STAG_ERR_INVALID_ARG, "n too large");
+    launch_philox(ctr, key, n, out, (hipStream_t)stream);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(nullptr, STAG_ERR_HIP, hipGetErrorString(err));
+    return STAG_OK;
+}
+
+stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_traj_info* info) {
+    const double t0 = now_s();
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!p) return fail(c, STAG_ERR_INVALID_ARG, "params NULL");
+    if (p->n_steps < 1 || !(p->tau > 0) || !std::isfinite(p->beta) || !(p->tol_md > 0) || !(p->tol_action > 0) ||
+        p->maxiter < 1)
+        return fail(c, STAG_ERR_INVALID_ARG, "need n_steps >= 1, tau > 0, tolerances > 0, maxiter >= 1");
+    const bool ferm = !p->no_fermions;
+    if (ferm) {
+        if ((e = check_rational(c, &p->r_md, p->mass)) || (e = check_rational(c, &p->r_action, p->mass)) ||
+            (e = check_rational(c, &p->r_heatbath, p->mass)))
+            return e;
+    }
+    if ((p->inject_mom && !aligned16(p->inject_mom)) || (p->inject_xi && !aligned16(p->inject_xi)))
+        return fail(c, STAG_ERR_INVALID_ARG, "injected fields misaligned");
+    if (!(p->inject_u < 1.0)) return fail(c, STAG_ERR_INVALID_ARG, "inject_u must be < 1 (negative = draw)");
+    if ((e = enter(c))) return e;
+    const Geom& g = c->g;
+    const size_t mb = (size_t)64 * g.vh * sizeof(double);
+    const size_t lb = (size_t)72 * g.vh * sizeof(double2);
+    stag_traj_info I{};
+    SolveResult res;
+    int iters = 0, nsolve = 0;
+    auto acc = [&](const SolveResult& r) {
+        iters += r.iters;
+        nsolve += 1;
+    };
+    // step 1: momenta and pseudofermion heat bath
+    if (p->inject_mom)
+        launch_copy(c->mom, p->inject_mom, mb, c->s);
+    else
+        launch_random_momentum(g, p->seed, p->traj_index, c->mom, c->s);
+    if (ferm) {
+        if (p->inject_xi)
+            launch_copy(c->xi, p->inject_xi, half_bytes(g), c->s);
+        else
+            launch_random_source(g, p->seed, p->traj_index, c->xi, c->s);
+        if ((e = ensure_pool(c, std::max(p->r_heatbath.n, std::max(p->r_md.n, p->r_action.n))))) return e;
+        std::vector<double2*> xs(p->r_heatbath.n);
+        for (int k = 0; k < p->r_heatbath.n; ++k) xs[k] = pool_vec(c->pool_x, g, k);
+        if ((e = ms_solve(c, p->mass, &p->r_heatbath, p->tol_action, p->maxiter, c->xi, xs.data(), false, nullptr,
+                          nullptr, res)))
+            return e;
+        if ((e = finish_solve_status(c, res))) return e;
+        acc(res);
+        VecPtrs X{};
+        for (int k = 0; k < p->r_heatbath.n; ++k) X.p[k] = xs[k];
+        launch_rational_sum(g, c->xi, X, c->st, c->phi, c->s);
+    }
+    launch_copy(c->links_backup, c->links, lb, c->s);
+    // H at the start
+    if ((e = kinetic_impl(c, c->mom, &I.K_old))) return e;
+    if ((e = gauge_action_impl(c, p->beta, &I.Sg_old, nullptr))) return e;
+    if (ferm) {
+        if ((e = fermion_action_impl(c, p->mass, &p->r_action, p->tol_action, p->maxiter, c->phi, &I.Sf_old, res)))
+            return e;
+        if ((e = finish_solve_status(c, res))) return e;
+        acc(res);
+    }
+    // step 2: leapfrog
+    const double dt = p->tau / p->n_steps;
+    auto kick = [&](double h) -> stag_status {
+        launch_gauge_force(g, c->links, p->beta, c->mom, h, c->s);
+        if (ferm) {
+            stag_status e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, h, res);
+            if (e2) return e2;
+            if ((e2 = finish_solve_status(c, res))) return e2;
+            acc(res);
+        }
+        return STAG_OK;
+    };
+    if ((e = kick(0.5 * dt))) return e;
+    for (int step = 0; step < p->n_steps; ++step) {
+        launch_link_update(g, c->links, c->mom, dt, c->s);
+        if ((e = kick(step < p->n_steps - 1 ? dt : 0.5 * dt))) return e;
+    }
+    // step 3: Metropolis on the rational action
+    if ((e = kinetic_impl(c, c->mom, &I.K_new))) return e;
+    if ((e = gauge_action_impl(c, p->beta, &I.Sg_new, nullptr))) return e;
+    if (ferm) {
+        if ((e = fermion_action_impl(c, p->mass, &p->r_action, p->tol_action, p->maxiter, c->phi, &I.Sf_new, res)))
+            return e;
+        if ((e = finish_solve_status(c, res))) return e;
+        acc(res);
+    }
+    I.dH = (I.K_new + I.Sg_new + I.Sf_new) - (I.K_old + I.Sg_old + I.Sf_old);
+    double u = p->inject_u;
+    if (u < 0.0) {
+        launch_uniform(p->seed, p->traj_index, c->scal, c->s);
+        if ((e = reduce_to_host(c, &u))) return e;
+    }
+    I.accepted = (u < std::exp(-I.dH)) ? 1 : 0;
+    if (!I.accepted) launch_copy(c->links, c->links_backup, lb, c->s);
+    if ((e = gauge_action_impl(c, p->beta, nullptr, &I.plaquette))) return e;
+    if ((e = leave(c))) return e;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    I.cg_iters_total = iters;
+    I.n_solves = nsolve;
+    I.seconds = now_s() - t0;
+    if (info) *info = I;
+    return STAG_OK;
+}
+
+// ---- measurement support (not part of the method) --------------------------
+
+// Record hipEvents around every Dslash and shift-update launch of subsequent
+// solves (capacity: max_launches launches); 0 switches it off and clears.
+stag_status stag_profile_enable(stag_handle c, int max_launches) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    for (auto ev : c->prof_ev) hipEventDestroy(ev);
+    c->prof_ev.clear();
+    c->prof_on = max_launches > 0;
+    for (int i = 0; i < 3; ++i) c->prof_ms[i] = 0, c->prof_cnt[i] = 0;
+    if (!c->prof_on) return STAG_OK;
+    c->prof_ev.resize((size_t)2 * max_launches);
+    for (auto& ev : c->prof_ev)
+        if (hipEventCreate(&ev) != hipSuccess) return fail(c, STAG_ERR_HIP, "event creation failed");
+    return STAG_OK;
+}
+
+// Accumulated milliseconds and launch counts: [0] D_oe, [1] D_eo with the CG
+// epilogue, [2] the fused shift update.
+stag_status stag_profile_read(stag_handle c, double ms[3], long counts[3]) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    for (int i = 0; i < 3; ++i) {
+        if (ms) ms[i] = c->prof_ms[i];
+        if (counts) counts[i] = c->prof_cnt[i];
+    }
+    return STAG_OK;
+}
+
+// Set the Dslash work split (threads per site: 1, 2 or 4) and the number of
+// iterations between convergence polls.
+stag_status stag_tune(stag_handle c, int tps, int chunk) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if ((tps != 1 && tps != 2 && tps != 4) || chunk < 1)
+        return fail(c, STAG_ERR_INVALID_ARG, "tps must be 1, 2 or 4 and chunk >= 1");
+    c->tps = tps;
+    c->chunk = chunk;
+    return STAG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Conversions between the canonical boundary formats and the internal
+// structure-of-arrays layouts, plus fill/copy kernels.
+#include "common.h"
+
+namespace stag {
+
+namespace {
+
+__global__ void k_gauge_to_internal(Geom g, const double2* __restrict__ canon, double2* __restrict__ links) {
+    // one thread per (site, mu); canonical is [l][mu][9]
+    const int V = 2 * g.vh;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int l = i >> 2, mu = i & 3;
+    const int x = l % g.nx, r = l / g.nx;
+    const int y = r % g.ny, r2 = r / g.ny;
+    const int z = r2 % g.nz, t = r2 / g.nz;
+    const int par = (x + y + z + t) & 1;
+    const int cb = l >> 1;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) links[link_off(g, par, mu, e) + cb] = canon[(size_t)i * 9 + e];
+}
+
+__global__ void k_gauge_to_canon(Geom g, const double2* __restrict__ links, double2* __restrict__ canon) {
+    const int V = 2 * g.vh;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int l = i >> 2, mu = i & 3;
+    const int x = l % g.nx, r = l / g.nx;
+    const int y = r % g.ny, r2 = r / g.ny;
+    const int z = r2 % g.nz, t = r2 / g.nz;
+    const int par = (x + y + z + t) & 1;
+    const int cb = l >> 1;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) canon[(size_t)i * 9 + e] = links[link_off(g, par, mu, e) + cb];
+}
+
+__global__ void k_vec_to_internal(int vh, const double2* __restrict__ canon, double2* __restrict__ vec) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= vh) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vec[(size_t)c * vh + k] = canon[(size_t)k * 3 + c];
+}
+
+__global__ void k_vec_to_canon(int vh, const double2* __restrict__ vec, double2* __restrict__ canon) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= vh) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) canon[(size_t)k * 3 + c] = vec[(size_t)c * vh + k];
+}
+
+__global__ void k_mom_to_internal(Geom g, const double* __restrict__ canon, double* __restrict__ mom) {
+    const int V = 2 * g.vh;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int l = i >> 2, mu = i & 3;
+    const int x = l % g.nx, r = l / g.nx;
+    const int y = r % g.ny, r2 = r / g.ny;
+    const int z = r2 % g.nz, t = r2 / g.nz;
+    const int par = (x + y + z + t) & 1;
+    const int cb = l >> 1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) mom[mom_off(g, par, mu, a) + cb] = canon[(size_t)i * 8 + a];
+}
+
+__global__ void k_mom_to_canon(Geom g, const double* __restrict__ mom, double* __restrict__ canon) {
+    const int V = 2 * g.vh;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int l = i >> 2, mu = i & 3;
+    const int x = l % g.nx, r = l / g.nx;
+    const int y = r % g.ny, r2 = r / g.ny;
+    const int z = r2 % g.nz, t = r2 / g.nz;
+    const int par = (x + y + z + t) & 1;
+    const int cb = l >> 1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) canon[(size_t)i * 8 + a] = mom[mom_off(g, par, mu, a) + cb];
+}
+
+__global__ void k_fill_zero(uint4* __restrict__ p, size_t n16) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_copy(uint4* __restrict__ d, const uint4* __restrict__ s, size_t n16) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+
+inline int blocks_for(size_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_gauge_to_internal(const Geom& g, const double2* canon, double2* links, hipStream_t s) {
+    const size_t n = (size_t)8 * g.vh;
+    k_gauge_to_internal<<<blocks_for(n), 256, 0, s>>>(g, canon, links);
+}
+void launch_gauge_to_canon(const Geom& g, const double2* links, double2* canon, hipStream_t s) {
+    const size_t n = (size_t)8 * g.vh;
+    k_gauge_to_canon<<<blocks_for(n), 256, 0, s>>>(g, links, canon);
+}
+void launch_vec_to_internal(const Geom& g, const double2* canon, double2* vec, hipStream_t s) {
+    k_vec_to_internal<<<blocks_for(g.vh), 256, 0, s>>>(g.vh, canon, vec);
+}
+void launch_vec_to_canon(const Geom& g, const double2* vec, double2* canon, hipStream_t s) {
+    k_vec_to_canon<<<blocks_for(g.vh), 256, 0, s>>>(g.vh, vec, canon);
+}
+void launch_mom_to_internal(const Geom& g, const double* canon, double* mom, int, hipStream_t s) {
+    const size_t n = (size_t)8 * g.vh;
+    k_mom_to_internal<<<blocks_for(n), 256, 0, s>>>(g, canon, mom);
+}
+void launch_mom_to_canon(const Geom& g, const double* mom, double* canon, hipStream_t s) {
+    const size_t n = (size_t)8 * g.vh;
+    k_mom_to_canon<<<blocks_for(n), 256, 0, s>>>(g, mom, canon);
+}
+void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+    // every internal buffer is a multiple of 16 bytes
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return;
+    int nb = blocks_for(n16);
+    if (nb > 8192) nb = 8192;
+    k_fill_zero<<<nb, 256, 0, s>>>((uint4*)p, n16);
+}
+void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return;
+    int nb = blocks_for(n16);
+    if (nb > 8192) nb = 8192;
+    k_copy<<<nb, 256, 0, s>>>((uint4*)dst, (const uint4*)src, n16);
+}
+
+}  // namespace stag

@@ -1,0 +1,315 @@
+"""Thin Python binding of libstag (include/stag.h) via ctypes.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch supplies device memory (tensors) and the HIP stream.  If the
+shared library has not been built this module raises instead of falling back
+to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstag.so")
+
+STAG_OK = 0
+STAG_ERR_INVALID_ARG = -1
+STAG_ERR_NO_GAUGE = -2
+STAG_ERR_NOT_CONVERGED = -3
+STAG_ERR_NONFINITE = -4
+STAG_ERR_HIP = -6
+STAG_ERR_OOM = -7
+
+FIELD_HALF_VEC, FIELD_MOM, FIELD_CANON_HALF_VEC, FIELD_CANON_GAUGE, FIELD_CANON_MOM = range(5)
+MAX_POLES = 48
+
+
+class StagError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"stag error {code}: {msg}")
+        self.code = code
+
+
+class CRational(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("c0", ctypes.c_double),
+                ("residue", ctypes.POINTER(ctypes.c_double)), ("pole", ctypes.POINTER(ctypes.c_double))]
+
+
+class CSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("n", ctypes.c_int),
+                ("true_resid", ctypes.POINTER(ctypes.c_double)),
+                ("iters_per_pole", ctypes.POINTER(ctypes.c_int)), ("seconds", ctypes.c_double)]
+
+
+class CHMCParams(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mass", ctypes.c_double), ("tau", ctypes.c_double),
+                ("n_steps", ctypes.c_int), ("r_md", CRational), ("r_action", CRational),
+                ("r_heatbath", CRational), ("tol_md", ctypes.c_double), ("tol_action", ctypes.c_double),
+                ("maxiter", ctypes.c_int), ("seed", ctypes.c_uint64), ("traj_index", ctypes.c_uint64),
+                ("inject_mom", ctypes.c_void_p), ("inject_xi", ctypes.c_void_p),
+                ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int)]
+
+
+class CTrajInfo(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_double), ("K_old", ctypes.c_double), ("Sg_old", ctypes.c_double),
+                ("Sf_old", ctypes.c_double), ("K_new", ctypes.c_double), ("Sg_new", ctypes.c_double),
+                ("Sf_new", ctypes.c_double), ("plaquette", ctypes.c_double), ("accepted", ctypes.c_int),
+                ("cg_iters_total", ctypes.c_int), ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree libstag.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_09178_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    H = ctypes.c_void_p
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    S = ctypes.c_int
+    sig = {
+        "stag_create": (S, [ctypes.POINTER(H), ctypes.POINTER(ctypes.c_int), P]),
+        "stag_destroy": (S, [H]),
+        "stag_last_error": (ctypes.c_char_p, [H]),
+        "stag_field_bytes": (ctypes.c_size_t, [H, I]),
+        "stag_set_gauge": (S, [H, P]),
+        "stag_get_gauge": (S, [H, P]),
+        "stag_vec_import": (S, [H, P, P, I]),
+        "stag_vec_export": (S, [H, P, P, I]),
+        "stag_mom_import": (S, [H, P, P]),
+        "stag_mom_export": (S, [H, P, P]),
+        "stag_dslash": (S, [H, P, P, I]),
+        "stag_mdagm": (S, [H, P, P, D]),
+        "stag_multishift_solve": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(P), P,
+                                      ctypes.POINTER(CSolveInfo)]),
+        "stag_fermion_action": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(D),
+                                    ctypes.POINTER(CSolveInfo)]),
+        "stag_fermion_force": (S, [H, D, ctypes.POINTER(CRational), D, I, P, P, D, ctypes.POINTER(CSolveInfo)]),
+        "stag_gauge_force": (S, [H, D, P, D]),
+        "stag_gauge_action": (S, [H, D, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "stag_kinetic_energy": (S, [H, P, ctypes.POINTER(D)]),
+        "stag_link_update": (S, [H, P, D]),
+        "stag_random_momentum": (S, [H, ctypes.c_uint64, ctypes.c_uint64, P]),
+        "stag_random_source": (S, [H, ctypes.c_uint64, ctypes.c_uint64, P]),
+        "stag_philox": (S, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32), ctypes.c_size_t,
+                            P, P]),
+        "stag_md_trajectory": (S, [H, ctypes.POINTER(CHMCParams), ctypes.POINTER(CTrajInfo)]),
+        "stag_profile_enable": (S, [H, I]),
+        "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
+        "stag_tune": (S, [H, I, I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class RationalArg:
+    """Keeps the coefficient arrays of a CRational alive."""
+
+    def __init__(self, rat):
+        if isinstance(rat, dict):
+            c0, res, pole = rat.get("c0", 0.0), rat["residue"], rat["pole"]
+        else:
+            c0, res, pole = rat
+        self.res = np.ascontiguousarray(res, dtype=np.float64)
+        self.pole = np.ascontiguousarray(pole, dtype=np.float64)
+        self.c = CRational(len(self.pole), float(c0),
+                           self.res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           self.pole.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+
+class Lattice:
+    """One libstag handle: a lattice, its gauge field and solver workspace."""
+
+    def __init__(self, dims: Sequence[int], stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.stream = stream or torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int * 4)(*self.dims)
+        code = self.lib.stag_create(ctypes.byref(h), arr, ctypes.c_void_p(self.stream.cuda_stream))
+        if code != STAG_OK:
+            raise StagError(code, self.lib.stag_last_error(None).decode())
+        self.h = h
+        nx, ny, nz, nt = self.dims
+        self.V = nx * ny * nz * nt
+        self.Vh = self.V // 2
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.stag_destroy(h)
+            self.h = None
+
+    def _check(self, code: int, allow=(STAG_OK,)):
+        if code not in allow:
+            raise StagError(code, self.lib.stag_last_error(self.h).decode())
+        return code
+
+    # ---- allocation helpers (torch device memory)
+    def field_bytes(self, kind: int) -> int:
+        return int(self.lib.stag_field_bytes(self.h, kind))
+
+    def new_vec(self) -> torch.Tensor:
+        return torch.zeros(self.field_bytes(FIELD_HALF_VEC) // 8, dtype=torch.float64, device="cuda")
+
+    def new_mom(self) -> torch.Tensor:
+        return torch.zeros(self.field_bytes(FIELD_MOM) // 8, dtype=torch.float64, device="cuda")
+
+    # ---- fields
+    def set_gauge(self, U: torch.Tensor):
+        self._check(self.lib.stag_set_gauge(self.h, _ptr(U)))
+
+    def get_gauge(self) -> torch.Tensor:
+        nx, ny, nz, nt = self.dims
+        out = torch.empty((nt, nz, ny, nx, 4, 3, 3), dtype=torch.complex128, device="cuda")
+        self._check(self.lib.stag_get_gauge(self.h, _ptr(out)))
+        return out
+
+    def vec_import(self, canon: torch.Tensor, parity: int = 0) -> torch.Tensor:
+        out = self.new_vec()
+        self._check(self.lib.stag_vec_import(self.h, _ptr(out), _ptr(canon), parity))
+        return out
+
+    def vec_export(self, internal: torch.Tensor, parity: int = 0) -> torch.Tensor:
+        out = torch.empty((self.Vh, 3), dtype=torch.complex128, device="cuda")
+        self._check(self.lib.stag_vec_export(self.h, _ptr(out), _ptr(internal), parity))
+        return out
+
+    def mom_import(self, canon: torch.Tensor) -> torch.Tensor:
+        out = self.new_mom()
+        self._check(self.lib.stag_mom_import(self.h, _ptr(out), _ptr(canon)))
+        return out
+
+    def mom_export(self, internal: torch.Tensor) -> torch.Tensor:
+        nx, ny, nz, nt = self.dims
+        out = torch.empty((nt, nz, ny, nx, 4, 8), dtype=torch.float64, device="cuda")
+        self._check(self.lib.stag_mom_export(self.h, _ptr(out), _ptr(internal)))
+        return out
+
+    # ---- operators
+    def dslash(self, out: torch.Tensor, inp: torch.Tensor, out_parity: int):
+        self._check(self.lib.stag_dslash(self.h, _ptr(out), _ptr(inp), out_parity))
+
+    def mdagm(self, out: torch.Tensor, inp: torch.Tensor, mass: float):
+        self._check(self.lib.stag_mdagm(self.h, _ptr(out), _ptr(inp), float(mass)))
+
+    # ---- solver
+    def multishift_solve(self, mass, rat, tol, maxiter, b, xs=None, sum_out=None, true_resid=True,
+                         allow_not_converged=False):
+        r = RationalArg(rat)
+        n = r.c.n
+        resid = (ctypes.c_double * n)()
+        ipp = (ctypes.c_int * n)()
+        info = CSolveInfo(0, 0, resid if true_resid else None, ipp, 0.0)
+        xarr = None
+        if xs is not None:
+            xarr = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+        code = self.lib.stag_multishift_solve(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
+                                              _ptr(b), xarr, _ptr(sum_out), ctypes.byref(info))
+        allow = (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,)
+        self._check(code, allow)
+        return {"code": code, "iters": info.iters, "seconds": info.seconds,
+                "true_resid": list(resid) if true_resid else None, "iters_per_pole": list(ipp)}
+
+    def fermion_action(self, mass, rat, tol, maxiter, phi) -> float:
+        r = RationalArg(rat)
+        S = ctypes.c_double()
+        info = CSolveInfo()
+        self._check(self.lib.stag_fermion_action(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
+                                                 _ptr(phi), ctypes.byref(S), ctypes.byref(info)))
+        return S.value
+
+    def fermion_force(self, mass, rat, tol, maxiter, phi, mom, dt=0.0) -> dict:
+        r = RationalArg(rat)
+        info = CSolveInfo()
+        self._check(self.lib.stag_fermion_force(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
+                                                _ptr(phi), _ptr(mom), float(dt), ctypes.byref(info)))
+        return {"iters": info.iters, "seconds": info.seconds}
+
+    def gauge_force(self, beta, mom, dt=0.0):
+        self._check(self.lib.stag_gauge_force(self.h, float(beta), _ptr(mom), float(dt)))
+
+    def gauge_action(self, beta):
+        S, plaq = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.stag_gauge_action(self.h, float(beta), ctypes.byref(S), ctypes.byref(plaq)))
+        return S.value, plaq.value
+
+    def kinetic_energy(self, mom) -> float:
+        K = ctypes.c_double()
+        self._check(self.lib.stag_kinetic_energy(self.h, _ptr(mom), ctypes.byref(K)))
+        return K.value
+
+    def link_update(self, mom, dt):
+        self._check(self.lib.stag_link_update(self.h, _ptr(mom), float(dt)))
+
+    def random_momentum(self, seed, traj) -> torch.Tensor:
+        out = self.new_mom()
+        self._check(self.lib.stag_random_momentum(self.h, int(seed), int(traj), _ptr(out)))
+        return out
+
+    def random_source(self, seed, traj) -> torch.Tensor:
+        out = self.new_vec()
+        self._check(self.lib.stag_random_source(self.h, int(seed), int(traj), _ptr(out)))
+        return out
+
+    def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
+                   maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
+                   no_fermions=False) -> dict:
+        a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
+        prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
+                         _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions))
+        info = CTrajInfo()
+        self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
+
+    # ---- measurement / tuning
+    def profile_enable(self, max_launches: int):
+        self._check(self.lib.stag_profile_enable(self.h, int(max_launches)))
+
+    def profile_read(self):
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_long * 3)()
+        self._check(self.lib.stag_profile_read(self.h, ms, cnt))
+        return list(ms), list(cnt)
+
+    def tune(self, tps: int, chunk: int):
+        self._check(self.lib.stag_tune(self.h, int(tps), int(chunk)))
+
+
+def philox(ctr, key, n: int) -> torch.Tensor:
+    """Raw Philox4x32-10 words for counters ctr + (i,0,0,0), i < n (device tensor, int64 view of uint32)."""
+    lib = load_library()
+    out = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    code = lib.stag_philox(c, k, n, _ptr(out), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if code != STAG_OK:
+        raise StagError(code, lib.stag_last_error(None).decode())
+    return out

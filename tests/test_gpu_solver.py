@@ -1,0 +1,149 @@
+"""GPU multi-shift CG (Sec. 4) against the oracle: solutions, true residuals
+evaluated with the oracle's operator, the rational sum, the Krylov bound at
+U = 1, determinism, and the documented error paths."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac
+from oracle.solvers import multishift_cg, true_residuals
+from paper_1710_09178_amd.stag import (STAG_ERR_INVALID_ARG, STAG_ERR_NO_GAUGE, STAG_ERR_NONFINITE,
+                                       STAG_ERR_NOT_CONVERGED, Lattice, StagError)
+from tests.gpu_util import dev, host, lattice, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+C0_DIMS = (4, 4, 4, 4)
+C0_POLES = list(np.logspace(-4, 0, 8))
+
+
+def _rat(poles, residues=None, c0=0.0):
+    return {"c0": c0, "pole": list(poles), "residue": list(residues if residues is not None else np.ones(len(poles)))}
+
+
+def _solve(lat, dims, mass, rat, tol, b, maxiter=100000):
+    n = len(rat["pole"])
+    xs = [lat.new_vec() for _ in range(n)]
+    s = lat.new_vec()
+    info = lat.multishift_solve(mass, rat, tol, maxiter, lat.vec_import(dev(b), 0), xs, s)
+    return [host(lat.vec_export(x, 0)) for x in xs], host(lat.vec_export(s, 0)), info
+
+
+@pytest.mark.parametrize("dims,eps,mass", [(C0_DIMS, 0.3, 0.1), ((8, 6, 4, 10), 0.4, 0.05), ((2, 2, 2, 2), 0.8, 0.2)])
+def test_multishift_matches_oracle(dims, eps, mass):
+    """Solutions agree with the oracle's multi-shift CG (both to tol 1e-12);
+    the bound 2 tol kappa_k follows from both residuals being below tol."""
+    log(f"multishift parity dims={dims} mass={mass}")
+    rng = synth.make_rng(0, 0)
+    U = synth.random_su3_near_identity(dims, eps, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    lat = lattice(dims, U)
+    rat = _rat(C0_POLES, np.linspace(0.5, 2.0, 8), c0=0.25)
+    xs, s, info = _solve(lat, dims, mass, rat, 1e-12, b)
+    op = lambda v: dirac.apply_A(U, v, dims, mass)
+    ref = multishift_cg(op, b, C0_POLES, 1e-12)
+    lmin, lmax = 4 * mass * mass, 4 * mass * mass + 64
+    for k, (sig, x, xr) in enumerate(zip(C0_POLES, xs, ref["x"])):
+        kappa = (lmax + sig) / (lmin + sig)
+        assert np.linalg.norm(x - xr) <= 2e-12 * kappa * np.linalg.norm(xr)
+    res = true_residuals(op, b, C0_POLES, xs)
+    assert res.max() < 1e-11
+    assert np.allclose(info["true_resid"], res, rtol=1e-3, atol=1e-15)
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    expect_sum = 0.25 * b + sum(c * x for c, x in zip(rat["residue"], xs))
+    assert rel_err(s, expect_sum) < 1e-14
+
+
+def test_c0_configuration_tol_1e10():
+    """4^4, eps 0.3, m 0.1, 8 poles logspace(-4,0), tolerance 1e-10."""
+    rng = synth.make_rng(0, 1)
+    U = synth.random_su3_near_identity(C0_DIMS, 0.3, rng)
+    b = synth.gaussian_half_vector(C0_DIMS, rng)
+    lat = lattice(C0_DIMS, U)
+    xs, _, info = _solve(lat, C0_DIMS, 0.1, _rat(C0_POLES), 1e-10, b)
+    res = true_residuals(lambda v: dirac.apply_A(U, v, C0_DIMS, 0.1), b, C0_POLES, xs)
+    assert res.max() < 1e-10
+    assert max(info["true_resid"]) < 1e-10
+
+
+def test_full_size_32c8_twelve_poles():
+    """32^3x8, eps 0.2, m 0.005, the 12-pole x^(-1/4) table, tol 1e-10: every
+    pole's true residual, evaluated by the oracle's operator, is below 1e-10."""
+    dims = (32, 32, 32, 8)
+    log("multishift at 32^3x8, 12 poles")
+    rng = synth.make_rng(1, 0)
+    U = synth.random_su3_near_identity(dims, 0.2, rng)
+    b = synth.gaussian_half_vector(dims, synth.make_rng(1, 1))
+    rat = synth.load_rational("xm025_n12_m0.005")
+    lat = lattice(dims, U)
+    xs, s, info = _solve(lat, dims, 0.005, rat, 1e-10, b)
+    log(f"  iterations {info['iters']} seconds {info['seconds']:.3f}")
+    res = true_residuals(lambda v: dirac.apply_A(U, v, dims, 0.005), b, rat["pole"], xs)
+    assert res.max() < 1e-10, res
+    assert np.allclose(info["true_resid"], res, rtol=1e-2, atol=1e-14)
+    expect_sum = rat["c0"] * b + sum(c * x for c, x in zip(rat["residue"], xs))
+    assert rel_err(s, expect_sum) < 1e-13
+
+
+def test_krylov_bound_unit_gauge():
+    nx, ny, nz, nt = C0_DIMS
+    U = np.zeros((nt, nz, ny, nx, 4, 3, 3), dtype=np.complex128)
+    U[...] = np.eye(3)
+    b = synth.gaussian_half_vector(C0_DIMS, synth.make_rng(0, 2))
+    lat = lattice(C0_DIMS, U)
+    xs, _, info = _solve(lat, C0_DIMS, 0.1, _rat(C0_POLES), 1e-12, b)
+    assert info["iters"] <= 5
+    assert max(info["true_resid"]) < 1e-12
+
+
+def test_deterministic_bitwise():
+    dims = (8, 6, 4, 10)
+    rng = synth.make_rng(0, 3)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    lat = lattice(dims, U)
+    a, sa, ia = _solve(lat, dims, 0.1, _rat(C0_POLES), 1e-10, b)
+    c, sc, ic = _solve(lat, dims, 0.1, _rat(C0_POLES), 1e-10, b)
+    assert ia["iters"] == ic["iters"]
+    assert all(np.array_equal(x, y) for x, y in zip(a, c)) and np.array_equal(sa, sc)
+
+
+def test_error_paths():
+    dims = (4, 4, 4, 4)
+    rng = synth.make_rng(0, 4)
+    U = synth.random_su3_near_identity(dims, 0.3, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    lat = Lattice(dims)
+    bd = lat.vec_import(dev(b), 0)
+    with pytest.raises(StagError) as e:
+        lat.multishift_solve(0.1, _rat(C0_POLES), 1e-10, 100, bd)
+    assert e.value.code == STAG_ERR_NO_GAUGE
+    lat.set_gauge(dev(U))
+    # zero source: zero solutions, no iterations
+    z = lat.new_vec()
+    xs = [lat.new_vec() for _ in C0_POLES]
+    info = lat.multishift_solve(0.1, _rat(C0_POLES), 1e-10, 100, z, xs)
+    assert info["iters"] == 0 and all(float(x.abs().max()) == 0 for x in xs)
+    # maxiter reached: non-fatal, info filled
+    info = lat.multishift_solve(0.1, _rat(C0_POLES), 1e-10, 1, bd, allow_not_converged=True)
+    assert info["code"] == STAG_ERR_NOT_CONVERGED and info["iters"] == 1
+    # NaN in the source
+    bn = b.copy()
+    bn[3, 1] = np.nan
+    with pytest.raises(StagError) as e:
+        lat.multishift_solve(0.1, _rat(C0_POLES), 1e-10, 100, lat.vec_import(dev(bn), 0))
+    assert e.value.code == STAG_ERR_NONFINITE
+    # invalid pole lists and aliasing
+    for bad in [_rat([-1.0, 0.5]), _rat([]), _rat([np.inf])]:
+        with pytest.raises(StagError) as e:
+            lat.multishift_solve(0.1, bad, 1e-10, 100, bd)
+        assert e.value.code == STAG_ERR_INVALID_ARG
+    with pytest.raises(StagError) as e:
+        lat.multishift_solve(0.0, _rat([0.0]), 1e-10, 100, bd)
+    assert e.value.code == STAG_ERR_INVALID_ARG
+    with pytest.raises(StagError) as e:
+        lat.multishift_solve(0.1, _rat([0.1]), 1e-10, 100, bd, xs=[bd])
+    assert e.value.code == STAG_ERR_INVALID_ARG
+    with pytest.raises(StagError) as e:
+        lat.dslash(bd, bd, 1)
+    assert e.value.code == STAG_ERR_INVALID_ARG

@@ -1,0 +1,78 @@
+"""One RHMC trajectory on the GPU (Sec. 3.1: heat bath, leapfrog, Metropolis)
+against the oracle trajectory with the same momenta, noise and uniform."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hmc, philox
+from tests.gpu_util import dev, host, lattice, log
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(n_steps, tau):
+    return hmc.HMCParams(beta=5.4, mass=0.1, tau=tau, n_steps=n_steps,
+                         r_md=synth.load_rational("xm050_n8_m0.1"),
+                         r_action=synth.load_rational("xm050_n8_m0.1"),
+                         r_heatbath=synth.load_rational("xp025_n8_m0.1"),
+                         tol_md=1e-12, tol_action=1e-12)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 2, 4), (6, 4, 4, 8)])
+def test_trajectory_matches_oracle(dims):
+    log(f"trajectory parity dims={dims}")
+    rng = synth.make_rng(300, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.4, rng)
+    seed, traj = 2024, 3
+    prm = _params(6, 0.5)
+    P0 = philox.momentum(dims, seed, traj)
+    xi = philox.source(dims, seed, traj)
+    u = philox.uniform(seed, traj)
+    ref = hmc.trajectory(U0, dims, prm, P0, xi, u)
+    lat = lattice(dims, U0)
+    out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                         tol_md=1e-12, tol_action=1e-12, seed=seed, traj_index=traj)
+    log(f"  dH gpu {out['dH']:.12e} oracle {ref['dH']:.12e}")
+    K0, Sg0, Sf0 = ref["H0"]
+    K1, Sg1, Sf1 = ref["H1"]
+    for a, b in [(out["K_old"], K0), (out["Sg_old"], Sg0), (out["Sf_old"], Sf0),
+                 (out["K_new"], K1), (out["Sg_new"], Sg1), (out["Sf_new"], Sf1)]:
+        assert abs(a - b) <= 1e-10 * abs(b)
+    assert abs(out["dH"] - ref["dH"]) < 1e-8
+    assert out["accepted"] == int(ref["accepted"])
+    Ug = host(lat.get_gauge())
+    assert np.abs(Ug - ref["U"]).max() < 1e-10
+    assert abs(out["plaquette"] - ref["plaquette"]) < 1e-12
+
+
+def test_injected_fields_and_rejection_restores():
+    dims = (4, 4, 2, 4)
+    rng = synth.make_rng(301, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.4, rng)
+    P0 = synth.gaussian_momentum(dims, rng)
+    xi = synth.gaussian_half_vector(dims, rng, scale=np.sqrt(0.5))
+    prm = _params(4, 0.5)
+    ref = hmc.trajectory(U0, dims, prm, P0, xi, 0.999999)
+    lat = lattice(dims, U0)
+    out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                         tol_md=1e-12, tol_action=1e-12, inject_mom=lat.mom_import(dev(P0)),
+                         inject_xi=lat.vec_import(dev(xi), 0), inject_u=0.999999)
+    assert abs(out["dH"] - ref["dH"]) < 1e-8
+    assert out["accepted"] == int(ref["accepted"])
+    if not out["accepted"]:
+        assert np.array_equal(host(lat.get_gauge()), U0)
+
+
+def test_pure_gauge_trajectory():
+    dims = (6, 4, 4, 8)
+    rng = synth.make_rng(302, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.6, rng)
+    seed, traj = 5, 0
+    prm = _params(8, 1.0)
+    P0 = philox.momentum(dims, seed, traj)
+    ref = hmc.trajectory(U0, dims, prm, P0, None, philox.uniform(seed, traj), with_fermions=False)
+    lat = lattice(dims, U0)
+    out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                         seed=seed, traj_index=traj, no_fermions=True)
+    assert abs(out["dH"] - ref["dH"]) < 1e-9
+    assert np.abs(host(lat.get_gauge()) - ref["U"]).max() < 1e-11
