@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--tps", type=int, default=0, help="Dslash threads per site (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -145,6 +146,11 @@ def main():
     upd_bytes = solve_bytes(vh, chk["iters"], chk["iters_per_pole"], base) - (B_DOE + B_DEO_CG) * vh * chk["iters"]
     upd_gbs = upd_bytes / max(cnt[2], 1) / (avg_us[2] * 1e-6) / 1e9
 
+    forms = {}
+    if not args.no_forms:
+        log("precision forms")
+        forms = precision_forms(lat, rat, bd, xs, vh, base, ms_per_step)
+
     traj = None
     if not args.no_trajectory:
         log("RHMC trajectory at 16^3x8")
@@ -179,10 +185,46 @@ def main():
     }
     if traj:
         out["sec_per_trajectory"] = traj
+    if forms:
+        out["precision_forms"] = forms
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(U, b, rat, vh, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
+    """The same 32^3x8 solve with 12-real FP64 links, and in mixed precision
+    (FP32 Krylov vectors with FP32-18 or FP16-12 links, FP64 reliable updates,
+    every pole to the FP64 true residual 1e-10)."""
+    import torch
+    from paper_1710_09178_amd import stag
+    out = {}
+    lat.set_link_format(stag.LINKS_F64_12)
+    lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        i12 = lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
+    torch.cuda.synchronize()
+    ms12 = (time.perf_counter() - t0) / reps * 1e3
+    chk = lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=True)
+    out["fp64_links12"] = {"ms_per_solve": round(ms12, 3), "speedup_vs_fp64_18": round(fp64_ms / ms12, 3),
+                           "iterations": i12["iters"], "true_resid_max": max(chk["true_resid"])}
+    lat.set_link_format(stag.LINKS_F64_18)
+    for name, fmt in [("mixed_fp32_links18", stag.LINKS_F32_18), ("mixed_fp32_fp16links12", stag.LINKS_F16_12)]:
+        lat.multishift_solve_mixed(MASS, rat, TOL, 100000, bd, xs, None, sloppy=fmt, true_resid=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            im = lat.multishift_solve_mixed(MASS, rat, TOL, 100000, bd, xs, None, sloppy=fmt, true_resid=False)
+        torch.cuda.synchronize()
+        msm = (time.perf_counter() - t0) / reps * 1e3
+        chk = lat.multishift_solve_mixed(MASS, rat, TOL, 100000, bd, xs, None, sloppy=fmt, true_resid=True)
+        out[name] = {"ms_per_solve": round(msm, 3), "speedup_vs_fp64_18": round(fp64_ms / msm, 3),
+                     "iterations_total": im["iters"], "iterations_per_pole": im["iters_per_pole"],
+                     "true_resid_max": max(chk["true_resid"]), "tol_sloppy": 1e-5, "reliable_every": 50}
+    return out
 
 
 def trajectory_timing():

@@ -138,6 +138,41 @@ stag_status stag_multishift_solve(stag_handle h, double mass, const stag_rationa
                                   int maxiter, const void* b_even, void* const* x_even,
                                   void* sum_even, stag_solve_info* info);
 
+/* ---- precision form ------------------------------------------------------ */
+
+/* Storage of the links read by the Dirac operator.  The 12-real formats keep
+ * rows 0 and 1 and rebuild row 2 = conj(row0 x row1), exact for SU(3). */
+typedef enum {
+    STAG_LINKS_F64_18 = 0,   /* FP64, 18 reals per link (default) */
+    STAG_LINKS_F64_12 = 1,   /* FP64, 12 reals per link */
+    STAG_LINKS_F32_18 = 2,   /* FP32, 18 reals (mixed-precision solver only) */
+    STAG_LINKS_F16_12 = 3    /* IEEE FP16, 12 reals (mixed-precision solver only) */
+} stag_link_format;
+
+/* Storage used by every FP64 operator application of h (Dslash, A, solves,
+ * forces): STAG_LINKS_F64_18 or STAG_LINKS_F64_12.  The compressed copy is
+ * derived from the handle's links whenever they change. */
+stag_status stag_set_link_format(stag_handle h, int format);
+
+typedef struct {
+    int sloppy;              /* STAG_LINKS_F32_18 or STAG_LINKS_F16_12 (FP32 vectors in both) */
+    double tol_sloppy;       /* FP32 multi-shift phase stops at this relative residual, e.g. 1e-5 */
+    int reliable_every;      /* FP64 true-residual recompute interval of the refinement CG, e.g. 50 */
+} stag_mixed_opts;
+
+/* Same contract as stag_multishift_solve (outputs, tolerance meaning: FP64
+ * true residual |b - (A+pole_k) x_k| <= tol |b| for every pole), computed in
+ * mixed precision: an FP32 multi-shift CG with FP64 solution accumulators and
+ * FP64 reductions down to tol_sloppy, then for each pole a CG in FP32 started
+ * from the FP64 residual whose residual is recomputed in FP64 (with FP64 links)
+ * every reliable_every iterations.  info->iters counts all iterations of both
+ * phases; info->iters_per_pole[k] = multi-shift iterations of pole k plus its
+ * refinement iterations. */
+stag_status stag_multishift_solve_mixed(stag_handle h, double mass, const stag_rational* r, double tol,
+                                        int maxiter, const void* b_even, void* const* x_even,
+                                        void* sum_even, const stag_mixed_opts* opts,
+                                        stag_solve_info* info);
+
 /* ---- actions and forces (eq. pfact; Sec. 3.1) ---------------------------- */
 
 /* S_f = phi^dag r(A) phi with r the action's rational function (host out). */

@@ -11,54 +11,15 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "ctx.h"
 
 using namespace stag;
 
-struct stag_ctx {
-    Geom g{};
-    int dims[4]{};
-    int device = 0;
-    hipStream_t user = nullptr;
-    hipStream_t s = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipEvent_t chunk_ev[2]{};
-    double2* links = nullptr;
-    double2* links_backup = nullptr;
-    double* mom = nullptr;
-    double2 *r = nullptr, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
-    double2 *xi = nullptr, *phi = nullptr;
-    double2* pool_x = nullptr;   // n_cap even vectors: solutions
-    double2* pool_p = nullptr;   // n_cap even vectors: shifted search directions
-    double2* pool_y = nullptr;   // n_cap odd vectors: D_oe x_k for the force
-    int n_cap = 0;
-    MsState* st = nullptr;
-    MsState* st_host = nullptr;  // pinned
-    double* dpart = nullptr;      // CG dot partials of the D_eo kernel (3 x blocks)
-    double* qpart[2] = {nullptr, nullptr};  // <r,r> partials, alternating by iteration parity
-    double* gpart = nullptr;      // partials of the other reductions
-    double* scal = nullptr;       // device scalars for reductions
-    double* scal_host = nullptr;  // pinned
-    int* done_host = nullptr;     // pinned [2]
-    bool has_gauge = false;
-    int tps = 2;                  // threads per site in the Dslash
-    int chunk = 16;               // iterations enqueued between convergence polls
-    // profiling of the Dslash launches inside the solver (hipEvent pairs)
-    int prof_on = 0;
-    std::vector<hipEvent_t> prof_ev;
-    size_t prof_used = 0;
-    double prof_ms[3] = {0, 0, 0};   // D_oe, D_eo+CG epilogue, shift update
-    long prof_cnt[3] = {0, 0, 0};
-    std::string err;
-    int last_iters = 0;
-};
-
 namespace {
-
 thread_local std::string g_create_err;
+}
 
-size_t half_bytes(const Geom& g) { return (size_t)3 * g.vh * sizeof(double2); }
-
+namespace stag {
 stag_status fail(stag_ctx* c, stag_status code, const std::string& msg) {
     if (c)
         c->err = msg;
@@ -66,13 +27,9 @@ stag_status fail(stag_ctx* c, stag_status code, const std::string& msg) {
         g_create_err = msg;
     return code;
 }
+}  // namespace stag
 
-#define HIP_OR_FAIL(c, expr)                                                                   \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess)                                                                  \
-            return fail((c), STAG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+namespace {
 
 bool aligned16(const void* p) { return p && ((uintptr_t)p % 16 == 0); }
 
@@ -113,172 +70,6 @@ stag_status leave(stag_ctx* c) {
     HIP_OR_FAIL(c, hipGetLastError());
     HIP_OR_FAIL(c, hipEventRecord(c->ev_out, c->s));
     HIP_OR_FAIL(c, hipStreamWaitEvent(c->user, c->ev_out, 0));
-    return STAG_OK;
-}
-
-template <class T>
-stag_status dmalloc(stag_ctx* c, T** p, size_t bytes) {
-    if (hipMalloc((void**)p, bytes) != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(c, STAG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
-    return STAG_OK;
-}
-
-stag_status ensure_pool(stag_ctx* c, int n) {
-    if (n <= c->n_cap) return STAG_OK;
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
-    hipFree(c->pool_x);
-    hipFree(c->pool_p);
-    hipFree(c->pool_y);
-    c->pool_x = c->pool_p = c->pool_y = nullptr;
-    c->n_cap = 0;
-    const size_t hb = half_bytes(c->g);
-    stag_status st;
-    if ((st = dmalloc(c, &c->pool_x, hb * n)) != STAG_OK) return st;
-    if ((st = dmalloc(c, &c->pool_p, hb * n)) != STAG_OK) return st;
-    if ((st = dmalloc(c, &c->pool_y, hb * n)) != STAG_OK) return st;
-    c->n_cap = n;
-    return STAG_OK;
-}
-
-double2* pool_vec(double2* pool, const Geom& g, int k) { return pool + (size_t)k * 3 * g.vh; }
-
-// ---- profiling helpers: events around kernels inside the solver loop
-void prof_begin(stag_ctx* c, hipEvent_t* a) {
-    if (!c->prof_on) return;
-    if (c->prof_used + 2 > c->prof_ev.size()) {
-        *a = nullptr;
-        return;
-    }
-    *a = c->prof_ev[c->prof_used];
-    hipEventRecord(*a, c->s);
-}
-void prof_end(stag_ctx* c, hipEvent_t a, int kind, std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>& rec) {
-    if (!c->prof_on || !a) return;
-    hipEvent_t b = c->prof_ev[c->prof_used + 1];
-    hipEventRecord(b, c->s);
-    c->prof_used += 2;
-    rec.push_back({{a, b}, kind});
-}
-
-struct SolveResult {
-    int iters = 0;
-    int nonfinite = 0;
-    int converged = 1;
-};
-
-// Multi-shift CG on A + pole_k.  x[k] receive the solutions.  The host only
-// enqueues kernels and polls the device "done" flag once per chunk of
-// iterations; two chunks are kept in flight so the GPU never waits.
-stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter, const double2* b,
-                     double2* const* x, bool want_resid, double* resid_out, int* ipp_out, SolveResult& res) {
-    const Geom& g = c->g;
-    const int n = r->n;
-    stag_status e = ensure_pool(c, n);
-    if (e != STAG_OK) return e;
-    int base = 0;
-    for (int k = 1; k < n; ++k)
-        if (r->pole[k] < r->pole[base]) base = k;
-    const double s0 = r->pole[base];
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));  // st_host is reused
-    MsState* h = c->st_host;
-    std::memset(h, 0, sizeof(MsState));
-    h->n = n;
-    h->base = base;
-    h->maxiter = maxiter;
-    h->tol2 = tol * tol;
-    h->mass_term = 4.0 * mass * mass + s0;
-    h->c0 = r->c0;
-    for (int k = 0; k < n; ++k) {
-        h->shift[k] = r->pole[k] - s0;
-        h->coef[k] = r->residue[k];
-        h->it[0].zeta[k] = h->it[0].zeta_old[k] = 1.0;
-        h->it[0].active[k] = 1;
-    }
-    h->it[0].alpha_old = 1.0;
-    h->it[0].beta_old = 0.0;
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
-    VecPtrs X{}, P{};
-    for (int k = 0; k < n; ++k) {
-        X.p[k] = x[k];
-        P.p[k] = pool_vec(c->pool_p, g, k);
-    }
-    launch_ms_init(g, b, c->r, c->p, X, P, c->st, c->qpart[0], c->s);
-
-    std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>> rec;
-    c->prof_used = 0;
-    const double mt = h->mass_term;
-    const int nb2 = dslash_grid(g, c->tps);
-    int it_issued = 0;
-    auto issue_chunk = [&](int slot) {
-        for (int it = 0; it < c->chunk; ++it, ++it_issued) {
-            const int par = it_issued & 1;
-            hipEvent_t a;
-            prof_begin(c, &a);
-            launch_dslash_gated(g, c->links, c->p, c->w_o, 1, c->tps, c->st, c->s);
-            prof_end(c, a, 0, rec);
-            prof_begin(c, &a);
-            launch_dslash_cg(g, c->links, c->w_o, c->p, c->r, c->Ap, c->st, c->dpart, c->tps, c->s, mt);
-            prof_end(c, a, 1, rec);
-            prof_begin(c, &a);
-            launch_ms_step(g, c->r, c->Ap, c->p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
-                           c->s);
-            prof_end(c, a, 2, rec);
-        }
-        hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->s);
-        hipEventRecord(c->chunk_ev[slot], c->s);
-    };
-    issue_chunk(0);
-    issue_chunk(1);
-    int cur = 0;
-    for (;;) {
-        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
-        if (c->done_host[cur]) break;
-        issue_chunk(cur);
-        cur ^= 1;
-    }
-    HIP_OR_FAIL(c, hipGetLastError());
-    if (want_resid) {
-        const int nbr = dslash_grid(g, c->tps);
-        for (int k = 0; k < n; ++k) {
-            launch_dslash(g, c->links, x[k], c->tmp_o, 1, c->tps, c->s);
-            launch_dslash_resid(g, c->links, c->tmp_o, x[k], b, 4.0 * mass * mass + r->pole[k], c->gpart, c->tps,
-                                c->s);
-            double* slot = (double*)((char*)c->st + offsetof(MsState, true_res2)) + k;
-            launch_finalize(c->gpart, nbr, 1, slot, c->s);
-        }
-    }
-    HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
-    const MsIter& f = h->fin;
-    // kernel times: iterations 0..iter (the last one only detects convergence
-    // in its step kernel, after full Dslash launches)
-    {
-        long seen[3] = {0, 0, 0};
-        const long lim[3] = {f.iter + 1, f.iter + 1, f.iter};
-        for (auto& q : rec) {
-            const int kind = q.second;
-            if (seen[kind]++ >= lim[kind]) continue;
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, q.first.first, q.first.second) == hipSuccess) {
-                c->prof_ms[kind] += ms;
-                c->prof_cnt[kind] += 1;
-            }
-        }
-    }
-    res.iters = f.iter;
-    res.nonfinite = f.nonfinite;
-    res.converged = 1;
-    for (int k = 0; k < n; ++k)
-        if (f.active[k]) res.converged = 0;
-    const double bb = f.bb;
-    for (int k = 0; k < n; ++k) {
-        if (resid_out) resid_out[k] = (want_resid && bb > 0) ? std::sqrt(h->true_res2[k] / bb) : -1.0;
-        if (ipp_out) ipp_out[k] = f.iters_per_pole[k];
-    }
-    c->last_iters = f.iter;
     return STAG_OK;
 }
 
@@ -324,11 +115,13 @@ stag_status fermion_force_impl(stag_ctx* c, double mass, const stag_rational* r,
     std::vector<double2*> xs(r->n);
     for (int k = 0; k < r->n; ++k) xs[k] = pool_vec(c->pool_x, g, k);
     if ((e = ms_solve(c, mass, r, tol, maxiter, phi, xs.data(), false, nullptr, nullptr, res)) != STAG_OK) return e;
+    LinkSet ls;
+    if ((e = get_links(c, -1, ls))) return e;
     VecPtrs X{}, Y{};
     for (int k = 0; k < r->n; ++k) {
         X.p[k] = xs[k];
         Y.p[k] = pool_vec(c->pool_y, g, k);
-        launch_dslash(g, c->links, X.p[k], Y.p[k], 1, c->tps, c->s);
+        launch_dslash(g, ls, xs[k], pool_vec(c->pool_y, g, k), 1, c->tps, nullptr, c->s);
     }
     const double* coef = (const double*)((const char*)c->st + offsetof(MsState, coef));
     launch_fermion_force(g, c->links, X, Y, coef, r->n, mom, dt, c->s);
@@ -433,7 +226,8 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
 stag_status stag_destroy(stag_handle c) {
     if (!c) return STAG_OK;
     if (c->s) hipStreamSynchronize(c->s);
-    void* bufs[] = {c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
+    void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->r32, c->p32, c->Ap32, c->w32,
+                    c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
                     c->gpart, c->scal};
     for (void* b : bufs)
@@ -471,6 +265,7 @@ stag_status stag_set_gauge(stag_handle c, const double* U) {
     if (!aligned16(U)) return fail(c, STAG_ERR_INVALID_ARG, "gauge pointer is NULL or not 16-byte aligned");
     if ((e = enter(c))) return e;
     launch_gauge_to_internal(c->g, (const double2*)U, c->links, c->s);
+    links_changed(c);
     c->has_gauge = true;
     return leave(c);
 }
@@ -533,7 +328,9 @@ stag_status stag_dslash(stag_handle c, void* out, const void* in, int out_parity
         return fail(c, STAG_ERR_INVALID_ARG, "vector pointers NULL, misaligned or equal");
     if (out_parity != 0 && out_parity != 1) return fail(c, STAG_ERR_INVALID_ARG, "parity must be 0 or 1");
     if ((e = enter(c))) return e;
-    launch_dslash(c->g, c->links, (const double2*)in, (double2*)out, out_parity, c->tps, c->s);
+    LinkSet ls;
+    if ((e = get_links(c, -1, ls))) return e;
+    launch_dslash(c->g, ls, (const double2*)in, (double2*)out, out_parity, c->tps, nullptr, c->s);
     return leave(c);
 }
 
@@ -544,13 +341,16 @@ stag_status stag_mdagm(stag_handle c, void* out, const void* in, double mass) {
         return fail(c, STAG_ERR_INVALID_ARG, "vector pointers NULL, misaligned or equal");
     if (!std::isfinite(mass)) return fail(c, STAG_ERR_INVALID_ARG, "mass must be finite");
     if ((e = enter(c))) return e;
-    launch_dslash(c->g, c->links, (const double2*)in, c->tmp_o, 1, c->tps, c->s);
-    launch_dslash_axpy(c->g, c->links, c->tmp_o, (const double2*)in, 4.0 * mass * mass, (double2*)out, c->tps, c->s);
+    LinkSet ls;
+    if ((e = get_links(c, -1, ls))) return e;
+    launch_dslash(c->g, ls, (const double2*)in, c->tmp_o, 1, c->tps, nullptr, c->s);
+    launch_dslash_axpy(c->g, ls, c->tmp_o, (const double2*)in, 4.0 * mass * mass, (double2*)out, c->tps, c->s);
     return leave(c);
 }
 
-stag_status stag_multishift_solve(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
-                                  const void* b, void* const* x, void* sum, stag_solve_info* info) {
+namespace {
+stag_status solve_entry(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter, const void* b,
+                        void* const* x, void* sum, const stag_mixed_opts* mixed, stag_solve_info* info) {
     const double t0 = now_s();
     stag_status e = check_common(c, true);
     if (e) return e;
@@ -565,14 +365,24 @@ stag_status stag_multishift_solve(stag_handle c, double mass, const stag_rationa
                 if (x[j] == x[k]) return fail(c, STAG_ERR_INVALID_ARG, "solution pointers must be distinct");
         }
     if (sum && (!aligned16(sum) || sum == b)) return fail(c, STAG_ERR_INVALID_ARG, "sum pointer misaligned or aliases b");
+    if (mixed) {
+        if (mixed->sloppy != STAG_LINKS_F32_18 && mixed->sloppy != STAG_LINKS_F16_12)
+            return fail(c, STAG_ERR_INVALID_ARG, "sloppy link format must be STAG_LINKS_F32_18 or STAG_LINKS_F16_12");
+        if (!(mixed->tol_sloppy > 0.0) || mixed->tol_sloppy >= 1.0 || mixed->reliable_every < 1)
+            return fail(c, STAG_ERR_INVALID_ARG, "need 0 < tol_sloppy < 1 and reliable_every >= 1");
+    }
     if ((e = enter(c))) return e;
     if ((e = ensure_pool(c, r->n))) return e;
     std::vector<double2*> xs(r->n);
     for (int k = 0; k < r->n; ++k) xs[k] = x ? (double2*)x[k] : pool_vec(c->pool_x, c->g, k);
     SolveResult res;
     const bool want_resid = info && info->true_resid;
-    e = ms_solve(c, mass, r, tol, maxiter, (const double2*)b, xs.data(), want_resid, info ? info->true_resid : nullptr,
-                 info ? info->iters_per_pole : nullptr, res);
+    double* ro = info ? info->true_resid : nullptr;
+    int* ipp = info ? info->iters_per_pole : nullptr;
+    if (mixed)
+        e = ms_solve_mixed(c, mass, r, tol, maxiter, (const double2*)b, xs.data(), mixed, want_resid, ro, ipp, res);
+    else
+        e = ms_solve(c, mass, r, tol, maxiter, (const double2*)b, xs.data(), want_resid, ro, ipp, res);
     if (e) return e;
     if (sum) {
         VecPtrs X{};
@@ -587,6 +397,28 @@ stag_status stag_multishift_solve(stag_handle c, double mass, const stag_rationa
         info->seconds = now_s() - t0;
     }
     return finish_solve_status(c, res);
+}
+}  // namespace
+
+stag_status stag_multishift_solve(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
+                                  const void* b, void* const* x, void* sum, stag_solve_info* info) {
+    return solve_entry(c, mass, r, tol, maxiter, b, x, sum, nullptr, info);
+}
+
+stag_status stag_multishift_solve_mixed(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
+                                        const void* b, void* const* x, void* sum, const stag_mixed_opts* opts,
+                                        stag_solve_info* info) {
+    if (!opts) return fail(c, STAG_ERR_INVALID_ARG, "mixed-precision options are NULL");
+    return solve_entry(c, mass, r, tol, maxiter, b, x, sum, opts, info);
+}
+
+stag_status stag_set_link_format(stag_handle c, int format) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (format != STAG_LINKS_F64_18 && format != STAG_LINKS_F64_12)
+        return fail(c, STAG_ERR_INVALID_ARG, "FP64 operator format must be STAG_LINKS_F64_18 or STAG_LINKS_F64_12");
+    c->fmt64 = format;
+    return STAG_OK;
 }
 
 stag_status stag_fermion_action(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
@@ -663,6 +495,7 @@ stag_status stag_link_update(stag_handle c, const void* mom, double dt) {
     if (!aligned16(mom) || !std::isfinite(dt)) return fail(c, STAG_ERR_INVALID_ARG, "mom NULL/misaligned or dt not finite");
     if ((e = enter(c))) return e;
     launch_link_update(c->g, c->links, (const double*)mom, dt, c->s);
+    links_changed(c);
     return leave(c);
 }
 
@@ -769,6 +602,7 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     if ((e = kick(0.5 * dt))) return e;
     for (int step = 0; step < p->n_steps; ++step) {
         launch_link_update(g, c->links, c->mom, dt, c->s);
+        links_changed(c);
         if ((e = kick(step < p->n_steps - 1 ? dt : 0.5 * dt))) return e;
     }
     // step 3: Metropolis on the rational action
@@ -787,7 +621,10 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         if ((e = reduce_to_host(c, &u))) return e;
     }
     I.accepted = (u < std::exp(-I.dH)) ? 1 : 0;
-    if (!I.accepted) launch_copy(c->links, c->links_backup, lb, c->s);
+    if (!I.accepted) {
+        launch_copy(c->links, c->links_backup, lb, c->s);
+        links_changed(c);
+    }
     if ((e = gauge_action_impl(c, p->beta, nullptr, &I.plaquette))) return e;
     if ((e = leave(c))) return e;
     HIP_OR_FAIL(c, hipStreamSynchronize(c->s));

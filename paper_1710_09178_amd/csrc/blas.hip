@@ -15,21 +15,36 @@ namespace stag {
 
 namespace {
 
-__global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __restrict__ b, double2* __restrict__ r,
-                                                    double2* __restrict__ p, VecPtrs x, VecPtrs ps,
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __restrict__ b, V* __restrict__ r,
+                                                    V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     const MsState* __restrict__ st, double* __restrict__ qout) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const int n = st->n, base = st->base;
     double acc[1] = {0.0};
     if (i < n3) {
         const double2 bv = b[i];
-        r[i] = bv;
-        p[i] = bv;
+        const V bl = from_d2<V>(bv);
+        r[i] = bl;
+        p[i] = bl;
         for (int k = 0; k < n; ++k) {
-            x.p[k][i] = make_double2(0.0, 0.0);
-            if (k != base) ps.p[k][i] = bv;
+            x.at<double2>(k)[i] = make_double2(0.0, 0.0);
+            if (k != base) ps.at<V>(k)[i] = bl;
         }
         acc[0] = bv.x * bv.x + bv.y * bv.y;
+    }
+    block_partial<1>(acc, qout);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cg_restart(int n3, const float2* __restrict__ r, float2* __restrict__ p,
+                                                       double* __restrict__ qout) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double acc[1] = {0.0};
+    if (i < n3) {
+        const float2 rv = r[i];
+        p[i] = rv;
+        const double2 d = to_d2(rv);
+        acc[0] = d.x * d.x + d.y * d.y;
     }
     block_partial<1>(acc, qout);
 }
@@ -41,17 +56,18 @@ __global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __res
 //   beta   = rr_{k+1} / rr_k, zeta', alpha_s, beta_s from the shifted-CG recurrences
 //   r -= alpha Ap; x_base += alpha p; p = r + beta p;
 //   x_s += alpha_s p_s; p_s = zeta_s' r + beta_s p_s      (active shifts)
-__global__ __launch_bounds__(kBlock) void k_ms_step(int n3, double2* __restrict__ r, const double2* __restrict__ Ap,
-                                                    double2* __restrict__ p, VecPtrs x, VecPtrs ps,
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, const V* __restrict__ Ap,
+                                                    V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     MsState* __restrict__ st, const double* __restrict__ dpart,
                                                     int nb2, const double* __restrict__ qin, double* __restrict__ qout,
                                                     int par) {
     if (st->done) return;
     __shared__ double lds[16];
     __shared__ double sh_as[kMaxPoles], sh_bs[kMaxPoles], sh_zn[kMaxPoles];
-    __shared__ int sh_act[kMaxPoles];
+    __shared__ int sh_act[kMaxPoles], sh_list[kMaxPoles];
     __shared__ double sh_alpha, sh_beta;
-    __shared__ int sh_stop;
+    __shared__ int sh_stop, sh_nact;
     const int n = st->n, base = st->base;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int nbq = gridDim.x;  // init and step kernels use the same grid
@@ -66,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, double2* __restrict_
         const MsIter& s = st->it[par];
         const double rr = v[0], pAp = v[1], rAp = v[2], ApAp = v[3];
         const int iter = s.iter;
-        const double bb = (iter == 0) ? rr : s.bb;
+        const double bb = (iter == 0 && !st->bb_given) ? rr : s.bb;
         int nonfinite = !isfinite(rr);
         int any = 0;
         int act[kMaxPoles];
@@ -132,35 +148,61 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, double2* __restrict_
             if (stop) st->done = 1;
         }
     }
+    // compact list of the active shifted poles (the base pole is handled with p)
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int k = 0; k < n; ++k)
+            if (k != base && sh_act[k]) sh_list[m++] = k;
+        sh_nact = m;
+    }
     __syncthreads();
     if (sh_stop) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     const double alpha = sh_alpha, beta = sh_beta;
     double acc[1] = {0.0};
     if (i < n3) {
-        const double2 a = Ap[i];
-        double2 rv = r[i];
+        // r and p in the Krylov precision V, solutions accumulated in FP64
+        const double2 a = to_d2(Ap[i]);
+        double2 rv = to_d2(r[i]);
+        const double2 pv = to_d2(p[i]);
+        const bool base_on = sh_act[base];
+        double2* xb = x.at<double2>(base);
+        double2 xbv = base_on ? xb[i] : make_double2(0.0, 0.0);
         rv.x -= alpha * a.x;
         rv.y -= alpha * a.y;
-        r[i] = rv;
+        const V rl = from_d2<V>(rv);
+        r[i] = rl;
+        rv = to_d2(rl);
         acc[0] = rv.x * rv.x + rv.y * rv.y;
-        const double2 pv = p[i];
-        if (sh_act[base]) {
-            double2 xv = x.p[base][i];
-            xv.x += alpha * pv.x;
-            xv.y += alpha * pv.y;
-            x.p[base][i] = xv;
+        if (base_on) {
+            xbv.x += alpha * pv.x;
+            xbv.y += alpha * pv.y;
+            xb[i] = xbv;
         }
-        p[i] = make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y);
-        for (int k = 0; k < n; ++k) {
-            if (k == base || !sh_act[k]) continue;
-            const double ak = sh_as[k], bk = sh_bs[k], zk = sh_zn[k];
-            const double2 pk = ps.p[k][i];
-            double2 xv = x.p[k][i];
-            xv.x += ak * pk.x;
-            xv.y += ak * pk.y;
-            x.p[k][i] = xv;
-            ps.p[k][i] = make_double2(zk * rv.x + bk * pk.x, zk * rv.y + bk * pk.y);
+        p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
+        // shifted poles in groups: all loads of a group are issued before its
+        // stores (the pointers may not be proven distinct by the compiler)
+        constexpr int G = 4;
+        const int nact = sh_nact;
+        for (int g0 = 0; g0 < nact; g0 += G) {
+            double2 pk[G], xk[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (g0 + j < nact) {
+                    const int k = sh_list[g0 + j];
+                    pk[j] = to_d2(ps.at<V>(k)[i]);
+                    xk[j] = x.at<double2>(k)[i];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                if (g0 + j < nact) {
+                    const int k = sh_list[g0 + j];
+                    const double ak = sh_as[k], bk = sh_bs[k], zk = sh_zn[k];
+                    x.at<double2>(k)[i] = make_double2(xk[j].x + ak * pk[j].x, xk[j].y + ak * pk[j].y);
+                    ps.at<V>(k)[i] = from_d2<V>(make_double2(zk * rv.x + bk * pk[j].x, zk * rv.y + bk * pk[j].y));
+                }
+            }
         }
     }
     block_partial<1>(acc, qout);
@@ -175,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_rational_sum(int n3, const double2* 
     const double c0 = st->c0;
     double2 s = make_double2(c0 * bv.x, c0 * bv.y);
     for (int k = 0; k < st->n; ++k) {
-        const double2 v = x.p[k][i];
+        const double2 v = x.at<double2>(k)[i];
         const double ck = st->coef[k];
         s.x += ck * v.x;
         s.y += ck * v.y;
@@ -192,6 +234,13 @@ __global__ __launch_bounds__(kBlock) void k_dot_re(int n3, const double2* __rest
         acc[0] = u.x * v.x + u.y * v.y;
     }
     block_partial<1>(acc, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize_pad(const double* __restrict__ part, int nb,
+                                                         double* __restrict__ out, int npad) {
+    __shared__ double lds[4];
+    const double t = sum_partials(part, nb, lds);
+    for (int i = threadIdx.x; i < npad; i += kBlock) out[i] = (i == 0) ? t : 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ part, int nb, int K,
@@ -211,14 +260,28 @@ inline int grid3(const Geom& g) { return (3 * g.vh + kBlock - 1) / kBlock; }
 int ms_update_grid(const Geom& g) { return grid3(g); }
 int dot_grid(const Geom& g) { return grid3(g); }
 
-void launch_ms_init(const Geom& g, const double2* b, double2* r, double2* p, VecPtrs x, VecPtrs ps,
-                    const MsState* st, double* qout, hipStream_t s) {
-    k_ms_init<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
+template <class V>
+void launch_ms_init(const Geom& g, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, const MsState* st,
+                    double* qout, hipStream_t s) {
+    k_ms_init<V><<<grid3(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
 }
+template void launch_ms_init<double2>(const Geom&, const double2*, double2*, double2*, VecPtrs, VecPtrs,
+                                      const MsState*, double*, hipStream_t);
+template void launch_ms_init<float2>(const Geom&, const double2*, float2*, float2*, VecPtrs, VecPtrs,
+                                     const MsState*, double*, hipStream_t);
 
-void launch_ms_step(const Geom& g, double2* r, const double2* Ap, double2* p, VecPtrs x, VecPtrs ps, MsState* st,
-                    const double* dpart, int nb2, const double* qin, double* qout, int par, hipStream_t s) {
-    k_ms_step<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin, qout, par);
+template <class V>
+void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
+                    int nb2, const double* qin, double* qout, int par, hipStream_t s) {
+    k_ms_step<V><<<grid3(g), kBlock, 0, s>>>(3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin, qout, par);
+}
+template void launch_ms_step<double2>(const Geom&, double2*, const double2*, double2*, VecPtrs, VecPtrs, MsState*,
+                                      const double*, int, const double*, double*, int, hipStream_t);
+template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2*, VecPtrs, VecPtrs, MsState*,
+                                     const double*, int, const double*, double*, int, hipStream_t);
+
+void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
+    k_cg_restart<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);
 }
 
 void launch_rational_sum(const Geom& g, const double2* b, VecPtrs x, const MsState* st, double2* out,
@@ -228,6 +291,10 @@ void launch_rational_sum(const Geom& g, const double2* b, VecPtrs x, const MsSta
 
 void launch_dot_re(const Geom& g, const double2* a, const double2* b, double* part, hipStream_t s) {
     k_dot_re<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, a, b, part);
+}
+
+void launch_finalize_pad(const double* part, int nb, double* out, int npad, hipStream_t s) {
+    k_finalize_pad<<<1, kBlock, 0, s>>>(part, nb, out, npad);
 }
 
 void launch_finalize(const double* part, int nb, int K, double* out, hipStream_t s) {

@@ -42,6 +42,10 @@ __device__ __forceinline__ int cb_index(const Geom& g, int x, int y, int z, int 
 __host__ __device__ __forceinline__ size_t link_off(const Geom& g, int par, int mu, int e) {
     return ((size_t)((par * 4 + mu) * 9 + e)) * g.vh;
 }
+// compressed links keep rows 0 and 1: [2][4][6][Vh]
+__host__ __device__ __forceinline__ size_t link12_off(const Geom& g, int par, int mu, int e) {
+    return ((size_t)((par * 4 + mu) * 6 + e)) * g.vh;
+}
 __host__ __device__ __forceinline__ size_t mom_off(const Geom& g, int par, int mu, int a) {
     return ((size_t)((par * 4 + mu) * 8 + a)) * g.vh;
 }
@@ -58,6 +62,27 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// float2 versions for the single-precision operator
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// conversions between the vector precisions
+template <class V>
+__device__ __forceinline__ V from_d2(double2 a);
+template <>
+__device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <>
+__device__ __forceinline__ float2 from_d2<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
 
 struct M3 {
     double2 e[9];
@@ -190,6 +215,7 @@ struct MsState {
     double c0;          // rational constant term
     double shift[kMaxPoles];   // pole_k - sigma_0
     double coef[kMaxPoles];    // rational residues
+    int bb_given;       // 1: it[0].bb is set by the host (refinement of a residual)
     // iteration state
     MsIter it[2];
     int done;           // set once by block 0 of the update kernel
@@ -199,7 +225,9 @@ struct MsState {
 
 // Pointer bundles passed by value to kernels.
 struct VecPtrs {
-    double2* p[kMaxPoles];
+    void* p[kMaxPoles];
+    template <class T>
+    __host__ __device__ T* at(int k) const { return (T*)p[k]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -213,33 +241,19 @@ void launch_mom_to_canon(const Geom& g, const double* mom, double* canon, hipStr
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
-// Dslash variants
-void launch_dslash(const Geom& g, const double2* links, const double2* in, double2* out, int out_par,
-                   int tps, hipStream_t s);
-// same, skipped by the whole grid once gate->done is set
-void launch_dslash_gated(const Geom& g, const double2* links, const double2* in, double2* out, int out_par,
-                         int tps, const MsState* gate, hipStream_t s);
-// Ap = (4m^2+sigma0) p - D_eo w_o, and the block partials of <p,Ap>, <r,Ap>, <Ap,Ap>
-void launch_dslash_cg(const Geom& g, const double2* links, const double2* w_o, const double2* p,
-                      const double2* r, double2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s,
-                      double mass_term);
-// out = c*in - D_eo w_o (no reductions)
-void launch_dslash_axpy(const Geom& g, const double2* links, const double2* w_o, const double2* in,
-                        double c, double2* out, int tps, hipStream_t s);
-// block partials of |b - (c x - D_eo w_o)|^2
-void launch_dslash_resid(const Geom& g, const double2* links, const double2* w_o, const double2* x,
-                         const double2* b, double c, double* part, int tps, hipStream_t s);
-int dslash_grid(const Geom& g, int tps);
-
 // Multi-shift CG pieces
 int ms_update_grid(const Geom& g);
-void launch_ms_init(const Geom& g, const double2* b, double2* r, double2* p, VecPtrs x, VecPtrs ps,
-                    const MsState* st, double* qout, hipStream_t s);
+// r = p = p_k = b (in the Krylov precision V), x_k = 0, partials of |b|^2
+template <class V>
+void launch_ms_init(const Geom& g, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, const MsState* st,
+                    double* qout, hipStream_t s);
 // one iteration's scalars (from the partials of the previous kernels) and the
-// fused r, p, x_k, p_k update; par = iteration parity
-void launch_ms_step(const Geom& g, double2* r, const double2* Ap, double2* p, VecPtrs x, VecPtrs ps,
-                    MsState* st, const double* dpart, int nb2, const double* qin, double* qout, int par,
-                    hipStream_t s);
+// fused r, p, x_k, p_k update; par = iteration parity.  x_k stay FP64.
+template <class V>
+void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
+                    int nb2, const double* qin, double* qout, int par, hipStream_t s);
+// p = r and partials of |r|^2 (restart of a CG from a given residual)
+void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s);
 // out = c0 b + sum_k coef_k x_k with c0, coef, n read from st
 void launch_rational_sum(const Geom& g, const double2* b, VecPtrs x, const MsState* st, double2* out,
                          hipStream_t s);
@@ -248,6 +262,8 @@ void launch_dot_re(const Geom& g, const double2* a, const double2* b, double* pa
 int dot_grid(const Geom& g);
 // out[k] = sum_b part[k*nb + b], k < K, in block order (one block)
 void launch_finalize(const double* part, int nb, int K, double* out, hipStream_t s);
+// out[0] = sum of nb partials, out[1..npad) = 0 (a partial array of another grid)
+void launch_finalize_pad(const double* part, int nb, double* out, int npad, hipStream_t s);
 
 // Forces and MD
 void launch_fermion_force(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef,

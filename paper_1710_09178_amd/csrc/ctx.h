@@ -1,0 +1,104 @@
+// The library handle and the host-side helpers shared by abi.hip and solver.hip.
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+#include "dslash.h"
+
+struct stag_ctx {
+    stag::Geom g{};
+    int dims[4]{};
+    int device = 0;
+    hipStream_t user = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t chunk_ev[2]{};
+    // gauge field: FP64 master copy plus copies derived on demand
+    double2* links = nullptr;
+    double2* links_backup = nullptr;
+    double2* links_d12 = nullptr;
+    float2* links_s18 = nullptr;
+    void* links_h12 = nullptr;
+    bool d12_ok = false, s18_ok = false, h12_ok = false;
+    int fmt64 = STAG_LINKS_F64_18;  // storage used by the FP64 operator
+    double* mom = nullptr;
+    // FP64 Krylov workspace
+    double2 *r = nullptr, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
+    double2 *xi = nullptr, *phi = nullptr;
+    // FP32 Krylov workspace (precision form)
+    float2 *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *w32 = nullptr;
+    double2* pool_x = nullptr;   // n_cap even vectors: solutions
+    double2* pool_p = nullptr;   // n_cap even vectors: shifted search directions (FP64 or FP32)
+    double2* pool_y = nullptr;   // n_cap odd vectors: D_oe x_k for the force
+    int n_cap = 0;
+    stag::MsState* st = nullptr;
+    stag::MsState* st_host = nullptr;  // pinned
+    double* dpart = nullptr;             // CG dot partials of the D_eo kernel (3 x blocks)
+    double* qpart[2] = {nullptr, nullptr};  // <r,r> partials, alternating by iteration parity
+    double* gpart = nullptr;             // partials of the other reductions
+    double* scal = nullptr;              // device scalars for reductions
+    double* scal_host = nullptr;         // pinned
+    int* done_host = nullptr;            // pinned [2]
+    bool has_gauge = false;
+    int tps = 2;                         // threads per site in the Dslash
+    int chunk = 16;                      // iterations enqueued between convergence polls
+    // profiling of the solver kernels (hipEvent pairs)
+    int prof_on = 0;
+    std::vector<hipEvent_t> prof_ev;
+    size_t prof_used = 0;
+    double prof_ms[3] = {0, 0, 0};       // D_oe, D_eo + CG epilogue, multi-shift step
+    long prof_cnt[3] = {0, 0, 0};
+    std::string err;
+    int last_iters = 0;
+};
+
+namespace stag {
+
+stag_status fail(stag_ctx* c, stag_status code, const std::string& msg);
+
+#define HIP_OR_FAIL(c, expr)                                                                           \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return ::stag::fail((c), STAG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+stag_status dmalloc(stag_ctx* c, T** p, size_t bytes) {
+    if (hipMalloc((void**)p, bytes) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, STAG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return STAG_OK;
+}
+
+inline size_t half_bytes(const Geom& g) { return (size_t)3 * g.vh * sizeof(double2); }
+inline double2* pool_vec(double2* pool, const Geom& g, int k) { return pool + (size_t)k * 3 * g.vh; }
+
+stag_status ensure_pool(stag_ctx* c, int n);
+// the link copies needed by the FP64 operator and (fmt32 >= 0) the FP32 one, refreshed if stale
+stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls);
+inline void links_changed(stag_ctx* c) { c->d12_ok = c->s18_ok = c->h12_ok = false; }
+
+struct SolveResult {
+    int iters = 0;
+    int nonfinite = 0;
+    int converged = 1;
+    double bb = 0.0;
+};
+
+// FP64 multi-shift CG on A + pole_k; x[k] receive the solutions
+stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter, const double2* b,
+                     double2* const* x, bool want_resid, double* resid_out, int* ipp_out, SolveResult& res);
+// FP32 multi-shift (x_k in FP64) down to opts->tol_sloppy, then per-pole CG in
+// FP32 with FP64 reliable updates every opts->reliable_every iterations until
+// the FP64 true residual of every pole is below tol
+stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
+                           const double2* b, double2* const* x, const stag_mixed_opts* opts, bool want_resid,
+                           double* resid_out, int* ipp_out, SolveResult& res);
+
+}  // namespace stag

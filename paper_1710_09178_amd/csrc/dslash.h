@@ -1,0 +1,47 @@
+// Launchers of the even-odd Dslash for every link storage format.
+#pragma once
+
+#include "common.h"
+
+namespace stag {
+
+// The operator's link copies.  d18 is the master FP64 field; the others are
+// derived from it (rows 0-1 only for the 12-real formats).
+struct LinkSet {
+    int fmt64;               // STAG_LINKS_F64_18 or STAG_LINKS_F64_12
+    int fmt32;               // STAG_LINKS_F32_18 or STAG_LINKS_F16_12
+    const double2* d18;
+    const double2* d12;
+    const float2* s18;
+    const void* h12;         // __half2 [2][4][6][Vh]
+};
+
+int dslash_grid(const Geom& g, int tps);
+
+// FP64 operator (format fmt64)
+void launch_dslash(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int out_par, int tps,
+                   const MsState* gate, hipStream_t s);
+// out = c*in - D_eo w_o
+void launch_dslash_axpy(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* in, double c,
+                        double2* out, int tps, hipStream_t s);
+// Ap = mt p - D_eo w_o and block partials of <p,Ap>, <r,Ap>, <Ap,Ap>
+void launch_dslash_cg(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
+                      double2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mass_term);
+// res = b - (c x - D_eo w_o): block partials of |res|^2; res stored as float2 when r32_out != NULL
+void launch_dslash_resid(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* x, const double2* b,
+                         double c, double* part, int tps, hipStream_t s, float2* r32_out = nullptr);
+
+// FP32 operator (format fmt32)
+void launch_dslash32(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int out_par, int tps,
+                     const MsState* gate, hipStream_t s);
+void launch_dslash32_cg(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* p, const float2* r,
+                        float2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mass_term);
+void launch_dslash32_axpy(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* in, double c,
+                          float2* out, int tps, hipStream_t s);
+
+// link copies derived from the FP64 master field
+void launch_links_to_d12(const Geom& g, const double2* d18, double2* d12, hipStream_t s);
+void launch_links_to_s18(const Geom& g, const double2* d18, float2* s18, hipStream_t s);
+void launch_links_to_h12(const Geom& g, const double2* d18, void* h12, hipStream_t s);
+
+}  // namespace stag

@@ -65,8 +65,8 @@ __global__ __launch_bounds__(kBlock) void k_fermion_force(Geom g, int par, const
 #pragma unroll
         for (int e = 0; e < 9; ++e) W.e[e] = make_double2(0.0, 0.0);
         for (int k = 0; k < n; ++k) {
-            const double2* here = (par == 0 ? X.p[k] : Y.p[k]);
-            const double2* there = (par == 0 ? Y.p[k] : X.p[k]);
+            const double2* here = (par == 0 ? X.at<double2>(k) : Y.at<double2>(k));
+            const double2* there = (par == 0 ? Y.at<double2>(k) : X.at<double2>(k));
             double2 a[3], b[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {

@@ -1,6 +1,9 @@
 // Conversions between the canonical boundary formats and the internal
 // structure-of-arrays layouts, plus fill/copy kernels.
+#include <hip/hip_fp16.h>
+
 #include "common.h"
+#include "dslash.h"
 
 namespace stag {
 
@@ -87,6 +90,36 @@ __global__ void k_copy(uint4* __restrict__ d, const uint4* __restrict__ s, size_
         d[i] = s[i];
 }
 
+// derived link copies: one thread per (parity, mu, site)
+__global__ void k_links_to_d12(Geom g, const double2* __restrict__ d18, double2* __restrict__ d12) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 8 * g.vh) return;
+    const int pm = i / g.vh, cb = i % g.vh;
+    const int par = pm >> 2, mu = pm & 3;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) d12[link12_off(g, par, mu, e) + cb] = d18[link_off(g, par, mu, e) + cb];
+}
+
+__global__ void k_links_to_s18(Geom g, const double2* __restrict__ d18, float2* __restrict__ s18) {
+    const size_t n = (size_t)72 * g.vh;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 v = d18[i];
+        s18[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void k_links_to_h12(Geom g, const double2* __restrict__ d18, __half2* __restrict__ h12) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 8 * g.vh) return;
+    const int pm = i / g.vh, cb = i % g.vh;
+    const int par = pm >> 2, mu = pm & 3;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const double2 v = d18[link_off(g, par, mu, e) + cb];
+        h12[link12_off(g, par, mu, e) + cb] = __floats2half2_rn((float)v.x, (float)v.y);
+    }
+}
+
 inline int blocks_for(size_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -113,6 +146,18 @@ void launch_mom_to_canon(const Geom& g, const double* mom, double* canon, hipStr
     const size_t n = (size_t)8 * g.vh;
     k_mom_to_canon<<<blocks_for(n), 256, 0, s>>>(g, mom, canon);
 }
+void launch_links_to_d12(const Geom& g, const double2* d18, double2* d12, hipStream_t s) {
+    k_links_to_d12<<<blocks_for((size_t)8 * g.vh), 256, 0, s>>>(g, d18, d12);
+}
+void launch_links_to_s18(const Geom& g, const double2* d18, float2* s18, hipStream_t s) {
+    int nb = blocks_for((size_t)72 * g.vh);
+    if (nb > 8192) nb = 8192;
+    k_links_to_s18<<<nb, 256, 0, s>>>(g, d18, s18);
+}
+void launch_links_to_h12(const Geom& g, const double2* d18, void* h12, hipStream_t s) {
+    k_links_to_h12<<<blocks_for((size_t)8 * g.vh), 256, 0, s>>>(g, d18, (__half2*)h12);
+}
+
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
     // every internal buffer is a multiple of 16 bytes
     const size_t n16 = bytes / 16;

@@ -1,0 +1,365 @@
+// Host drivers of the multi-shift CG (Sec. 4, eq. ratapprx) in FP64 and in
+// mixed precision.  The host only enqueues kernels and polls one device flag
+// per chunk of iterations; all scalars of the iteration stay on the GPU.
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+
+#include "ctx.h"
+
+namespace stag {
+
+stag_status fail(stag_ctx* c, stag_status code, const std::string& msg);
+
+stag_status ensure_pool(stag_ctx* c, int n) {
+    if (n <= c->n_cap) return STAG_OK;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    hipFree(c->pool_x);
+    hipFree(c->pool_p);
+    hipFree(c->pool_y);
+    c->pool_x = c->pool_p = c->pool_y = nullptr;
+    c->n_cap = 0;
+    const size_t hb = half_bytes(c->g);
+    stag_status st;
+    if ((st = dmalloc(c, &c->pool_x, hb * n)) != STAG_OK) return st;
+    if ((st = dmalloc(c, &c->pool_p, hb * n)) != STAG_OK) return st;
+    if ((st = dmalloc(c, &c->pool_y, hb * n)) != STAG_OK) return st;
+    c->n_cap = n;
+    return STAG_OK;
+}
+
+stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls) {
+    const Geom& g = c->g;
+    const size_t l12 = (size_t)48 * g.vh;  // complex entries of a 12-real field
+    ls = LinkSet{c->fmt64, fmt32 < 0 ? STAG_LINKS_F32_18 : fmt32, c->links, nullptr, nullptr, nullptr};
+    stag_status e;
+    if (c->fmt64 == STAG_LINKS_F64_12) {
+        if (!c->links_d12 && (e = dmalloc(c, &c->links_d12, l12 * sizeof(double2)))) return e;
+        if (!c->d12_ok) launch_links_to_d12(g, c->links, c->links_d12, c->s);
+        c->d12_ok = true;
+        ls.d12 = c->links_d12;
+    }
+    if (fmt32 == STAG_LINKS_F32_18) {
+        if (!c->links_s18 && (e = dmalloc(c, &c->links_s18, (size_t)72 * g.vh * sizeof(float2)))) return e;
+        if (!c->s18_ok) launch_links_to_s18(g, c->links, c->links_s18, c->s);
+        c->s18_ok = true;
+        ls.s18 = c->links_s18;
+    } else if (fmt32 == STAG_LINKS_F16_12) {
+        if (!c->links_h12 && (e = dmalloc(c, &c->links_h12, l12 * 4))) return e;
+        if (!c->h12_ok) launch_links_to_h12(g, c->links, c->links_h12, c->s);
+        c->h12_ok = true;
+        ls.h12 = c->links_h12;
+    }
+    return STAG_OK;
+}
+
+namespace {
+
+using EvRec = std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>;
+
+void prof_begin(stag_ctx* c, hipEvent_t* a) {
+    *a = nullptr;
+    if (!c->prof_on || c->prof_used + 2 > c->prof_ev.size()) return;
+    *a = c->prof_ev[c->prof_used];
+    hipEventRecord(*a, c->s);
+}
+void prof_end(stag_ctx* c, hipEvent_t a, int kind, EvRec& rec) {
+    if (!a) return;
+    hipEvent_t b = c->prof_ev[c->prof_used + 1];
+    hipEventRecord(b, c->s);
+    c->prof_used += 2;
+    rec.push_back({{a, b}, kind});
+}
+// kernel times of iterations 0..iter (the last one only detects convergence in
+// its step kernel, after full Dslash launches)
+void prof_collect(stag_ctx* c, const EvRec& rec, int iters) {
+    long seen[3] = {0, 0, 0};
+    const long lim[3] = {iters + 1L, iters + 1L, (long)iters};
+    for (auto& q : rec) {
+        const int kind = q.second;
+        if (seen[kind]++ >= lim[kind]) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, q.first.first, q.first.second) == hipSuccess) {
+            c->prof_ms[kind] += ms;
+            c->prof_cnt[kind] += 1;
+        }
+    }
+}
+
+// Krylov workspace and operator of one precision
+template <class V>
+struct Krylov;
+
+template <>
+struct Krylov<double2> {
+    double2 *r, *p, *Ap, *w;
+    explicit Krylov(stag_ctx* c) : r(c->r), p(c->p), Ap(c->Ap), w(c->w_o) {}
+    static void doe(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int tps, const MsState* gate,
+                    hipStream_t s) {
+        launch_dslash(g, ls, in, out, 1, tps, gate, s);
+    }
+    static void deo_cg(const Geom& g, const LinkSet& ls, const double2* w, const double2* p, const double2* r,
+                       double2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mt) {
+        launch_dslash_cg(g, ls, w, p, r, Ap, gate, dpart, tps, s, mt);
+    }
+};
+
+template <>
+struct Krylov<float2> {
+    float2 *r, *p, *Ap, *w;
+    explicit Krylov(stag_ctx* c) : r(c->r32), p(c->p32), Ap(c->Ap32), w(c->w32) {}
+    static void doe(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int tps, const MsState* gate,
+                    hipStream_t s) {
+        launch_dslash32(g, ls, in, out, 1, tps, gate, s);
+    }
+    static void deo_cg(const Geom& g, const LinkSet& ls, const float2* w, const float2* p, const float2* r,
+                       float2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mt) {
+        launch_dslash32_cg(g, ls, w, p, r, Ap, gate, dpart, tps, s, mt);
+    }
+};
+
+// Fill the pinned host copy of the state for a solve with the given poles.
+void init_state(MsState* h, int n, const double* pole, const double* residue, double c0, double mass, double tol,
+                int maxiter, int& base) {
+    base = 0;
+    for (int k = 1; k < n; ++k)
+        if (pole[k] < pole[base]) base = k;
+    const double s0 = pole[base];
+    std::memset(h, 0, sizeof(MsState));
+    h->n = n;
+    h->base = base;
+    h->maxiter = maxiter;
+    h->tol2 = tol * tol;
+    h->mass_term = 4.0 * mass * mass + s0;
+    h->c0 = c0;
+    for (int k = 0; k < n; ++k) {
+        h->shift[k] = pole[k] - s0;
+        h->coef[k] = residue ? residue[k] : 0.0;
+        h->it[0].zeta[k] = h->it[0].zeta_old[k] = 1.0;
+        h->it[0].active[k] = 1;
+    }
+    h->it[0].alpha_old = 1.0;
+    h->it[0].beta_old = 0.0;
+}
+
+// Enqueue iterations in chunks and poll the device "done" flag once per chunk,
+// keeping two chunks in flight.  between_chunks(par_next) may enqueue extra
+// work after every chunk (reliable updates); it receives the parity of the
+// next iteration.
+template <class V, class Between>
+stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtrs X, VecPtrs P, int chunk,
+                           EvRec& rec, Between between_chunks) {
+    const Geom& g = c->g;
+    const double mt = c->st_host->mass_term;
+    const int nb2 = dslash_grid(g, c->tps);
+    int it_issued = 0;
+    auto issue_chunk = [&](int slot) {
+        for (int it = 0; it < chunk; ++it, ++it_issued) {
+            const int par = it_issued & 1;
+            hipEvent_t a;
+            prof_begin(c, &a);
+            Krylov<V>::doe(g, ls, K.p, K.w, c->tps, c->st, c->s);
+            prof_end(c, a, 0, rec);
+            prof_begin(c, &a);
+            Krylov<V>::deo_cg(g, ls, K.w, K.p, K.r, K.Ap, c->st, c->dpart, c->tps, c->s, mt);
+            prof_end(c, a, 1, rec);
+            prof_begin(c, &a);
+            launch_ms_step<V>(g, K.r, K.Ap, K.p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
+                              c->s);
+            prof_end(c, a, 2, rec);
+        }
+        between_chunks(it_issued & 1);
+        hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->s);
+        hipEventRecord(c->chunk_ev[slot], c->s);
+    };
+    issue_chunk(0);
+    issue_chunk(1);
+    int cur = 0;
+    for (;;) {
+        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
+        if (c->done_host[cur]) break;
+        issue_chunk(cur);
+        cur ^= 1;
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    return STAG_OK;
+}
+
+// Multi-shift CG in Krylov precision V (x_k always FP64).
+template <class V>
+stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_rational* r, double tol, int maxiter,
+                       const double2* b, double2* const* x, int* ipp_out, SolveResult& res, EvRec& rec) {
+    const Geom& g = c->g;
+    const int n = r->n;
+    stag_status e = ensure_pool(c, n);
+    if (e != STAG_OK) return e;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));  // st_host is reused
+    MsState* h = c->st_host;
+    int base;
+    init_state(h, n, r->pole, r->residue, r->c0, mass, tol, maxiter, base);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
+    Krylov<V> K(c);
+    VecPtrs X{}, P{};
+    for (int k = 0; k < n; ++k) {
+        X.p[k] = x[k];
+        P.p[k] = (V*)c->pool_p + (size_t)k * 3 * g.vh;
+    }
+    launch_ms_init<V>(g, b, K.r, K.p, X, P, c->st, c->qpart[0], c->s);
+    if ((e = run_iterations<V>(c, ls, K, X, P, c->chunk, rec, [](int) {}))) return e;
+    HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    const MsIter& f = h->fin;
+    res.iters = f.iter;
+    res.nonfinite = f.nonfinite;
+    res.bb = f.bb;
+    res.converged = 1;
+    for (int k = 0; k < n; ++k) {
+        if (f.active[k]) res.converged = 0;
+        if (ipp_out) ipp_out[k] = f.iters_per_pole[k];
+    }
+    return STAG_OK;
+}
+
+// FP64 true residuals |b - (A + pole_k) x_k|^2 into st->true_res2[k]
+void true_residuals(stag_ctx* c, const LinkSet& ls, double mass, const stag_rational* r, const double2* b,
+                    double2* const* x) {
+    const Geom& g = c->g;
+    const int nbr = dslash_grid(g, c->tps);
+    for (int k = 0; k < r->n; ++k) {
+        launch_dslash(g, ls, x[k], c->tmp_o, 1, c->tps, nullptr, c->s);
+        launch_dslash_resid(g, ls, c->tmp_o, x[k], b, 4.0 * mass * mass + r->pole[k], c->gpart, c->tps, c->s);
+        double* slot = (double*)((char*)c->st + offsetof(MsState, true_res2)) + k;
+        launch_finalize(c->gpart, nbr, 1, slot, c->s);
+    }
+}
+
+// CG in FP32 on (A + pole) for one pole, started from the FP64 residual of x
+// (FP64), whose residual is recomputed in FP64 every `every` iterations and
+// copied into the FP32 Krylov residual (reliable update; the search direction
+// is kept).  Returns the iterations run.
+stag_status refine_pole(stag_ctx* c, const LinkSet& ls, double mass, double pole, double tol, int maxiter,
+                        const double2* b, double2* x, double bb, int every, int& iters_out, bool& converged) {
+    const Geom& g = c->g;
+    const int nbr = dslash_grid(g, c->tps);
+    const int nq = ms_update_grid(g);
+    const double coef = 4.0 * mass * mass + pole;
+    Krylov<float2> K(c);
+    iters_out = 0;
+    converged = false;
+    EvRec rec;
+    // reliable update: r32 = b - (A + pole) x computed in FP64, |r|^2 partials for the next step
+    auto reliable = [&](double* qdst) {
+        launch_dslash(g, ls, x, c->tmp_o, 1, c->tps, nullptr, c->s);
+        launch_dslash_resid(g, ls, c->tmp_o, x, b, coef, c->gpart, c->tps, c->s, K.r);
+        launch_finalize_pad(c->gpart, nbr, qdst, nq, c->s);
+    };
+    for (int restart = 0; restart < 8 && iters_out < maxiter; ++restart) {
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+        MsState* h = c->st_host;
+        int base;
+        const double one = 1.0;
+        init_state(h, 1, &pole, &one, 0.0, mass, tol, maxiter - iters_out, base);
+        h->bb_given = 1;
+        h->it[0].bb = bb;
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
+        reliable(c->gpart + 4 * (size_t)nbr);  // r32 from the FP64 residual (partials unused)
+        launch_cg_restart(g, K.r, K.p, c->qpart[0], c->s);
+        VecPtrs X{}, P{};
+        X.p[0] = x;
+        stag_status e = run_iterations<float2>(c, ls, K, X, P, every, rec,
+                                               [&](int par_next) { reliable(c->qpart[par_next]); });
+        if (e) return e;
+        HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+        iters_out += h->fin.iter;
+        if (h->fin.nonfinite) return fail(c, STAG_ERR_NONFINITE, "non-finite value in the refinement CG");
+        // the step kernel may have stopped on a recursive residual: check in FP64
+        launch_dslash(g, ls, x, c->tmp_o, 1, c->tps, nullptr, c->s);
+        launch_dslash_resid(g, ls, c->tmp_o, x, b, coef, c->gpart, c->tps, c->s);
+        launch_finalize(c->gpart, nbr, 1, c->scal, c->s);
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->scal_host, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->s));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+        if (c->scal_host[0] <= tol * tol * bb) {
+            converged = true;
+            break;
+        }
+        if (h->fin.iter == 0) break;  // no progress possible
+    }
+    return STAG_OK;
+}
+
+}  // namespace
+
+stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter, const double2* b,
+                     double2* const* x, bool want_resid, double* resid_out, int* ipp_out, SolveResult& res) {
+    LinkSet ls;
+    stag_status e = get_links(c, -1, ls);
+    if (e) return e;
+    EvRec rec;
+    c->prof_used = 0;
+    if ((e = ms_solve_t<double2>(c, ls, mass, r, tol, maxiter, b, x, ipp_out, res, rec))) return e;
+    prof_collect(c, rec, res.iters);
+    if (want_resid) {
+        true_residuals(c, ls, mass, r, b, x);
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->st_host, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    }
+    for (int k = 0; k < r->n && resid_out; ++k)
+        resid_out[k] = (want_resid && res.bb > 0) ? std::sqrt(c->st_host->true_res2[k] / res.bb) : -1.0;
+    c->last_iters = res.iters;
+    return STAG_OK;
+}
+
+stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
+                           const double2* b, double2* const* x, const stag_mixed_opts* opts, bool want_resid,
+                           double* resid_out, int* ipp_out, SolveResult& res) {
+    LinkSet ls;
+    stag_status e = get_links(c, opts->sloppy, ls);
+    if (e) return e;
+    const Geom& g = c->g;
+    if (!c->r32) {
+        if ((e = dmalloc(c, &c->r32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->p32, half_bytes(g) / 2)) ||
+            (e = dmalloc(c, &c->Ap32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->w32, half_bytes(g) / 2)))
+            return e;
+    }
+    EvRec rec;
+    c->prof_used = 0;
+    int ipp[kMaxPoles];
+    SolveResult r1;
+    // phase 1: FP32 multi-shift to tol_sloppy
+    if ((e = ms_solve_t<float2>(c, ls, mass, r, std::max(opts->tol_sloppy, tol), maxiter, b, x, ipp, r1, rec)))
+        return e;
+    prof_collect(c, rec, r1.iters);
+    if (r1.nonfinite) {
+        res = r1;
+        return STAG_OK;
+    }
+    res.bb = r1.bb;
+    res.iters = r1.iters;
+    res.converged = 1;
+    if (r1.bb > 0) {
+        // phase 2: every pole to the FP64 true residual tol, smallest pole first
+        for (int k = 0; k < r->n; ++k) {
+            int it = 0;
+            bool conv = false;
+            if ((e = refine_pole(c, ls, mass, r->pole[k], tol, std::max(1, maxiter - res.iters), b, x[k], r1.bb,
+                                 std::max(1, opts->reliable_every), it, conv)))
+                return e;
+            ipp[k] += it;
+            res.iters += it;
+            if (!conv) res.converged = 0;
+        }
+    }
+    for (int k = 0; k < r->n && ipp_out; ++k) ipp_out[k] = ipp[k];
+    if (want_resid) {
+        true_residuals(c, ls, mass, r, b, x);
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->st_host, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    }
+    for (int k = 0; k < r->n && resid_out; ++k)
+        resid_out[k] = (want_resid && res.bb > 0) ? std::sqrt(c->st_host->true_res2[k] / res.bb) : -1.0;
+    c->last_iters = res.iters;
+    return STAG_OK;
+}
+
+}  // namespace stag

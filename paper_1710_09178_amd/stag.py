@@ -26,6 +26,7 @@ STAG_ERR_HIP = -6
 STAG_ERR_OOM = -7
 
 FIELD_HALF_VEC, FIELD_MOM, FIELD_CANON_HALF_VEC, FIELD_CANON_GAUGE, FIELD_CANON_MOM = range(5)
+LINKS_F64_18, LINKS_F64_12, LINKS_F32_18, LINKS_F16_12 = range(4)
 MAX_POLES = 48
 
 
@@ -44,6 +45,10 @@ class CSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("n", ctypes.c_int),
                 ("true_resid", ctypes.POINTER(ctypes.c_double)),
                 ("iters_per_pole", ctypes.POINTER(ctypes.c_int)), ("seconds", ctypes.c_double)]
+
+
+class CMixedOpts(ctypes.Structure):
+    _fields_ = [("sloppy", ctypes.c_int), ("tol_sloppy", ctypes.c_double), ("reliable_every", ctypes.c_int)]
 
 
 class CHMCParams(ctypes.Structure):
@@ -93,6 +98,9 @@ def load_library() -> ctypes.CDLL:
         "stag_mdagm": (S, [H, P, P, D]),
         "stag_multishift_solve": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(P), P,
                                       ctypes.POINTER(CSolveInfo)]),
+        "stag_multishift_solve_mixed": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(P), P,
+                                            ctypes.POINTER(CMixedOpts), ctypes.POINTER(CSolveInfo)]),
+        "stag_set_link_format": (S, [H, I]),
         "stag_fermion_action": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(D),
                                     ctypes.POINTER(CSolveInfo)]),
         "stag_fermion_force": (S, [H, D, ctypes.POINTER(CRational), D, I, P, P, D, ctypes.POINTER(CSolveInfo)]),
@@ -237,6 +245,28 @@ class Lattice:
         self._check(code, allow)
         return {"code": code, "iters": info.iters, "seconds": info.seconds,
                 "true_resid": list(resid) if true_resid else None, "iters_per_pole": list(ipp)}
+
+    def multishift_solve_mixed(self, mass, rat, tol, maxiter, b, xs=None, sum_out=None, sloppy=LINKS_F32_18,
+                               tol_sloppy=1e-5, reliable_every=50, true_resid=True, allow_not_converged=False):
+        r = RationalArg(rat)
+        n = r.c.n
+        resid = (ctypes.c_double * n)()
+        ipp = (ctypes.c_int * n)()
+        info = CSolveInfo(0, 0, resid if true_resid else None, ipp, 0.0)
+        xarr = None
+        if xs is not None:
+            xarr = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+        opts = CMixedOpts(int(sloppy), float(tol_sloppy), int(reliable_every))
+        code = self.lib.stag_multishift_solve_mixed(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
+                                                    _ptr(b), xarr, _ptr(sum_out), ctypes.byref(opts),
+                                                    ctypes.byref(info))
+        allow = (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,)
+        self._check(code, allow)
+        return {"code": code, "iters": info.iters, "seconds": info.seconds,
+                "true_resid": list(resid) if true_resid else None, "iters_per_pole": list(ipp)}
+
+    def set_link_format(self, fmt: int):
+        self._check(self.lib.stag_set_link_format(self.h, int(fmt)))
 
     def fermion_action(self, mass, rat, tol, maxiter, phi) -> float:
         r = RationalArg(rat)
