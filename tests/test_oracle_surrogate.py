@@ -1,0 +1,82 @@
+"""Pins for the oracle of the learned force model: the channel basis
+reproduces the gauge force, gauge covariance, finite-difference gradients,
+bfloat16 rounding and Adam."""
+import numpy as np
+
+import synth
+from oracle import gauge, lattice as L, surrogate as S
+from oracle.su3 import to_coords, to_matrix
+
+DIMS = (4, 4, 2, 4)
+
+
+def _U(kind=0, eps=0.6):
+    return synth.random_su3_near_identity(DIMS, eps, synth.make_rng(600, kind))
+
+
+def test_basis_with_constant_coefficients_is_the_gauge_force():
+    """c_j = -beta/3 for every channel gives -(beta/3) Im tr(T_a U sum_j S_j),
+    the Wilson gauge force, because the six channels are the six staples."""
+    U = _U()
+    f, loops = S.features(U, DIMS)
+    B = S.basis(loops)
+    F = np.einsum("nj,nja->na", np.full((B.shape[0], S.N_CH), -5.4 / 3), B)
+    nx, ny, nz, nt = DIMS
+    assert np.abs(F.reshape(nt, nz, ny, nx, 4, 8) - gauge.gauge_force(U, DIMS, 5.4)).max() < 1e-12
+    # each plaquette appears in the loops of its 4 links (real parts of the traces)
+    plaq_sum = gauge.mean_plaquette(U, DIMS) * 3 * 6 * L.volume(DIMS)
+    assert abs(f[:, 0:12:2].sum() - 4 * plaq_sum) < 1e-9
+
+
+def test_model_force_is_gauge_covariant():
+    U = _U(1)
+    rng = synth.make_rng(600, 9)
+    params = S.init_params(rng)
+    params["W3"] = rng.standard_normal(params["W3"].shape)
+    Om = synth.haar_su3(DIMS, rng)[..., 0, :, :]
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Ug[..., mu, :, :] = np.einsum("...ij,...jk,...lk->...il", Om, U[..., mu, :, :], L.fwd(Om, mu).conj())
+    F = S.surrogate_force(params, U, DIMS)
+    Fg = S.surrogate_force(params, Ug, DIMS)
+    rot = to_coords(np.einsum("...ij,...mjk,...lk->...mil", Om, to_matrix(F), Om.conj()))
+    assert np.abs(rot - Fg).max() < 1e-10 * np.abs(F).max()
+
+
+def test_gradients_match_finite_differences():
+    U = _U(2)
+    rng = synth.make_rng(600, 3)
+    params = S.init_params(rng)
+    params["W3"] = rng.standard_normal(params["W3"].shape) * 0.3
+    params["b1"] = rng.standard_normal(S.HID) * 0.1
+    f, loops = S.features(U, DIMS)
+    B = S.basis(loops)
+    target = rng.standard_normal((f.shape[0], 8))
+    _, g = S.loss_and_grad(params, f, B, target)
+    h = 1e-6
+    for key in params:
+        flat = params[key].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(4, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = S.loss_and_grad(params, f, B, target)
+            flat[idx] = old - h
+            lm, _ = S.loss_and_grad(params, f, B, target)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[key].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (key, idx, fd, an)
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 3.140625, 0.1, -2.5, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 65504.0])
+    exp = np.array([1.0, 3.140625, 0.10009765625, -2.5, 1.0, 1.015625, 65536.0])
+    assert np.array_equal(S.bf16(vals), exp)
+
+
+def test_adam_minimises_a_quadratic():
+    params = {"w": np.array([3.0, -2.0])}
+    state = {}
+    for _ in range(2000):
+        S.adam_step(params, {"w": 2 * params["w"]}, state, lr=0.05)
+    assert np.abs(params["w"]).max() < 1e-3
