@@ -239,6 +239,56 @@ typedef struct {
  * field; on rejection the field is restored.  info may be NULL. */
 stag_status stag_md_trajectory(stag_handle h, const stag_hmc_params* p, stag_traj_info* info);
 
+/* ---- batched form: many lattices x right-hand sides x poles ---------------- */
+
+typedef struct stag_batch* stag_batch_handle;
+
+#define STAG_BATCH_MAX_RHS 4
+
+/* A batch of n_inst independent lattices (dims: host int[n_inst][4], each
+ * extent even and >= 2) with nrhs right-hand sides each (1..4).  Every
+ * multi-shift kernel launch covers all tiles of all lattices, and the Dslash
+ * applies each link it loads to all nrhs vectors of its lattice. */
+stag_status stag_batch_create(stag_batch_handle* out, int n_inst, const int* dims, int nrhs, void* hip_stream);
+stag_status stag_batch_destroy(stag_batch_handle b);
+const char* stag_batch_last_error(stag_batch_handle b);
+/* Bytes of one packed canonical batch vector: for lattice i (in order) and
+ * right-hand side j, the canonical even half vector complex128 [Vh_i][3]. */
+size_t stag_batch_vec_bytes(stag_batch_handle b);
+/* Canonical gauge field (device, complex128 [V_i][4][3][3]) of lattice inst. */
+stag_status stag_batch_set_gauge(stag_batch_handle b, int inst, const double* U_canon);
+
+typedef struct {
+    int precision;        /* 0: FP64 links and Krylov vectors; 1: FP32 links and Krylov
+                             vectors (FP64 solutions and reductions) to tol_sloppy, then
+                             FP64 CG refinement of every pole to tol */
+    double tol;           /* per system and pole: |b - (A_i + pole) x| <= tol |b| */
+    double tol_sloppy;    /* precision 1 only */
+    int maxiter;
+    int use_graph;        /* 1: replay chunks of iterations from a captured hipGraph */
+} stag_batch_opts;
+
+typedef struct {
+    int iters;            /* multi-shift iterations until the last system stopped */
+    int refine_iters;     /* precision 1: CG iterations of the refinement (sum over poles) */
+    double seconds;       /* wall time of the call */
+    double* latency;      /* NULL or host [n_inst*nrhs]: seconds from the start of the solve
+                             to the stop of each system (device wall clock) */
+    double* true_resid;   /* NULL or host [n_inst*nrhs*n_poles]: FP64 |b-(A+pole)x|/|b| */
+    int* iters_sys;       /* NULL or host [n_inst*nrhs]: multi-shift iterations per system */
+} stag_batch_info;
+
+/* Solve (A_i + pole_k) x = b for every lattice i (mass masses[i], host
+ * array), right-hand side and pole of r.  b: one packed canonical batch
+ * vector; x: n_poles packed canonical batch vectors one after the other (pole
+ * k at byte offset k * stag_batch_vec_bytes).  Both device pointers. */
+stag_status stag_batch_solve(stag_batch_handle b, const double* masses, const stag_rational* r, const void* b_canon,
+                             void* x_canon, const stag_batch_opts* opts, stag_batch_info* info);
+/* Autotune the Dslash work split for this batch: times the batched operator
+ * for 1, 2 and 4 threads per site (precision 0 or 1) and keeps the fastest.
+ * us_out: NULL or host [3] microseconds per application. */
+stag_status stag_batch_tune(stag_batch_handle b, int precision, double* us_out);
+
 /* ---- measurement and tuning (not part of the method) ---------------------- */
 
 /* Record a pair of hipEvents around each Dslash and shift-update launch of the

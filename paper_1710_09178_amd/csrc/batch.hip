@@ -1,0 +1,593 @@
+// Batched multi-shift CG kernels: every launch covers all tiles of all
+// lattices of the batch, and each Dslash thread applies the links it loads to
+// every right-hand side of its lattice (links read once per nrhs vectors).
+// Scalars are per system (lattice, right-hand side); reductions are per tile
+// and are summed over the lattice's tiles by the consuming kernel.
+#include "batch.h"
+
+namespace stag {
+
+namespace {
+
+template <class V>
+struct BPrec;
+template <>
+struct BPrec<double2> {
+    using R = double;
+};
+template <>
+struct BPrec<float2> {
+    using R = float;
+};
+
+__device__ __forceinline__ void bhop_geometry(const Geom& g, int mu, int x, int y, int z, int t, int& cbf, int& cbb,
+                                              bool& nf, bool& nb) {
+    if (mu == 0) {
+        cbf = cb_index(g, (x + 1 == g.nx) ? 0 : x + 1, y, z, t);
+        cbb = cb_index(g, (x == 0) ? g.nx - 1 : x - 1, y, z, t);
+        nf = nb = false;
+    } else if (mu == 1) {
+        cbf = cb_index(g, x, (y + 1 == g.ny) ? 0 : y + 1, z, t);
+        cbb = cb_index(g, x, (y == 0) ? g.ny - 1 : y - 1, z, t);
+        nf = nb = (x & 1);
+    } else if (mu == 2) {
+        cbf = cb_index(g, x, y, (z + 1 == g.nz) ? 0 : z + 1, t);
+        cbb = cb_index(g, x, y, (z == 0) ? g.nz - 1 : z - 1, t);
+        nf = nb = ((x + y) & 1);
+    } else {
+        cbf = cb_index(g, x, y, z, (t + 1 == g.nt) ? 0 : t + 1);
+        cbb = cb_index(g, x, y, z, (t == 0) ? g.nt - 1 : t - 1);
+        const bool eta = ((x + y + z) & 1);
+        nf = eta ^ (t == g.nt - 1);
+        nb = eta ^ (t == 0);
+    }
+}
+
+// ---- epilogues over (rhs, colour, site) items of one tile
+template <class V>
+struct BEpiStore {
+    static constexpr int K = 1;
+    V* out;
+    __device__ void item(const BInst& I, int, int R, int rh, int site, int c, V v, double*) const {
+        out[bvec_off(I, R, rh, c) + site] = v;
+    }
+    __device__ void finish(int, double*) const {}
+};
+
+// Ap = (4 m_i^2 + sigma_0) p - v and per-rhs partials of <p,Ap>, <r,Ap>, <Ap,Ap>
+template <class V>
+struct BEpiCG {
+    static constexpr int K = 3 * kMaxRhs;
+    V* Ap;
+    const V* p;
+    const V* r;
+    const double* sigma0_term;  // [inst] 4 m_i^2 + sigma_0
+    double* part;  // [tile][kMaxRhs][3]
+    __device__ void item(const BInst& I, int inst, int R, int rh, int site, int c, V v, double* acc) const {
+        const size_t i = bvec_off(I, R, rh, c) + site;
+        const V pv = p[i], rv = r[i];
+        using Rl = typename BPrec<V>::R;
+        const Rl m = (Rl)sigma0_term[inst];
+        const V a = V{m * pv.x - v.x, m * pv.y - v.y};
+        Ap[i] = a;
+        const double2 pd = to_d2(pv), rd = to_d2(rv), ad = to_d2(a);
+        const double d0 = pd.x * ad.x + pd.y * ad.y, d1 = rd.x * ad.x + rd.y * ad.y, d2 = ad.x * ad.x + ad.y * ad.y;
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)  // predicated: no dynamic register indexing
+            if (q == rh) {
+                acc[3 * q + 0] += d0;
+                acc[3 * q + 1] += d1;
+                acc[3 * q + 2] += d2;
+            }
+    }
+    __device__ void finish(int tile, double* acc) const {
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = acc[k];
+        __shared__ double lds[4 * K];
+        block_sum<K>(v, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < K; ++k) part[(size_t)tile * K + k] = v[k];
+    }
+};
+
+// FP64 residual b - ((4 m_i^2 + pole) x - v): per-rhs partials of |res|^2
+struct BEpiResid {
+    static constexpr int K = kMaxRhs;
+    const double2* x;
+    const double2* b;
+    double2* rout;
+    double pole;
+    double* part;  // [tile][kMaxRhs]
+    __device__ void item(const BInst& I, int, int R, int rh, int site, int c, double2 v, double* acc) const {
+        const size_t i = bvec_off(I, R, rh, c) + site;
+        const double coef = I.four_m2 + pole;
+        const double2 xv = x[i], bv = b[i];
+        const double rx = bv.x - (coef * xv.x - v.x), ry = bv.y - (coef * xv.y - v.y);
+        if (rout) rout[i] = make_double2(rx, ry);
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (q == rh) acc[q] += rx * rx + ry * ry;
+    }
+    __device__ void finish(int tile, double* acc) const {
+        double v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = acc[k];
+        __shared__ double lds[4 * K];
+        block_sum<K>(v, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < K; ++k) part[(size_t)tile * K + k] = v[k];
+    }
+};
+
+// One block per tile: TPS threads per site split the 4 directions; every
+// thread applies its links to all right-hand sides of the lattice.
+template <int TPS, class V, class Epi>
+__global__ __launch_bounds__(kBlock) void k_bdslash(BatchDev bd, const V* __restrict__ links, const V* __restrict__ in,
+                                                    int out_par, Epi epi, const int* __restrict__ inst_done) {
+    constexpr int SB = kBlock / TPS;
+    constexpr int DPT = 4 / TPS;
+    using Rl = typename BPrec<V>::R;
+    const BTile tl = bd.tiles[blockIdx.x];
+    if (inst_done && inst_done[tl.inst]) return;
+    const BInst I = bd.inst[tl.inst];
+    const Geom& g = I.g;
+    const int R = bd.nrhs;
+    __shared__ V part[TPS * kMaxRhs * 3 * SB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slice = wave % TPS, sgrp = wave / TPS;
+    const int j = sgrp * 64 + lane;
+    const int cb = tl.cb0 + j;
+    V acc[kMaxRhs][3];
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][c] = V{0, 0};
+    const V* lk = links + blink_base(I);
+    if (cb < g.vh) {
+        int x, y, z, t;
+        cb_coords(g, out_par, cb, x, y, z, t);
+#pragma unroll
+        for (int d = 0; d < DPT; ++d) {
+            const int mu = slice * DPT + d;
+            int cbf, cbb;
+            bool nf, nb;
+            bhop_geometry(g, mu, x, y, z, t, cbf, cbb, nf, nb);
+            V U[9], W[9];
+            const V* uf = lk + link_off(g, out_par, mu, 0) + cb;
+            const V* ub = lk + link_off(g, 1 - out_par, mu, 0) + cbb;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) U[e] = uf[(size_t)e * g.vh];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) W[e] = ub[(size_t)e * g.vh];
+            const Rl sf = nf ? Rl(-1) : Rl(1);
+            const Rl sb = nb ? Rl(-1) : Rl(1);
+#pragma unroll
+            for (int r = 0; r < kMaxRhs; ++r) {
+                if (r >= R) break;
+                V pf[3], pb[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pf[c] = in[bvec_off(I, R, r, c) + cbf];
+                    pb[c] = in[bvec_off(I, R, r, c) + cbb];
+                }
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    V f = cmul(U[3 * a], pf[0]);
+                    f = cadd(f, cmul(U[3 * a + 1], pf[1]));
+                    f = cadd(f, cmul(U[3 * a + 2], pf[2]));
+                    V bb = cmulc(W[a], pb[0]);
+                    bb = cadd(bb, cmulc(W[3 + a], pb[1]));
+                    bb = cadd(bb, cmulc(W[6 + a], pb[2]));
+                    acc[r][a].x += sf * f.x - sb * bb.x;
+                    acc[r][a].y += sf * f.y - sb * bb.y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (r < R) part[((slice * kMaxRhs + r) * 3 + c) * SB + j] = acc[r][c];
+    __syncthreads();
+    double racc[Epi::K];
+#pragma unroll
+    for (int k = 0; k < Epi::K; ++k) racc[k] = 0.0;
+    for (int it = threadIdx.x; it < R * 3 * SB; it += kBlock) {
+        const int rh = it / (3 * SB), c = (it / SB) % 3, jj = it % SB;
+        const int site = tl.cb0 + jj;
+        if (site >= g.vh) continue;
+        V v = part[((0 * kMaxRhs + rh) * 3 + c) * SB + jj];
+#pragma unroll
+        for (int s = 1; s < TPS; ++s) v = cadd(v, part[((s * kMaxRhs + rh) * 3 + c) * SB + jj]);
+        epi.item(I, tl.inst, R, rh, site, c, v, racc);
+    }
+    epi.finish(blockIdx.x, racc);
+}
+
+template <class V, class Epi>
+void bdslash_tps(const BatchDev& bd, int tps, const V* links, const V* in, int out_par, const Epi& epi,
+                 const int* inst_done, hipStream_t s) {
+    switch (tps) {
+        case 1: k_bdslash<1, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+        case 2: k_bdslash<2, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+        default: k_bdslash<4, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+    }
+}
+
+// r = p = p_k = b, x_k = 0, per-rhs partials of |b|^2
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_bms_init(BatchDev bd, const double2* __restrict__ b, V* __restrict__ r,
+                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
+                                                     BState st, double* __restrict__ qout) {
+    const BTile tl = bd.tiles[blockIdx.x];
+    const BInst I = bd.inst[tl.inst];
+    const int R = bd.nrhs, SB = bd.tile_sites;
+    const int n = st.n, base = st.base;
+    double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+    for (int it = threadIdx.x; it < R * 3 * SB; it += kBlock) {
+        const int rh = it / (3 * SB), c = (it / SB) % 3, jj = it % SB;
+        const int site = tl.cb0 + jj;
+        if (site >= I.g.vh) continue;
+        const size_t i = bvec_off(I, R, rh, c) + site;
+        const double2 bv = b[i];
+        const V bl = from_d2<V>(bv);
+        r[i] = bl;
+        p[i] = bl;
+        for (int k = 0; k < n; ++k) {
+            x.at<double2>(k)[i] = make_double2(0.0, 0.0);
+            if (k != base) ps.at<V>(k)[i] = bl;
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (q == rh) acc[q] += bv.x * bv.x + bv.y * bv.y;
+    }
+    __shared__ double lds[4 * kMaxRhs];
+    block_sum<kMaxRhs>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kMaxRhs; ++q) qout[(size_t)blockIdx.x * kMaxRhs + q] = acc[q];
+}
+
+// Scalars of system s from this iteration's sums (one thread per system).
+// Writes the per-rhs LDS tables; block `writer` also stores the next state.
+struct BScal {
+    double alpha, beta;
+    int stop, nact;
+    int list[kMaxPoles];
+    double as[kMaxPoles], bs[kMaxPoles], zn[kMaxPoles];
+    int base_on;
+};
+
+__device__ void bsystem_scalars(BState& st, int s, int par, double rr, double pAp, double rAp, double ApAp,
+                                bool writer, BScal& o) {
+    const int n = st.n, base = st.base;
+    const MsIter& S = st.it[par][s];
+    const int iter = S.iter;
+    const double bb = (iter == 0 && !st.bb_given) ? rr : S.bb;
+    int nonfinite = !isfinite(rr);
+    int act[kMaxPoles];
+    int any = 0;
+    for (int k = 0; k < n; ++k) {
+        act[k] = S.active[k];
+        if (act[k] && S.zeta[k] * S.zeta[k] * rr <= st.tol2 * bb) act[k] = 0;
+        any |= act[k];
+    }
+    int stop = nonfinite || !any || iter >= st.maxiter;
+    double alpha = 0.0, beta = 0.0;
+    double zn[kMaxPoles];
+    if (!stop) {
+        alpha = rr / pAp;
+        double rr1 = rr - 2.0 * alpha * rAp + alpha * alpha * ApAp;
+        if (rr1 < 0.0) rr1 = 0.0;
+        beta = rr1 / rr;
+        const double a_old = S.alpha_old, b_old = S.beta_old;
+        for (int k = 0; k < n; ++k) {
+            const double z = S.zeta[k], zo = S.zeta_old[k];
+            if (k == base) {
+                zn[k] = 1.0;
+                o.as[k] = alpha;
+                o.bs[k] = beta;
+            } else if (!act[k]) {
+                zn[k] = z;
+                o.as[k] = o.bs[k] = 0.0;
+            } else {
+                const double znk = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st.shift[k] * alpha));
+                const double q = znk / z;
+                zn[k] = znk;
+                o.as[k] = alpha * q;
+                o.bs[k] = beta * q * q;
+            }
+        }
+        if (!isfinite(alpha) || !isfinite(beta)) {
+            nonfinite = 1;
+            stop = 1;
+        }
+    }
+    o.alpha = alpha;
+    o.beta = beta;
+    o.stop = stop;
+    o.base_on = act[base] && !stop;
+    int m = 0;
+    for (int k = 0; k < n; ++k) {
+        o.zn[k] = zn[k];
+        if (k != base && act[k]) o.list[m++] = k;
+    }
+    o.nact = stop ? 0 : m;
+    if (writer) {
+        MsIter& N = stop ? st.fin[s] : st.it[par ^ 1][s];
+        for (int k = 0; k < n; ++k) {
+            N.active[k] = act[k];
+            N.iters_per_pole[k] = (act[k] && !stop) ? iter + 1 : (S.active[k] ? iter : S.iters_per_pole[k]);
+            N.zeta[k] = stop ? S.zeta[k] : zn[k];
+            N.zeta_old[k] = stop ? S.zeta_old[k] : S.zeta[k];
+        }
+        N.alpha_old = stop ? S.alpha_old : alpha;
+        N.beta_old = stop ? S.beta_old : beta;
+        N.bb = bb;
+        N.rr = rr;
+        N.iter = stop ? iter : iter + 1;
+        N.nonfinite = nonfinite;
+        if (stop) {
+            st.sys_done[s] = 1;
+            st.t_done[s] = wall_clock64();
+        }
+    }
+}
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict__ r, const V* __restrict__ Ap,
+                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps, BState st,
+                                                     const double* __restrict__ dpart, const double* __restrict__ qin,
+                                                     double* __restrict__ qout, int par) {
+    const BTile tl = bd.tiles[blockIdx.x];
+    if (st.inst_done[tl.inst]) return;
+    const BInst I = bd.inst[tl.inst];
+    const int R = bd.nrhs, SB = bd.tile_sites;
+    __shared__ BScal sc[kMaxRhs];
+    __shared__ double lds[4 * 4 * kMaxRhs];
+    // sums over the lattice's tiles: [rhs] rr, [rhs][3] dots
+    double v[4 * kMaxRhs];
+#pragma unroll
+    for (int k = 0; k < 4 * kMaxRhs; ++k) v[k] = 0.0;
+    for (int t = I.tile0 + threadIdx.x; t < I.tile0 + I.ntiles; t += kBlock) {
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q) {
+            v[4 * q + 0] += qin[(size_t)t * kMaxRhs + q];
+            v[4 * q + 1] += dpart[(size_t)t * 3 * kMaxRhs + 3 * q + 0];
+            v[4 * q + 2] += dpart[(size_t)t * 3 * kMaxRhs + 3 * q + 1];
+            v[4 * q + 3] += dpart[(size_t)t * 3 * kMaxRhs + 3 * q + 2];
+        }
+    }
+    block_sum<4 * kMaxRhs>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4 * kMaxRhs; ++k) lds[k] = v[k];
+    }
+    __syncthreads();
+    const bool writer = (blockIdx.x == I.tile0);
+    if (threadIdx.x < R) {
+        const int q = threadIdx.x;
+        const int s = tl.inst * R + q;
+        if (st.sys_done[s]) {
+            sc[q].stop = 1;
+            sc[q].nact = 0;
+            sc[q].base_on = 0;
+        } else {
+            bsystem_scalars(st, s, par, lds[4 * q], lds[4 * q + 1], lds[4 * q + 2], lds[4 * q + 3], writer, sc[q]);
+        }
+    }
+    __syncthreads();
+    if (writer && threadIdx.x == 0) {
+        int all = 1;
+        for (int q = 0; q < R; ++q) all &= (st.sys_done[tl.inst * R + q] | sc[q].stop);
+        if (all) st.inst_done[tl.inst] = 1;
+    }
+    double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
+    const int base = st.base;
+    for (int it = threadIdx.x; it < R * 3 * SB; it += kBlock) {
+        const int rh = it / (3 * SB), c = (it / SB) % 3, jj = it % SB;
+        const int site = tl.cb0 + jj;
+        if (site >= I.g.vh) continue;
+        const BScal& S = sc[rh];
+        if (S.stop) continue;
+        const size_t i = bvec_off(I, R, rh, c) + site;
+        const double alpha = S.alpha, beta = S.beta;
+        const double2 a = to_d2(Ap[i]);
+        double2 rv = to_d2(r[i]);
+        const double2 pv = to_d2(p[i]);
+        rv.x -= alpha * a.x;
+        rv.y -= alpha * a.y;
+        const V rl = from_d2<V>(rv);
+        r[i] = rl;
+        rv = to_d2(rl);
+#pragma unroll
+        for (int q = 0; q < kMaxRhs; ++q)
+            if (q == rh) acc[q] += rv.x * rv.x + rv.y * rv.y;
+        if (S.base_on) {
+            double2* xb = x.at<double2>(base);
+            double2 xv = xb[i];
+            xb[i] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+        }
+        p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
+        constexpr int G = 4;
+        for (int g0 = 0; g0 < S.nact; g0 += G) {
+            double2 pk[G], xk[G];
+#pragma unroll
+            for (int jq = 0; jq < G; ++jq)
+                if (g0 + jq < S.nact) {
+                    const int k = S.list[g0 + jq];
+                    pk[jq] = to_d2(ps.at<V>(k)[i]);
+                    xk[jq] = x.at<double2>(k)[i];
+                }
+#pragma unroll
+            for (int jq = 0; jq < G; ++jq)
+                if (g0 + jq < S.nact) {
+                    const int k = S.list[g0 + jq];
+                    x.at<double2>(k)[i] = make_double2(xk[jq].x + S.as[k] * pk[jq].x, xk[jq].y + S.as[k] * pk[jq].y);
+                    ps.at<V>(k)[i] = from_d2<V>(make_double2(S.zn[k] * rv.x + S.bs[k] * pk[jq].x,
+                                                              S.zn[k] * rv.y + S.bs[k] * pk[jq].y));
+                }
+        }
+    }
+    block_sum<kMaxRhs>(acc, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kMaxRhs; ++q) qout[(size_t)blockIdx.x * kMaxRhs + q] = acc[q];
+}
+
+__global__ void k_bsys_sum(BatchDev bd, int n_inst, const double* __restrict__ part, double* __restrict__ out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int R = bd.nrhs;
+    if (s >= n_inst * R) return;
+    const BInst I = bd.inst[s / R];
+    const int q = s % R;
+    double t = 0.0;
+    for (int k = 0; k < I.ntiles; ++k) t += part[(size_t)(I.tile0 + k) * kMaxRhs + q];
+    out[s] = t;
+}
+
+// canonical packed [inst][rhs][site][colour] <-> internal [inst][rhs][colour][site]
+__global__ void k_bvec_import(BatchDev bd, const double2* __restrict__ canon, double2* __restrict__ vec) {
+    const BTile tl = bd.tiles[blockIdx.x];
+    const BInst I = bd.inst[tl.inst];
+    const int R = bd.nrhs, SB = bd.tile_sites;
+    for (int it = threadIdx.x; it < R * SB; it += blockDim.x) {
+        const int rh = it / SB, site = tl.cb0 + it % SB;
+        if (site >= I.g.vh) continue;
+        const size_t cbase = (size_t)3 * ((size_t)R * I.off + (size_t)rh * I.g.vh + site);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vec[bvec_off(I, R, rh, c) + site] = canon[cbase + c];
+    }
+}
+
+__global__ void k_bvec_export(BatchDev bd, const double2* __restrict__ vec, double2* __restrict__ canon) {
+    const BTile tl = bd.tiles[blockIdx.x];
+    const BInst I = bd.inst[tl.inst];
+    const int R = bd.nrhs, SB = bd.tile_sites;
+    for (int it = threadIdx.x; it < R * SB; it += blockDim.x) {
+        const int rh = it / SB, site = tl.cb0 + it % SB;
+        if (site >= I.g.vh) continue;
+        const size_t cbase = (size_t)3 * ((size_t)R * I.off + (size_t)rh * I.g.vh + site);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) canon[cbase + c] = vec[bvec_off(I, R, rh, c) + site];
+    }
+}
+
+__global__ void k_blinks_to_f32(const double2* __restrict__ d, float2* __restrict__ f, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 v = d[i];
+        f[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void k_bstate_init(BState st, int from_fin) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nsys = st.n_inst * st.nrhs;
+    if (s >= nsys) return;
+    MsIter& S = st.it[0][s];
+    for (int k = 0; k < st.n; ++k) {
+        S.zeta[k] = S.zeta_old[k] = 1.0;
+        S.active[k] = 1;
+        S.iters_per_pole[k] = 0;
+    }
+    S.alpha_old = 1.0;
+    S.beta_old = 0.0;
+    S.bb = from_fin ? st.fin[s].bb : 0.0;
+    S.rr = 0.0;
+    S.iter = 0;
+    S.nonfinite = 0;
+    st.sys_done[s] = 0;
+    st.t_done[s] = 0;
+    if (s % st.nrhs == 0) st.inst_done[s / st.nrhs] = 0;
+}
+
+__global__ void k_baxpy(size_t n, double2* __restrict__ x, const double2* __restrict__ e) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 a = x[i], b = e[i];
+        x[i] = make_double2(a.x + b.x, a.y + b.y);
+    }
+}
+
+__global__ void k_timestamp(unsigned long long* t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) t[0] = wall_clock64();
+}
+
+}  // namespace
+
+template <class V>
+void launch_bdslash(const BatchDev& bd, int tps, const void* links, const V* in, V* out, int out_par,
+                    const int* inst_done, hipStream_t s) {
+    bdslash_tps<V>(bd, tps, (const V*)links, in, out_par, BEpiStore<V>{out}, inst_done, s);
+}
+template void launch_bdslash<double2>(const BatchDev&, int, const void*, const double2*, double2*, int, const int*,
+                                      hipStream_t);
+template void launch_bdslash<float2>(const BatchDev&, int, const void*, const float2*, float2*, int, const int*,
+                                     hipStream_t);
+
+template <class V>
+void launch_bdslash_cg(const BatchDev& bd, int tps, const void* links, const V* w_o, const V* p, const V* r, V* Ap,
+                       BState st, double* dpart, hipStream_t s) {
+    bdslash_tps<V>(bd, tps, (const V*)links, w_o, 0, BEpiCG<V>{Ap, p, r, st.sigma0_term, dpart}, st.inst_done, s);
+}
+template void launch_bdslash_cg<double2>(const BatchDev&, int, const void*, const double2*, const double2*,
+                                         const double2*, double2*, BState, double*, hipStream_t);
+template void launch_bdslash_cg<float2>(const BatchDev&, int, const void*, const float2*, const float2*, const float2*,
+                                        float2*, BState, double*, hipStream_t);
+
+void launch_bdslash_resid(const BatchDev& bd, int tps, const double2* links, const double2* w_o, const double2* x,
+                          const double2* b, double pole, double* part, double2* rout, hipStream_t s) {
+    bdslash_tps<double2>(bd, tps, links, w_o, 0, BEpiResid{x, b, rout, pole, part}, nullptr, s);
+}
+
+template <class V>
+void launch_bms_init(const BatchDev& bd, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, BState st,
+                     double* qout, hipStream_t s) {
+    k_bms_init<V><<<bd.ntiles, kBlock, 0, s>>>(bd, b, r, p, x, ps, st, qout);
+}
+template void launch_bms_init<double2>(const BatchDev&, const double2*, double2*, double2*, VecPtrs, VecPtrs,
+                                       BState, double*, hipStream_t);
+template void launch_bms_init<float2>(const BatchDev&, const double2*, float2*, float2*, VecPtrs, VecPtrs,
+                                      BState, double*, hipStream_t);
+
+template <class V>
+void launch_bms_step(const BatchDev& bd, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, BState st,
+                     const double* dpart, const double* qin, double* qout, int par, hipStream_t s) {
+    k_bms_step<V><<<bd.ntiles, kBlock, 0, s>>>(bd, r, Ap, p, x, ps, st, dpart, qin, qout, par);
+}
+template void launch_bms_step<double2>(const BatchDev&, double2*, const double2*, double2*, VecPtrs, VecPtrs, BState,
+                                       const double*, const double*, double*, int, hipStream_t);
+template void launch_bms_step<float2>(const BatchDev&, float2*, const float2*, float2*, VecPtrs, VecPtrs, BState,
+                                      const double*, const double*, double*, int, hipStream_t);
+
+void launch_bsys_sum(const BatchDev& bd, int n_inst, const double* part, double* out, hipStream_t s) {
+    const int n = n_inst * bd.nrhs;
+    k_bsys_sum<<<(n + 255) / 256, 256, 0, s>>>(bd, n_inst, part, out);
+}
+
+void launch_bvec_import(const BatchDev& bd, const double2* canon, double2* vec, hipStream_t s) {
+    k_bvec_import<<<bd.ntiles, kBlock, 0, s>>>(bd, canon, vec);
+}
+void launch_bvec_export(const BatchDev& bd, const double2* vec, double2* canon, hipStream_t s) {
+    k_bvec_export<<<bd.ntiles, kBlock, 0, s>>>(bd, vec, canon);
+}
+void launch_blinks_to_f32(const double2* d, float2* f, size_t n, hipStream_t s) {
+    int nb = (int)((n + 255) / 256);
+    if (nb > 8192) nb = 8192;
+    k_blinks_to_f32<<<nb, 256, 0, s>>>(d, f, n);
+}
+void launch_b_timestamp(unsigned long long* t, hipStream_t s) { k_timestamp<<<1, 64, 0, s>>>(t); }
+
+void launch_bstate_init(BState st, int from_fin, hipStream_t s) {
+    const int n = st.n_inst * st.nrhs;
+    k_bstate_init<<<(n + 255) / 256, 256, 0, s>>>(st, from_fin);
+}
+
+void launch_baxpy(size_t n, double2* x, const double2* e, hipStream_t s) {
+    int nb = (int)((n + 255) / 256);
+    if (nb > 8192) nb = 8192;
+    k_baxpy<<<nb, 256, 0, s>>>(n, x, e);
+}
+
+}  // namespace stag

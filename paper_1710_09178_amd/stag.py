@@ -67,6 +67,17 @@ class CTrajInfo(ctypes.Structure):
                 ("cg_iters_total", ctypes.c_int), ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double)]
 
 
+class CBatchOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("tol_sloppy", ctypes.c_double),
+                ("maxiter", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+
+class CBatchInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("refine_iters", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("latency", ctypes.POINTER(ctypes.c_double)), ("true_resid", ctypes.POINTER(ctypes.c_double)),
+                ("iters_sys", ctypes.POINTER(ctypes.c_int))]
+
+
 _lib = None
 
 
@@ -113,6 +124,14 @@ def load_library() -> ctypes.CDLL:
         "stag_philox": (S, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32), ctypes.c_size_t,
                             P, P]),
         "stag_md_trajectory": (S, [H, ctypes.POINTER(CHMCParams), ctypes.POINTER(CTrajInfo)]),
+        "stag_batch_create": (S, [ctypes.POINTER(H), ctypes.POINTER(ctypes.c_int), I, I, P]),
+        "stag_batch_destroy": (S, [H]),
+        "stag_batch_last_error": (ctypes.c_char_p, [H]),
+        "stag_batch_vec_bytes": (ctypes.c_size_t, [H]),
+        "stag_batch_set_gauge": (S, [H, I, P]),
+        "stag_batch_solve": (S, [H, ctypes.POINTER(D), ctypes.POINTER(CRational), P, P, ctypes.POINTER(CBatchOpts),
+                                 ctypes.POINTER(CBatchInfo)]),
+        "stag_batch_tune": (S, [H, I, ctypes.POINTER(D)]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
         "stag_tune": (S, [H, I, I]),
@@ -343,3 +362,65 @@ def philox(ctr, key, n: int) -> torch.Tensor:
     if code != STAG_OK:
         raise StagError(code, lib.stag_last_error(None).decode())
     return out
+
+
+class Batch:
+    """A libstag batch: many lattices x right-hand sides, solved together."""
+
+    def __init__(self, dims_list, nrhs: int, stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.dims = [tuple(int(v) for v in d) for d in dims_list]
+        self.nrhs = int(nrhs)
+        self.stream = stream or torch.cuda.current_stream()
+        flat = (ctypes.c_int * (4 * len(self.dims)))(*[v for d in self.dims for v in d])
+        h = ctypes.c_void_p()
+        code = self.lib.stag_batch_create(ctypes.byref(h), flat, len(self.dims), self.nrhs,
+                                          ctypes.c_void_p(self.stream.cuda_stream))
+        if code != STAG_OK:
+            raise StagError(code, self.lib.stag_batch_last_error(None).decode())
+        self.h = h
+        self.vh = [d[0] * d[1] * d[2] * d[3] // 2 for d in self.dims]
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.stag_batch_destroy(h)
+            self.h = None
+
+    def _check(self, code, allow=(STAG_OK,)):
+        if code not in allow:
+            raise StagError(code, self.lib.stag_batch_last_error(self.h).decode())
+        return code
+
+    def vec_len(self) -> int:
+        """complex entries of one packed canonical batch vector"""
+        return int(self.lib.stag_batch_vec_bytes(self.h)) // 16
+
+    def set_gauge(self, inst: int, U: torch.Tensor):
+        self._check(self.lib.stag_batch_set_gauge(self.h, int(inst), _ptr(U)))
+
+    def solve(self, masses, rat, b: torch.Tensor, precision=0, tol=1e-10, tol_sloppy=1e-5, maxiter=100000,
+              use_graph=True, true_resid=True, allow_not_converged=False):
+        r = RationalArg(rat)
+        n = r.c.n
+        nsys = len(self.dims) * self.nrhs
+        m = (ctypes.c_double * len(self.dims))(*[float(v) for v in masses])
+        x = torch.empty(n * self.vec_len(), dtype=torch.complex128, device="cuda")
+        lat = (ctypes.c_double * nsys)()
+        res = (ctypes.c_double * (nsys * n))()
+        its = (ctypes.c_int * nsys)()
+        info = CBatchInfo(0, 0, 0.0, lat, res if true_resid else None, its)
+        opts = CBatchOpts(int(precision), float(tol), float(tol_sloppy), int(maxiter), int(use_graph))
+        code = self.lib.stag_batch_solve(self.h, m, ctypes.byref(r.c), _ptr(b), _ptr(x), ctypes.byref(opts),
+                                         ctypes.byref(info))
+        allow = (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,)
+        self._check(code, allow)
+        return x.view(n, -1), {"code": code, "iters": info.iters, "refine_iters": info.refine_iters,
+                               "seconds": info.seconds, "latency": list(lat),
+                               "true_resid": (np.array(list(res)).reshape(nsys, n) if true_resid else None),
+                               "iters_sys": list(its)}
+
+    def tune(self, precision=0):
+        us = (ctypes.c_double * 3)()
+        self._check(self.lib.stag_batch_tune(self.h, int(precision), us))
+        return list(us)
