@@ -20,7 +20,10 @@ Loss: L = (1/N) sum over links and a of (F_s - F_target)^2, N = number of
 links.  Gradients are written out by hand (the reference for the GPU's
 backward kernels) and checked against finite differences.  A "bf16" mode
 rounds the weights and the inputs of every matrix product to bfloat16
-(round to nearest even) where the GPU's matrix-core kernels do.
+(round to nearest even) where the GPU's matrix-core kernels do: the inputs
+of every forward product (features, h1, h2 and the weights) and of every
+backward product (dL/dc, dL/dz2, dL/dz1 with the weights and activations);
+biases, pre-activations, the loss and all accumulations stay wide.
 """
 from __future__ import annotations
 
@@ -124,14 +127,14 @@ def loss_and_grad(params, f, B, target, mode="fp64"):
     dF = 2.0 * diff / N                                   # (N, 8)
     dc = np.zeros((N, N_OUT))
     dc[:, :N_CH] = np.einsum("na,nja->nj", dF, k["B"])    # (N, 8)
-    g = {"W3": dc.T @ r(k["h2"]), "b3": dc.sum(0)}
-    dh2 = dc @ W3
+    g = {"W3": r(dc).T @ r(k["h2"]), "b3": dc.sum(0)}
+    dh2 = r(dc) @ W3
     dz2 = dh2 * dsilu(k["z2"])
-    g["W2"] = dz2.T @ r(k["h1"])
+    g["W2"] = r(dz2).T @ r(k["h1"])
     g["b2"] = dz2.sum(0)
-    dh1 = dz2 @ W2
+    dh1 = r(dz2) @ W2
     dz1 = dh1 * dsilu(k["z1"])
-    g["W1"] = dz1.T @ r(k["f"])
+    g["W1"] = r(dz1).T @ r(k["f"])
     g["b1"] = dz1.sum(0)
     return L_, g
 
