@@ -80,6 +80,69 @@ def cpu_baseline(U, b, rat, vh, target_s=20.0):
             "seconds": dt, "iterations": iters}
 
 
+def _short(name: str) -> str:
+    import re
+    n = name.replace("stag::(anonymous namespace)::", "").replace("HIP_vector_type<double, 2u>", "double2")
+    n = n.replace("HIP_vector_type<float, 2u>", "float2")
+    m = re.match(r"(void )?([^(]*)", n)
+    return m.group(2).strip()
+
+
+def summarize_trace(path, vh=16 * 32 * 32 * 8 // 2 * 2, min_us=2.5):
+    """Per-kernel summary of a rocprofv3 kernel_trace.csv: all launches, and the
+    launches that did work (longer than min_us: converged solves make the
+    remaining queued launches exit at their first instruction)."""
+    import csv
+    from collections import defaultdict
+    d = defaultdict(list)
+    for row in csv.DictReader(open(path)):
+        d[_short(row["Kernel_Name"])].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+    lines = [f"{'kernel':70s} {'launches':>8s} {'worked':>7s} {'avg_us(all)':>11s} {'avg_us(worked)':>14s} "
+             f"{'min_us':>8s} {'max_us':>8s}"]
+    for k, v in sorted(d.items(), key=lambda kv: -sum(kv[1])):
+        w = [t for t in v if t >= min_us]
+        lines.append(f"{k[:70]:70s} {len(v):8d} {len(w):7d} {sum(v) / len(v):11.3f} "
+                     f"{(sum(w) / len(w) if w else 0):14.3f} {min(v):8.3f} {max(v):8.3f}")
+    return "\n".join(lines), d
+
+
+def summarize_pmc(path, counter, copy_bytes):
+    """Per-kernel average of a rocprofv3 --pmc counter (KiB per dispatch) and
+    the scale factor that maps the counter onto the known bytes of the plain
+    copy kernel run in --pmc-mode."""
+    import csv
+    from collections import defaultdict
+    d = defaultdict(list)
+    for row in csv.DictReader(open(path)):
+        if row.get("Counter_Name", counter) != counter:
+            continue
+        d[_short(row["Kernel_Name"])].append(float(row["Counter_Value"]))
+    return d
+
+
+def pmc_mode():
+    """One FP64 solve of the benchmark workload and a plain 512 MiB device copy
+    (the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice
+    torch.cuda.set_device(0)
+    U = synth.random_su3_near_identity(DIMS, 0.2, synth.make_rng(1, 0))
+    b = synth.gaussian_half_vector(DIMS, synth.make_rng(1, 1))
+    rat = synth.load_rational(TABLE)
+    lat = Lattice(DIMS)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    bd = lat.vec_import(torch.from_numpy(b).cuda(), 0)
+    xs = [lat.new_vec() for _ in rat["pole"]]
+    info = lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
+    src = torch.ones(512 * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_mode": True, "iters": info["iters"], "copy_bytes": 512 * 2 ** 20}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,7 +153,16 @@ def main():
     ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--pmc-mode", action="store_true", help="one solve + a 512 MiB copy, for counter runs")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
     args = ap.parse_args()
+    if args.summarize_trace:
+        text, _ = summarize_trace(args.summarize_trace)
+        print(text)
+        return
+    if args.pmc_mode:
+        pmc_mode()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the domain-decomposed design is described in DESIGN.md).", file=sys.stderr)

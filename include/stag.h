@@ -209,6 +209,33 @@ stag_status stag_philox(const uint32_t ctr[4], const uint32_t key[2], size_t n, 
 
 /* ---- one RHMC trajectory (Sec. 3.1) -------------------------------------- */
 
+/* ---- learned force model (optional stand-in for the pseudofermion force) -- */
+
+/* A gauge-covariant force model tied to lattice h: per link, an MLP
+ * (16 -> 64 -> 64 -> 8, SiLU; bf16 matrix-core products, FP32 accumulation)
+ * maps gauge-invariant loop traces of the link's six plaquette staples S_j to
+ * coefficients c_j, and F_a = sum_j c_j Im tr(T_a U S_j).  capacity = number
+ * of (gauge field, force) training pairs the device dataset can hold. */
+typedef struct stag_surrogate* stag_surrogate_handle;
+stag_status stag_surrogate_create(stag_surrogate_handle* out, stag_handle h, int capacity, uint64_t seed);
+stag_status stag_surrogate_destroy(stag_surrogate_handle s);
+const char* stag_surrogate_last_error(stag_surrogate_handle s);
+/* Number of FP32 parameters: W1[64][16], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]. */
+int stag_surrogate_param_count(void);
+/* Read (get_out) and/or replace (set_in, resets the optimiser) the parameters; host arrays. */
+stag_status stag_surrogate_params(stag_surrogate_handle s, float* get_out, const float* set_in);
+/* Store one training pair: the features of h's current gauge field and the
+ * given target force (internal momentum layout, e.g. from stag_fermion_force). */
+stag_status stag_surrogate_add_pair(stag_surrogate_handle s, const void* force);
+/* Adam (lr) over all stored pairs, one step per pair and epoch; loss_out =
+ * mean over the last epoch of (1/links) sum |F_model - F_target|^2. */
+stag_status stag_surrogate_train(stag_surrogate_handle s, int epochs, double lr, double* loss_out);
+/* Loss of the model on h's current gauge field against a target force; with
+ * grad_out (host, param_count floats) also its gradient. */
+stag_status stag_surrogate_eval(stag_surrogate_handle s, const void* force, double* loss_out, float* grad_out);
+/* Model force on h's current gauge field: mom = F (dt == 0) or mom += dt F. */
+stag_status stag_surrogate_force(stag_surrogate_handle s, void* mom, double dt);
+
 typedef struct {
     double beta, mass, tau;
     int n_steps;                  /* leapfrog steps, dt = tau / n_steps */
@@ -222,6 +249,12 @@ typedef struct {
     const void* inject_xi;        /* NULL or internal even vector used instead of the RNG */
     double inject_u;              /* Metropolis uniform in [0,1), or < 0 to draw it */
     int no_fermions;              /* 1: pure gauge trajectory (tests) */
+    stag_surrogate_handle surrogate;  /* NULL, or a model used for the pseudofermion force on kicks
+                                         k (0..n_steps) with k % exact_every != 0 */
+    int exact_every;              /* >= 1; with n_steps % exact_every == 0 the set of exact kicks is
+                                     symmetric under k -> n_steps - k, keeping leapfrog reversible.
+                                     The accept/reject step always uses the exact rational action. */
+    int zero_force_between;       /* 1: ablation, no pseudofermion force on the non-exact kicks */
 } stag_hmc_params;
 
 typedef struct {

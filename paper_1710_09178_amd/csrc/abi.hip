@@ -587,10 +587,21 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         if ((e = finish_solve_status(c, res))) return e;
         acc(res);
     }
-    // step 2: leapfrog
+    // step 2: leapfrog (kick k = 0..n_steps; exact pseudofermion force on
+    // kicks k % exact_every == 0 when a model or the ablation is in use)
     const double dt = p->tau / p->n_steps;
+    int kick_index = 0;
+    const int every = p->exact_every < 1 ? 1 : p->exact_every;
     auto kick = [&](double h) -> stag_status {
         launch_gauge_force(g, c->links, p->beta, c->mom, h, c->s);
+        const bool exact = (kick_index++ % every) == 0 || (!p->surrogate && !p->zero_force_between);
+        if (ferm && !exact) {
+            if (p->surrogate) {
+                stag_status e2 = stag_surrogate_force(p->surrogate, c->mom, h);
+                if (e2) return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
+            }
+            return STAG_OK;
+        }
         if (ferm) {
             stag_status e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, h, res);
             if (e2) return e2;

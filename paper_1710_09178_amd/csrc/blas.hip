@@ -15,14 +15,17 @@ namespace stag {
 
 namespace {
 
+constexpr int kEPTi = 2;  // must equal kEPT of the step kernel (same grid)
+
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __restrict__ b, V* __restrict__ r,
                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     const MsState* __restrict__ st, double* __restrict__ qout) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     const int n = st->n, base = st->base;
     double acc[1] = {0.0};
-    if (i < n3) {
+    for (int e = 0; e < kEPTi; ++e) {
+        const int i = (blockIdx.x * kEPTi + e) * kBlock + threadIdx.x;
+        if (i >= n3) continue;
         const double2 bv = b[i];
         const V bl = from_d2<V>(bv);
         r[i] = bl;
@@ -31,23 +34,42 @@ __global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __res
             x.at<double2>(k)[i] = make_double2(0.0, 0.0);
             if (k != base) ps.at<V>(k)[i] = bl;
         }
-        acc[0] = bv.x * bv.x + bv.y * bv.y;
+        acc[0] += bv.x * bv.x + bv.y * bv.y;
     }
     block_partial<1>(acc, qout);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_restart(int n3, const float2* __restrict__ r, float2* __restrict__ p,
                                                        double* __restrict__ qout) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
     double acc[1] = {0.0};
-    if (i < n3) {
+    for (int e = 0; e < kEPTi; ++e) {
+        const int i = (blockIdx.x * kEPTi + e) * kBlock + threadIdx.x;
+        if (i >= n3) continue;
         const float2 rv = r[i];
         p[i] = rv;
         const double2 d = to_d2(rv);
-        acc[0] = d.x * d.x + d.y * d.y;
+        acc[0] += d.x * d.x + d.y * d.y;
     }
     block_partial<1>(acc, qout);
 }
+
+// Non-temporal access for the per-pole streams (x_k, p_k): each is touched
+// once per iteration, so they should not displace the links and the
+// neighbour-shared vectors from the caches.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 nt_load(const double2* p) {
+    const d2v t = __builtin_nontemporal_load((const d2v*)p);
+    return make_double2(t.x, t.y);
+}
+__device__ __forceinline__ float2 nt_load(const float2* p) {
+    const f2v t = __builtin_nontemporal_load((const f2v*)p);
+    return make_float2(t.x, t.y);
+}
+__device__ __forceinline__ void nt_store(double2* p, double2 v) { __builtin_nontemporal_store(d2v{v.x, v.y}, (d2v*)p); }
+__device__ __forceinline__ void nt_store(float2* p, float2 v) { __builtin_nontemporal_store(f2v{v.x, v.y}, (f2v*)p); }
+
+constexpr int kEPT = 2;  // complex elements per thread in the vector kernels of the solve
 
 // Iteration k (parity par):
 //   rr_k   = sum of the <r,r> partials of the previous step (or of init)
@@ -56,6 +78,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_restart(int n3, const float2* __r
 //   beta   = rr_{k+1} / rr_k, zeta', alpha_s, beta_s from the shifted-CG recurrences
 //   r -= alpha Ap; x_base += alpha p; p = r + beta p;
 //   x_s += alpha_s p_s; p_s = zeta_s' r + beta_s p_s      (active shifts)
+// Every block evaluates the scalars itself (one thread per shift) from the
+// partial sums, so all blocks agree bitwise without a grid barrier.
 template <class V>
 __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, const V* __restrict__ Ap,
                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
@@ -66,9 +90,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
     __shared__ double lds[16];
     __shared__ double sh_as[kMaxPoles], sh_bs[kMaxPoles], sh_zn[kMaxPoles];
     __shared__ int sh_act[kMaxPoles], sh_list[kMaxPoles];
-    __shared__ double sh_alpha, sh_beta;
-    __shared__ int sh_stop, sh_nact;
+    __shared__ double sh_rr, sh_bb, sh_alpha, sh_beta;
+    __shared__ int sh_stop, sh_nact, sh_nonfinite;
     const int n = st->n, base = st->base;
+    const MsIter& s = st->it[par];
+    const int iter = s.iter;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int nbq = gridDim.x;  // init and step kernels use the same grid
     for (int b = threadIdx.x; b < nbq; b += kBlock) v[0] += qin[b];
@@ -79,128 +105,128 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
     }
     block_sum<4>(v, lds);
     if (threadIdx.x == 0) {
-        const MsIter& s = st->it[par];
         const double rr = v[0], pAp = v[1], rAp = v[2], ApAp = v[3];
-        const int iter = s.iter;
         const double bb = (iter == 0 && !st->bb_given) ? rr : s.bb;
         int nonfinite = !isfinite(rr);
-        int any = 0;
-        int act[kMaxPoles];
-        for (int k = 0; k < n; ++k) {
-            act[k] = s.active[k];
-            if (act[k] && s.zeta[k] * s.zeta[k] * rr <= st->tol2 * bb) act[k] = 0;
-            any |= act[k];
-        }
-        int stop = nonfinite || !any || iter >= st->maxiter;
         double alpha = 0.0, beta = 0.0;
-        double zn[kMaxPoles];
-        if (!stop) {
+        if (!nonfinite) {
             alpha = rr / pAp;
             double rr1 = rr - 2.0 * alpha * rAp + alpha * alpha * ApAp;
             if (rr1 < 0.0) rr1 = 0.0;
             beta = rr1 / rr;
-            const double a_old = s.alpha_old, b_old = s.beta_old;
-            for (int k = 0; k < n; ++k) {
-                if (k == base) {
-                    zn[k] = 1.0;
-                    sh_as[k] = alpha;
-                    sh_bs[k] = beta;
-                    continue;
-                }
-                const double z = s.zeta[k], zo = s.zeta_old[k];
-                if (!act[k]) {
-                    zn[k] = z;
-                    sh_as[k] = sh_bs[k] = 0.0;
-                    continue;
-                }
-                const double znk = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st->shift[k] * alpha));
-                const double q = znk / z;
-                zn[k] = znk;
-                sh_as[k] = alpha * q;
-                sh_bs[k] = beta * q * q;
-            }
-            if (!isfinite(alpha) || !isfinite(beta)) {
-                nonfinite = 1;
-                stop = 1;
-            }
         }
-        for (int k = 0; k < n; ++k) {
-            sh_act[k] = act[k];
-            sh_zn[k] = zn[k];
-        }
+        sh_rr = rr;
+        sh_bb = bb;
         sh_alpha = alpha;
         sh_beta = beta;
-        sh_stop = stop;
-        if (blockIdx.x == 0) {
-            MsIter& o = stop ? st->fin : st->it[par ^ 1];
-            for (int k = 0; k < n; ++k) {
-                o.active[k] = act[k];
-                o.iters_per_pole[k] = (act[k] && !stop) ? iter + 1 : (s.active[k] ? iter : s.iters_per_pole[k]);
-                o.zeta[k] = stop ? s.zeta[k] : zn[k];
-                o.zeta_old[k] = stop ? s.zeta_old[k] : s.zeta[k];
-            }
-            o.alpha_old = stop ? s.alpha_old : alpha;
-            o.beta_old = stop ? s.beta_old : beta;
-            o.bb = bb;
-            o.rr = rr;
-            o.iter = stop ? iter : iter + 1;
-            o.nonfinite = nonfinite;
-            if (stop) st->done = 1;
-        }
+        sh_nonfinite = nonfinite;
     }
-    // compact list of the active shifted poles (the base pole is handled with p)
+    __syncthreads();
+    // one thread per shift: freezing test and recurrences
+    const int k = threadIdx.x;
+    if (k < n) {
+        const double rr = sh_rr, alpha = sh_alpha, beta = sh_beta;
+        int act = s.active[k];
+        if (act && s.zeta[k] * s.zeta[k] * rr <= st->tol2 * sh_bb) act = 0;
+        const double z = s.zeta[k], zo = s.zeta_old[k];
+        double zn = z, as = 0.0, bs = 0.0;
+        if (k == base) {
+            zn = 1.0;
+            as = alpha;
+            bs = beta;
+        } else if (act) {
+            const double a_old = s.alpha_old, b_old = s.beta_old;
+            zn = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st->shift[k] * alpha));
+            const double q = zn / z;
+            as = alpha * q;
+            bs = beta * q * q;
+        }
+        sh_act[k] = act;
+        sh_zn[k] = zn;
+        sh_as[k] = as;
+        sh_bs[k] = bs;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        int m = 0;
-        for (int k = 0; k < n; ++k)
-            if (k != base && sh_act[k]) sh_list[m++] = k;
+        int any = 0, m = 0;
+        for (int q = 0; q < n; ++q) {
+            any |= sh_act[q];
+            if (q != base && sh_act[q]) sh_list[m++] = q;
+        }
+        int nonfinite = sh_nonfinite;
+        if (any && !(isfinite(sh_alpha) && isfinite(sh_beta))) nonfinite = 1;
+        sh_nonfinite = nonfinite;
+        sh_stop = nonfinite || !any || iter >= st->maxiter;
         sh_nact = m;
     }
     __syncthreads();
-    if (sh_stop) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int stop = sh_stop;
+    if (blockIdx.x == 0) {
+        // the state of the next iteration (or the final one)
+        MsIter& o = stop ? st->fin : st->it[par ^ 1];
+        if (k < n) {
+            const int act = sh_act[k];
+            o.active[k] = act;
+            o.iters_per_pole[k] = (act && !stop) ? iter + 1 : (s.active[k] ? iter : s.iters_per_pole[k]);
+            o.zeta[k] = stop ? s.zeta[k] : sh_zn[k];
+            o.zeta_old[k] = stop ? s.zeta_old[k] : s.zeta[k];
+        }
+        if (threadIdx.x == 0) {
+            o.alpha_old = stop ? s.alpha_old : sh_alpha;
+            o.beta_old = stop ? s.beta_old : sh_beta;
+            o.bb = sh_bb;
+            o.rr = sh_rr;
+            o.iter = stop ? iter : iter + 1;
+            o.nonfinite = sh_nonfinite;
+            if (stop) st->done = 1;
+        }
+    }
+    if (stop) return;
     const double alpha = sh_alpha, beta = sh_beta;
+    const bool base_on = sh_act[base];
+    const int nact = sh_nact;
     double acc[1] = {0.0};
-    if (i < n3) {
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+        const int i = (blockIdx.x * kEPT + e) * kBlock + threadIdx.x;
+        if (i >= n3) continue;
         // r and p in the Krylov precision V, solutions accumulated in FP64
         const double2 a = to_d2(Ap[i]);
         double2 rv = to_d2(r[i]);
         const double2 pv = to_d2(p[i]);
-        const bool base_on = sh_act[base];
         double2* xb = x.at<double2>(base);
-        double2 xbv = base_on ? xb[i] : make_double2(0.0, 0.0);
         rv.x -= alpha * a.x;
         rv.y -= alpha * a.y;
         const V rl = from_d2<V>(rv);
         r[i] = rl;
         rv = to_d2(rl);
-        acc[0] = rv.x * rv.x + rv.y * rv.y;
+        acc[0] += rv.x * rv.x + rv.y * rv.y;
         if (base_on) {
-            xbv.x += alpha * pv.x;
-            xbv.y += alpha * pv.y;
-            xb[i] = xbv;
+            const double2 xbv = nt_load(xb + i);
+            nt_store(xb + i, make_double2(xbv.x + alpha * pv.x, xbv.y + alpha * pv.y));
         }
         p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
         // shifted poles in groups: all loads of a group are issued before its
         // stores (the pointers may not be proven distinct by the compiler)
         constexpr int G = 4;
-        const int nact = sh_nact;
         for (int g0 = 0; g0 < nact; g0 += G) {
             double2 pk[G], xk[G];
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (g0 + j < nact) {
-                    const int k = sh_list[g0 + j];
-                    pk[j] = to_d2(ps.at<V>(k)[i]);
-                    xk[j] = x.at<double2>(k)[i];
+                    const int q = sh_list[g0 + j];
+                    pk[j] = to_d2(nt_load(ps.at<V>(q) + i));
+                    xk[j] = nt_load(x.at<double2>(q) + i);
                 }
             }
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (g0 + j < nact) {
-                    const int k = sh_list[g0 + j];
-                    const double ak = sh_as[k], bk = sh_bs[k], zk = sh_zn[k];
-                    x.at<double2>(k)[i] = make_double2(xk[j].x + ak * pk[j].x, xk[j].y + ak * pk[j].y);
-                    ps.at<V>(k)[i] = from_d2<V>(make_double2(zk * rv.x + bk * pk[j].x, zk * rv.y + bk * pk[j].y));
+                    const int q = sh_list[g0 + j];
+                    const double aq = sh_as[q], bq = sh_bs[q], zq = sh_zn[q];
+                    nt_store(x.at<double2>(q) + i, make_double2(xk[j].x + aq * pk[j].x, xk[j].y + aq * pk[j].y));
+                    nt_store(ps.at<V>(q) + i,
+                             from_d2<V>(make_double2(zq * rv.x + bq * pk[j].x, zq * rv.y + bq * pk[j].y)));
                 }
             }
         }
@@ -254,16 +280,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 }
 
 inline int grid3(const Geom& g) { return (3 * g.vh + kBlock - 1) / kBlock; }
+// grid of the init / step / restart kernels (kEPT elements per thread)
+inline int gridq(const Geom& g) { return (3 * g.vh + kBlock * kEPT - 1) / (kBlock * kEPT); }
 
 }  // namespace
 
-int ms_update_grid(const Geom& g) { return grid3(g); }
+int ms_update_grid(const Geom& g) { return gridq(g); }
 int dot_grid(const Geom& g) { return grid3(g); }
 
 template <class V>
 void launch_ms_init(const Geom& g, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, const MsState* st,
                     double* qout, hipStream_t s) {
-    k_ms_init<V><<<grid3(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
+    k_ms_init<V><<<gridq(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
 }
 template void launch_ms_init<double2>(const Geom&, const double2*, double2*, double2*, VecPtrs, VecPtrs,
                                       const MsState*, double*, hipStream_t);
@@ -273,7 +301,8 @@ template void launch_ms_init<float2>(const Geom&, const double2*, float2*, float
 template <class V>
 void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
                     int nb2, const double* qin, double* qout, int par, hipStream_t s) {
-    k_ms_step<V><<<grid3(g), kBlock, 0, s>>>(3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin, qout, par);
+    timed_launch(k_ms_step<V>, dim3(gridq(g)), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin, qout,
+                 par);
 }
 template void launch_ms_step<double2>(const Geom&, double2*, const double2*, double2*, VecPtrs, VecPtrs, MsState*,
                                       const double*, int, const double*, double*, int, hipStream_t);
@@ -281,7 +310,7 @@ template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2
                                      const double*, int, const double*, double*, int, hipStream_t);
 
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
-    k_cg_restart<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);
+    k_cg_restart<<<gridq(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);
 }
 
 void launch_rational_sum(const Geom& g, const double2* b, VecPtrs x, const MsState* st, double2* out,

@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP sources of libstag (gfx950 only).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -229,6 +230,30 @@ struct VecPtrs {
     template <class T>
     __host__ __device__ T* at(int k) const { return (T*)p[k]; }
 };
+
+// ---------------------------------------------------------------------------
+// Optional timing of the next launch: when set, launchers that support it
+// dispatch through hipExtLaunchKernelGGL so that the two events carry the
+// kernel's own start and end timestamps (the same interval a kernel trace
+// reports).  Host-side, per thread.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchTiming& next_launch_timing() {
+    static thread_local LaunchTiming t;
+    return t;
+}
+
+template <class K, class... Args>
+inline void timed_launch(K kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    LaunchTiming& t = next_launch_timing();
+    if (t.start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.start, t.stop, 0, args...);
+        t.start = t.stop = nullptr;
+    } else {
+        kernel<<<grid, block, 0, s>>>(args...);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Host-side launchers (defined in the .hip files).

@@ -266,9 +266,9 @@ void launch_tps(const Geom& g, const Link& L, const typename Link::C* in, int ou
                 const MsState* gate, hipStream_t s) {
     const int grid = dslash_grid(g, tps);
     switch (tps) {
-        case 1: k_dslash<1, Link, Epi><<<grid, kBlock, 0, s>>>(g, L, in, out_par, epi, gate); break;
-        case 2: k_dslash<2, Link, Epi><<<grid, kBlock, 0, s>>>(g, L, in, out_par, epi, gate); break;
-        default: k_dslash<4, Link, Epi><<<grid, kBlock, 0, s>>>(g, L, in, out_par, epi, gate); break;
+        case 1: timed_launch(k_dslash<1, Link, Epi>, dim3(grid), dim3(kBlock), s, g, L, in, out_par, epi, gate); break;
+        case 2: timed_launch(k_dslash<2, Link, Epi>, dim3(grid), dim3(kBlock), s, g, L, in, out_par, epi, gate); break;
+        default: timed_launch(k_dslash<4, Link, Epi>, dim3(grid), dim3(kBlock), s, g, L, in, out_par, epi, gate); break;
     }
 }
 

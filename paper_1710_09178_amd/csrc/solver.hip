@@ -57,18 +57,17 @@ namespace {
 
 using EvRec = std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, int>>;
 
+// the next launch records its own start/end timestamps into an event pair
 void prof_begin(stag_ctx* c, hipEvent_t* a) {
     *a = nullptr;
     if (!c->prof_on || c->prof_used + 2 > c->prof_ev.size()) return;
     *a = c->prof_ev[c->prof_used];
-    hipEventRecord(*a, c->s);
+    next_launch_timing() = LaunchTiming{*a, c->prof_ev[c->prof_used + 1]};
 }
 void prof_end(stag_ctx* c, hipEvent_t a, int kind, EvRec& rec) {
     if (!a) return;
-    hipEvent_t b = c->prof_ev[c->prof_used + 1];
-    hipEventRecord(b, c->s);
+    rec.push_back({{a, c->prof_ev[c->prof_used + 1]}, kind});
     c->prof_used += 2;
-    rec.push_back({{a, b}, kind});
 }
 // kernel times of iterations 0..iter (the last one only detects convergence in
 // its step kernel, after full Dslash launches)
@@ -148,7 +147,7 @@ void init_state(MsState* h, int n, const double* pole, const double* residue, do
 // next iteration.
 template <class V, class Between>
 stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtrs X, VecPtrs P, int chunk,
-                           EvRec& rec, Between between_chunks) {
+                           EvRec& rec, Between between_chunks, bool two_in_flight = true) {
     const Geom& g = c->g;
     const double mt = c->st_host->mass_term;
     const int nb2 = dslash_grid(g, c->tps);
@@ -173,13 +172,13 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
         hipEventRecord(c->chunk_ev[slot], c->s);
     };
     issue_chunk(0);
-    issue_chunk(1);
+    if (two_in_flight) issue_chunk(1);
     int cur = 0;
     for (;;) {
         HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
         if (c->done_host[cur]) break;
         issue_chunk(cur);
-        cur ^= 1;
+        if (two_in_flight) cur ^= 1;
     }
     HIP_OR_FAIL(c, hipGetLastError());
     return STAG_OK;
@@ -266,8 +265,8 @@ stag_status refine_pole(stag_ctx* c, const LinkSet& ls, double mass, double pole
         launch_cg_restart(g, K.r, K.p, c->qpart[0], c->s);
         VecPtrs X{}, P{};
         X.p[0] = x;
-        stag_status e = run_iterations<float2>(c, ls, K, X, P, every, rec,
-                                               [&](int par_next) { reliable(c->qpart[par_next]); });
+        stag_status e = run_iterations<float2>(
+            c, ls, K, X, P, every, rec, [&](int par_next) { reliable(c->qpart[par_next]); }, false);
         if (e) return e;
         HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
         HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
@@ -338,11 +337,18 @@ stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, dou
     res.iters = r1.iters;
     res.converged = 1;
     if (r1.bb > 0) {
-        // phase 2: every pole to the FP64 true residual tol, smallest pole first
+        // phase 2: every pole to the FP64 true residual tol, smallest pole
+        // first.  The refinement's sloppy operator uses FP32-18 links even when
+        // the multi-shift phase ran on FP16-12 links: CG on an operator with
+        // relative error delta only contracts the true residual when
+        // delta |(A + pole)^-1| |A| < 1, which FP16 links (delta ~ 5e-4)
+        // violate for light poles.
+        LinkSet lr;
+        if ((e = get_links(c, STAG_LINKS_F32_18, lr))) return e;
         for (int k = 0; k < r->n; ++k) {
             int it = 0;
             bool conv = false;
-            if ((e = refine_pole(c, ls, mass, r->pole[k], tol, std::max(1, maxiter - res.iters), b, x[k], r1.bb,
+            if ((e = refine_pole(c, lr, mass, r->pole[k], tol, std::max(1, maxiter - res.iters), b, x[k], r1.bb,
                                  std::max(1, opts->reliable_every), it, conv)))
                 return e;
             ipp[k] += it;

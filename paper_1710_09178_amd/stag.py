@@ -57,7 +57,9 @@ class CHMCParams(ctypes.Structure):
                 ("r_heatbath", CRational), ("tol_md", ctypes.c_double), ("tol_action", ctypes.c_double),
                 ("maxiter", ctypes.c_int), ("seed", ctypes.c_uint64), ("traj_index", ctypes.c_uint64),
                 ("inject_mom", ctypes.c_void_p), ("inject_xi", ctypes.c_void_p),
-                ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int)]
+                ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int),
+                ("surrogate", ctypes.c_void_p), ("exact_every", ctypes.c_int),
+                ("zero_force_between", ctypes.c_int)]
 
 
 class CTrajInfo(ctypes.Structure):
@@ -124,7 +126,7 @@ def load_library() -> ctypes.CDLL:
         "stag_philox": (S, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32), ctypes.c_size_t,
                             P, P]),
         "stag_md_trajectory": (S, [H, ctypes.POINTER(CHMCParams), ctypes.POINTER(CTrajInfo)]),
-        "stag_batch_create": (S, [ctypes.POINTER(H), ctypes.POINTER(ctypes.c_int), I, I, P]),
+        "stag_batch_create": (S, [ctypes.POINTER(H), I, ctypes.POINTER(ctypes.c_int), I, P]),
         "stag_batch_destroy": (S, [H]),
         "stag_batch_last_error": (ctypes.c_char_p, [H]),
         "stag_batch_vec_bytes": (ctypes.c_size_t, [H]),
@@ -132,6 +134,15 @@ def load_library() -> ctypes.CDLL:
         "stag_batch_solve": (S, [H, ctypes.POINTER(D), ctypes.POINTER(CRational), P, P, ctypes.POINTER(CBatchOpts),
                                  ctypes.POINTER(CBatchInfo)]),
         "stag_batch_tune": (S, [H, I, ctypes.POINTER(D)]),
+        "stag_surrogate_create": (S, [ctypes.POINTER(H), H, I, ctypes.c_uint64]),
+        "stag_surrogate_destroy": (S, [H]),
+        "stag_surrogate_last_error": (ctypes.c_char_p, [H]),
+        "stag_surrogate_param_count": (I, []),
+        "stag_surrogate_params": (S, [H, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+        "stag_surrogate_add_pair": (S, [H, P]),
+        "stag_surrogate_train": (S, [H, I, D, ctypes.POINTER(D)]),
+        "stag_surrogate_eval": (S, [H, P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_float)]),
+        "stag_surrogate_force": (S, [H, P, D]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
         "stag_tune": (S, [H, I, I]),
@@ -330,10 +341,12 @@ class Lattice:
 
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
-                   no_fermions=False) -> dict:
+                   no_fermions=False, surrogate=None, exact_every=1, zero_force_between=False) -> dict:
         a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
         prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
-                         _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions))
+                         _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions),
+                         surrogate.h if surrogate is not None else None, int(exact_every),
+                         int(zero_force_between))
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
@@ -374,7 +387,7 @@ class Batch:
         self.stream = stream or torch.cuda.current_stream()
         flat = (ctypes.c_int * (4 * len(self.dims)))(*[v for d in self.dims for v in d])
         h = ctypes.c_void_p()
-        code = self.lib.stag_batch_create(ctypes.byref(h), flat, len(self.dims), self.nrhs,
+        code = self.lib.stag_batch_create(ctypes.byref(h), len(self.dims), flat, self.nrhs,
                                           ctypes.c_void_p(self.stream.cuda_stream))
         if code != STAG_OK:
             raise StagError(code, self.lib.stag_batch_last_error(None).decode())
@@ -424,3 +437,61 @@ class Batch:
         us = (ctypes.c_double * 3)()
         self._check(self.lib.stag_batch_tune(self.h, int(precision), us))
         return list(us)
+
+
+class Surrogate:
+    """The learned force model of a Lattice (see include/stag.h)."""
+
+    def __init__(self, lat: Lattice, capacity: int, seed: int = 0):
+        self.lib = lat.lib
+        self.lat = lat
+        h = ctypes.c_void_p()
+        code = self.lib.stag_surrogate_create(ctypes.byref(h), lat.h, int(capacity), int(seed))
+        if code != STAG_OK:
+            raise StagError(code, lat.lib.stag_last_error(lat.h).decode())
+        self.h = h
+        self.n_params = int(self.lib.stag_surrogate_param_count())
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.stag_surrogate_destroy(h)
+            self.h = None
+
+    def _check(self, code):
+        if code != STAG_OK:
+            raise StagError(code, self.lib.stag_surrogate_last_error(self.h).decode())
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        self._check(self.lib.stag_surrogate_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), None))
+        return out
+
+    def set_params(self, p):
+        arr = np.ascontiguousarray(p, dtype=np.float32)
+        assert arr.size == self.n_params
+        self._check(self.lib.stag_surrogate_params(self.h, None, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def add_pair(self, force: torch.Tensor):
+        self._check(self.lib.stag_surrogate_add_pair(self.h, _ptr(force)))
+
+    def train(self, epochs: int, lr: float) -> float:
+        loss = ctypes.c_double()
+        self._check(self.lib.stag_surrogate_train(self.h, int(epochs), float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def eval(self, force: torch.Tensor, want_grad=False):
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None
+        self._check(self.lib.stag_surrogate_eval(self.h, _ptr(force), ctypes.byref(loss), gp))
+        return loss.value, g
+
+    def force(self, mom: torch.Tensor, dt: float = 0.0):
+        self._check(self.lib.stag_surrogate_force(self.h, _ptr(mom), float(dt)))
+
+
+def surrogate_params_to_flat(params: dict) -> np.ndarray:
+    """Flatten a parameter dict (W1, b1, W2, b2, W3, b3) in the library's order."""
+    return np.concatenate([np.asarray(params[k], dtype=np.float64).reshape(-1)
+                           for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)

@@ -51,3 +51,40 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.stag_dslash(None, None, None, 1) == -1
     assert lib.stag_destroy(None) == 0
     assert lib.stag_field_bytes(None, 0) == 0
+
+
+def _prototypes():
+    """name -> list of parameter declarations, parsed from include/stag.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    protos = {}
+    for m in re.finditer(r"\b(?:stag_status|const char\*|size_t|int)\s+(stag_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", text):
+        params = [p.strip() for p in m.group(2).split(",") if p.strip() and p.strip() != "void"]
+        protos[m.group(1)] = params
+    return protos
+
+
+def test_binding_signatures_match_the_header():
+    """Every ctypes signature of the Python binding has the header's arity and
+    puts pointers exactly where the C prototype has pointers (an argument-order
+    mistake here would hand an integer to C as an address)."""
+    import ctypes as C
+
+    from paper_1710_09178_amd import stag
+    lib = stag.load_library()
+    protos = _prototypes()
+    scalar = (C.c_int, C.c_uint32, C.c_uint64, C.c_double, C.c_size_t, C.c_long)
+    checked = 0
+    for name, params in protos.items():
+        fn = getattr(lib, name)
+        if fn.argtypes is None:
+            continue
+        assert len(fn.argtypes) == len(params), name
+        for decl, at in zip(params, fn.argtypes):
+            is_ptr = "*" in decl or "[" in decl or decl.split()[0] in ("stag_handle", "stag_batch_handle",
+                                                                       "stag_surrogate_handle")
+            if is_ptr:
+                assert at is C.c_void_p or issubclass(at, C._Pointer) or at is C.c_char_p, (name, decl, at)
+            else:
+                assert at in scalar, (name, decl, at)
+        checked += 1
+    assert checked >= 25

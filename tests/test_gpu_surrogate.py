@@ -1,0 +1,138 @@
+"""Learned force model on the GPU (bf16 matrix-core kernels) against the
+oracle's bf16-emulating reference: forces, loss, gradients; covariance;
+training reduces the loss; trajectories use it only on non-exact kicks."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice as L, surrogate as S
+from oracle.su3 import to_coords, to_matrix
+from paper_1710_09178_amd import stag
+from tests.gpu_util import dev, host, lattice, log
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (4, 4, 2, 4)
+KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def _params(seed):
+    rng = synth.make_rng(700, seed)
+    p = S.init_params(rng)
+    p["W3"] = rng.standard_normal(p["W3"].shape) * 0.3
+    p["b1"] = rng.standard_normal(S.HID) * 0.1
+    p["b3"] = rng.standard_normal(S.N_OUT) * 0.1
+    # the library keeps FP32 parameters: compare against the same values
+    return {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def _flat(p):
+    return stag.surrogate_params_to_flat(p)
+
+
+def _unflat(g):
+    out, o = {}, 0
+    shapes = {"W1": (64, 16), "b1": (64,), "W2": (64, 64), "b2": (64,), "W3": (8, 64), "b3": (8,)}
+    for k in KEYS:
+        n = int(np.prod(shapes[k]))
+        out[k] = g[o:o + n].reshape(shapes[k])
+        o += n
+    return out
+
+
+@pytest.mark.parametrize("dims", [DIMS, (6, 4, 4, 8)])
+def test_force_matches_bf16_oracle(dims):
+    log(f"surrogate force dims={dims}")
+    U = synth.random_su3_near_identity(dims, 0.6, synth.make_rng(701, 0))
+    lat = lattice(dims, U)
+    sur = stag.Surrogate(lat, 1)
+    p = _params(1)
+    sur.set_params(_flat(p))
+    mom = lat.new_mom()
+    sur.force(mom, 0.0)
+    got = host(lat.mom_export(mom))
+    exp = S.surrogate_force(p, U, dims, mode="bf16")
+    scale = np.abs(exp).max()
+    assert np.abs(got - exp).max() < 3e-3 * scale, np.abs(got - exp).max() / scale
+    assert np.sqrt(np.mean((got - exp) ** 2)) < 2e-4 * scale
+
+
+def test_loss_and_gradient_match_bf16_oracle():
+    U = synth.random_su3_near_identity(DIMS, 0.6, synth.make_rng(701, 1))
+    lat = lattice(DIMS, U)
+    sur = stag.Surrogate(lat, 1)
+    p = _params(2)
+    sur.set_params(_flat(p))
+    nx, ny, nz, nt = DIMS
+    target = synth.make_rng(701, 2).standard_normal((nt, nz, ny, nx, 4, 8))
+    loss, g = sur.eval(lat.mom_import(dev(target)), want_grad=True)
+    f, loops = S.features(U, DIMS)
+    tf = target.reshape(-1, 8).astype(np.float32).astype(np.float64)
+    lref, gref = S.loss_and_grad(p, f, S.basis(loops), tf, mode="bf16")
+    assert abs(loss - lref) < 1e-4 * lref
+    gg = _unflat(g.astype(np.float64))
+    for k in KEYS:
+        err = np.abs(gg[k] - gref[k]).max() / max(np.abs(gref[k]).max(), 1e-30)
+        assert err < 2e-2, (k, err)
+
+
+def test_force_is_gauge_covariant():
+    U = synth.random_su3_near_identity(DIMS, 0.6, synth.make_rng(701, 3))
+    rng = synth.make_rng(701, 4)
+    Om = synth.haar_su3(DIMS, rng)[..., 0, :, :]
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Ug[..., mu, :, :] = np.einsum("...ij,...jk,...lk->...il", Om, U[..., mu, :, :], L.fwd(Om, mu).conj())
+    lat = lattice(DIMS, U)
+    sur = stag.Surrogate(lat, 1)
+    sur.set_params(_flat(_params(3)))
+    m1 = lat.new_mom()
+    sur.force(m1, 0.0)
+    F = host(lat.mom_export(m1))
+    lat.set_gauge(dev(Ug))
+    m2 = lat.new_mom()
+    sur.force(m2, 0.0)
+    Fg = host(lat.mom_export(m2))
+    rot = to_coords(np.einsum("...ij,...mjk,...lk->...mil", Om, to_matrix(F), Om.conj()))
+    # invariant inputs are bf16-rounded on both sides: equal up to that rounding
+    assert np.abs(rot - Fg).max() < 2e-2 * np.abs(F).max()
+
+
+def test_training_reduces_the_fermion_force_loss():
+    dims = (6, 4, 4, 8)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    lat = stag.Lattice(dims)
+    sur = stag.Surrogate(lat, 4, seed=5)
+    rng = synth.make_rng(702, 0)
+    forces = []
+    for k in range(4):
+        U = synth.random_su3_near_identity(dims, 0.5, rng)
+        lat.set_gauge(dev(U))
+        phi = lat.vec_import(dev(synth.gaussian_half_vector(dims, rng)), 0)
+        mom = lat.new_mom()
+        lat.fermion_force(0.1, rat, 1e-10, 100000, phi, mom, 0.0)
+        sur.add_pair(mom)
+        forces.append(mom)
+    l0, _ = sur.eval(forces[-1])
+    loss = sur.train(30, 3e-3)
+    l1, _ = sur.eval(forces[-1])
+    log(f"  loss before {l0:.4e} after {l1:.4e} (training {loss:.4e})")
+    assert l1 < 0.8 * l0
+
+
+def test_trajectory_with_model_is_exact_when_every_kick_is_exact():
+    dims = (4, 4, 2, 4)
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(703, 0))
+    r_f = synth.load_rational("xm050_n8_m0.1")
+    r_h = synth.load_rational("xp025_n8_m0.1")
+    lat = lattice(dims, U0)
+    sur = stag.Surrogate(lat, 1)
+    sur.set_params(_flat(_params(4)))
+    a = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, seed=3, traj_index=1)
+    Ua = host(lat.get_gauge())
+    lat.set_gauge(dev(U0))
+    b = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, seed=3, traj_index=1, surrogate=sur, exact_every=1)
+    assert a["dH"] == b["dH"] and np.array_equal(Ua, host(lat.get_gauge()))
+    lat.set_gauge(dev(U0))
+    c = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, seed=3, traj_index=1, surrogate=sur, exact_every=2)
+    assert np.isfinite(c["dH"]) and c["dH"] != a["dH"]
