@@ -88,10 +88,11 @@ def _short(name: str) -> str:
     return m.group(2).strip()
 
 
-def summarize_trace(path, vh=16 * 32 * 32 * 8 // 2 * 2, min_us=2.5):
+def summarize_trace(path):
     """Per-kernel summary of a rocprofv3 kernel_trace.csv: all launches, and the
-    launches that did work (longer than min_us: converged solves make the
-    remaining queued launches exit at their first instruction)."""
+    launches that did the full work.  Once a solve has converged, the launches
+    still queued behind it return early (1-5 us); a launch counts as full when
+    it takes at least half the median of the kernel's longer half."""
     import csv
     from collections import defaultdict
     d = defaultdict(list)
@@ -100,7 +101,9 @@ def summarize_trace(path, vh=16 * 32 * 32 * 8 // 2 * 2, min_us=2.5):
     lines = [f"{'kernel':70s} {'launches':>8s} {'worked':>7s} {'avg_us(all)':>11s} {'avg_us(worked)':>14s} "
              f"{'min_us':>8s} {'max_us':>8s}"]
     for k, v in sorted(d.items(), key=lambda kv: -sum(kv[1])):
-        w = [t for t in v if t >= min_us]
+        top = sorted(v)[len(v) // 2:]
+        cut = 0.5 * top[len(top) // 2]
+        w = [t for t in v if t >= cut]
         lines.append(f"{k[:70]:70s} {len(v):8d} {len(w):7d} {sum(v) / len(v):11.3f} "
                      f"{(sum(w) / len(w) if w else 0):14.3f} {min(v):8.3f} {max(v):8.3f}")
     return "\n".join(lines), d
@@ -152,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-mode", action="store_true", help="one solve + a 512 MiB copy, for counter runs")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
@@ -223,6 +228,16 @@ def main():
         log("precision forms")
         forms = precision_forms(lat, rat, bd, xs, vh, base, ms_per_step)
 
+    batched = None
+    if not args.no_batch:
+        log("batched form")
+        batched = batched_form()
+
+    learned = None
+    if not args.no_surrogate:
+        log("learned force model RHMC")
+        learned = surrogate_rhmc()
+
     traj = None
     if not args.no_trajectory:
         log("RHMC trajectory at 16^3x8")
@@ -259,6 +274,10 @@ def main():
         out["sec_per_trajectory"] = traj
     if forms:
         out["precision_forms"] = forms
+    if batched:
+        out["batched_form"] = batched
+    if learned:
+        out["learned_force_rhmc"] = learned
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(U, b, rat, vh, args.cpu_seconds)
@@ -297,6 +316,178 @@ def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
                      "iterations_total": im["iters"], "iterations_per_pole": im["iters_per_pole"],
                      "true_resid_max": max(chk["true_resid"]), "tol_sloppy": 1e-5, "reliable_every": 50}
     return out
+
+
+BATCH_DIMS = [(8, 8, 8, 8), (12, 12, 12, 6), (16, 16, 16, 8), (24, 24, 24, 6)]
+
+
+def batch_bytes(dims, nrhs, iters_per_pole, base):
+    """Algorithmic FP64 bytes of one batched multi-shift solve: per instance and
+    iteration the two Dslash launches read the links once for all right-hand
+    sides; the shift update is counted per system from its per-pole stops."""
+    total = 0
+    for i, d in enumerate(dims):
+        vh = d[0] * d[1] * d[2] * d[3] // 2
+        ipp = iters_per_pole[i * nrhs:(i + 1) * nrhs]
+        iters_inst = int(ipp.max())
+        total += iters_inst * (1152 + 96 * nrhs + 1152 + 192 * nrhs) * vh
+        for sys_ipp in ipp:
+            total += solve_bytes(vh, int(sys_ipp.max()), list(sys_ipp), base) \
+                - (B_DOE + B_DEO_CG) * vh * int(sys_ipp.max())
+    return total
+
+
+def batched_form(per_class=16, nrhs=4, reps=2):
+    """64 lattices (16 each of 8^4, 12^3x6, 16^3x8, 24^3x6) x 4 right-hand sides
+    x the 12 poles of the x^(-1/4) table, masses uniform in [0.005, 0.05], in
+    one batched multi-shift solve; FP64 and mixed FP32/FP64."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Batch
+    dims = [d for d in BATCH_DIMS for _ in range(per_class)]
+    rng = synth.make_rng(3, 0)
+    masses = list(rng.uniform(0.005, 0.05, len(dims)))
+    rat = synth.load_rational(TABLE)
+    base = int(np.argmin(rat["pole"]))
+    B = Batch(dims, nrhs)
+    with ThreadPoolExecutor(8) as ex:
+        fields = ex.map(lambda i: synth.random_su3_near_identity(dims[i], 0.2, synth.make_rng(3, 1000 + i)),
+                        range(len(dims)))
+        for i, U in enumerate(fields):
+            B.set_gauge(i, torch.from_numpy(U).cuda())
+    srcs = [synth.gaussian_half_vector(d, synth.make_rng(3, 5000 + 8 * i + j))
+            for i, d in enumerate(dims) for j in range(nrhs)]
+    b = torch.from_numpy(np.concatenate([v.reshape(-1) for v in srcs])).cuda()
+    del srcs
+    tuned = B.tune(0)
+    out = {"workload": f"{len(dims)} lattices (16 each of 8^4, 12^3x6, 16^3x8, 24^3x6) x {nrhs} right-hand "
+                       f"sides x 12 poles of x^(-1/4), masses U[0.005, 0.05], tol 1e-10",
+           "systems": len(dims) * nrhs, "sites": int(sum(np.prod(d) for d in dims)),
+           "tune_us_tps_1_2_4": [round(u, 2) for u in tuned]}
+    for name, prec in (("fp64", 0), ("mixed_fp32_fp64", 1)):
+        B.solve(masses, rat, b, precision=prec, true_resid=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x, info = B.solve(masses, rat, b, precision=prec, true_resid=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        x, chk = B.solve(masses, rat, b, precision=prec, true_resid=True)
+        lat_ms = np.array(info["latency"]) * 1e3
+        row = {"ms_per_solve": round(dt * 1e3, 3), "iterations": info["iters"],
+               "refine_iterations": info["refine_iters"],
+               "latency_ms_p50": round(float(np.percentile(lat_ms, 50)), 3),
+               "latency_ms_p99": round(float(np.percentile(lat_ms, 99)), 3),
+               "true_resid_max": float(chk["true_resid"].max())}
+        if prec == 0:
+            row["GB/s"] = round(batch_bytes(dims, nrhs, info["iters_per_pole"], base) / dt / 1e9, 1)
+        out[name] = row
+        del x
+    out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32_fp64"]["ms_per_solve"], 3)
+    return out
+
+
+def surrogate_rhmc(n_pairs=2000, n_traj=50, every=4, train_seconds=40.0):
+    """RHMC at 16^3x8 (beta 5.4, m 0.02, 12-pole rational tables, tau 1, 20
+    leapfrog steps) from a seeded hot start, with and without the learned
+    force model.  Exact-force trajectories record n_pairs (U, force) pairs;
+    the model is trained on them on the GPU, then three chains start from the
+    same configuration with the same momenta and pseudofermions: exact force
+    on every kick, the model on all kicks but every `every`-th, and the
+    ablation without a model (exact force on those kicks only, with `every`
+    times the impulse).  Accept/reject always uses the exact action."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice, Surrogate
+    dims = (16, 16, 16, 8)
+    beta, mass, tau, n_steps = 5.4, 0.02, 1.0, 20
+    r_f = synth.load_rational("xm050_n12_m0.02")
+    r_h = synth.load_rational("xp025_n12_m0.02")
+    lat = Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.haar_su3(dims, synth.make_rng(5, 0))).cuda())
+    kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
+    t = 0
+    # thermalisation: pure-gauge trajectories, then dynamical ones, all accepted
+    for _ in range(60):
+        lat.trajectory(beta, mass, 0.5, 20, r_f, r_f, r_h, no_fermions=True, inject_u=0.0, traj_index=t, **kw)
+        t += 1
+    for _ in range(5):
+        lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, inject_u=0.0, traj_index=t, **kw)
+        t += 1
+    # exact-force chain that records the training pairs
+    sur = Surrogate(lat, n_pairs, seed=1)
+    rec = []
+    t0 = time.perf_counter()
+    while sur.pairs < n_pairs:
+        rec.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, surrogate=sur, record_pairs=True,
+                                  traj_index=t, **kw))
+        t += 1
+    t_rec = time.perf_counter() - t0
+    # training on the GPU
+    t0 = time.perf_counter()
+    losses, epochs, lr = [], 0, 1e-3
+    while time.perf_counter() - t0 < train_seconds and epochs < 30:
+        losses.append(sur.train(1, lr))
+        epochs += 1
+        if epochs == 10:
+            lr = 3e-4
+    t_train = time.perf_counter() - t0
+
+    # force error on held-out pseudofermions and configurations
+    def force_error(n=4):
+        errs = []
+        xs = [lat.new_vec() for _ in r_h["pole"]]
+        phi = lat.new_vec()
+        mom = lat.new_mom()
+        for j in range(n):
+            xi = lat.random_source(99, 100000 + j)
+            lat.multishift_solve(mass, r_h, 1e-10, 100000, xi, xs, phi, true_resid=False)
+            lat.fermion_force(mass, r_f, 1e-10, 100000, phi, mom, 0.0)
+            loss, _ = sur.eval(mom)
+            ref = float((mom * mom).sum().item()) / (lat.V * 4)
+            errs.append(float(np.sqrt(loss / ref)))
+        return errs
+
+    U_start = lat.get_gauge()
+    err = force_error()
+
+    def chain(**extra):
+        lat.set_gauge(U_start)
+        torch.cuda.synchronize()
+        res = []
+        t1 = time.perf_counter()
+        for i in range(n_traj):
+            res.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=10 ** 6 + i, **kw, **extra))
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t1) / n_traj
+        dH = np.array([r["dH"] for r in res])
+        return {"traj_per_s": round(1.0 / sec, 3), "sec_per_traj": round(sec, 4),
+                "acceptance": round(float(np.mean([r["accepted"] for r in res])), 3),
+                "mean_abs_dH": round(float(np.mean(np.abs(dH))), 4),
+                "mean_exp_minus_dH": round(float(np.mean(np.exp(-dH))), 4),
+                "cg_iters_per_traj": int(np.mean([r["cg_iters_total"] for r in res])),
+                "plaquette_end": round(res[-1]["plaquette"], 5)}
+
+    exact = chain()
+    model = chain(surrogate=sur, exact_every=every)
+    ablation = chain(coarse_force=True, exact_every=every)
+    for v in (model, ablation):
+        v["speedup_vs_exact"] = round(exact["sec_per_traj"] / v["sec_per_traj"], 3)
+    return {"workload": f"RHMC 16^3x8, beta 5.4, m 0.02, 12-pole tables, tau 1, 20 steps, hot start; "
+                        f"model on all kicks but every {every}th; {n_traj} trajectories per chain",
+            "pairs": n_pairs, "recording_trajectories": len(rec), "recording_seconds": round(t_rec, 2),
+            "recording_acceptance": round(float(np.mean([r["accepted"] for r in rec])), 3),
+            "train_epochs": epochs, "train_seconds": round(t_train, 2),
+            "train_loss_first_last": [losses[0], losses[-1]],
+            "force_rel_error_model": [round(e, 4) for e in err],
+            "force_rel_error_without_model": 1.0,
+            "exact": exact, "model": model, "ablation_coarse_exact": ablation}
 
 
 def trajectory_timing():

@@ -224,6 +224,9 @@ const char* stag_surrogate_last_error(stag_surrogate_handle s);
 int stag_surrogate_param_count(void);
 /* Read (get_out) and/or replace (set_in, resets the optimiser) the parameters; host arrays. */
 stag_status stag_surrogate_params(stag_surrogate_handle s, float* get_out, const float* set_in);
+/* Training pairs stored so far, and the dataset capacity (0 for a NULL handle). */
+int stag_surrogate_pair_count(stag_surrogate_handle s);
+int stag_surrogate_capacity(stag_surrogate_handle s);
 /* Store one training pair: the features of h's current gauge field and the
  * given target force (internal momentum layout, e.g. from stag_fermion_force). */
 stag_status stag_surrogate_add_pair(stag_surrogate_handle s, const void* force);
@@ -254,7 +257,12 @@ typedef struct {
     int exact_every;              /* >= 1; with n_steps % exact_every == 0 the set of exact kicks is
                                      symmetric under k -> n_steps - k, keeping leapfrog reversible.
                                      The accept/reject step always uses the exact rational action. */
-    int zero_force_between;       /* 1: ablation, no pseudofermion force on the non-exact kicks */
+    int coarse_force;             /* 1, with no model: the ablation without one.  The exact force acts
+                                     only on kicks k % exact_every == 0 with exact_every times the
+                                     impulse (two-time-scale leapfrog; needs n_steps % exact_every == 0) */
+    int record_pairs;             /* 1, with a model and exact_every == 1: every pseudofermion force of
+                                     the trajectory is also stored as a training pair of the model,
+                                     until its dataset is full */
 } stag_hmc_params;
 
 typedef struct {
@@ -309,6 +317,8 @@ typedef struct {
                              to the stop of each system (device wall clock) */
     double* true_resid;   /* NULL or host [n_inst*nrhs*n_poles]: FP64 |b-(A+pole)x|/|b| */
     int* iters_sys;       /* NULL or host [n_inst*nrhs]: multi-shift iterations per system */
+    int* iters_per_pole;  /* NULL or host [n_inst*nrhs*n_poles]: multi-shift iteration at which
+                             each pole of each system stopped */
 } stag_batch_info;
 
 /* Solve (A_i + pole_k) x = b for every lattice i (mass masses[i], host

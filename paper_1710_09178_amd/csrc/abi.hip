@@ -229,7 +229,7 @@ stag_status stag_destroy(stag_handle c) {
     void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->r32, c->p32, c->Ap32, c->w32,
                     c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
-                    c->gpart, c->scal};
+                    c->gpart, c->scal, c->mom_tmp};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (c->st_host) hipHostFree(c->st_host);
@@ -544,6 +544,14 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     if ((p->inject_mom && !aligned16(p->inject_mom)) || (p->inject_xi && !aligned16(p->inject_xi)))
         return fail(c, STAG_ERR_INVALID_ARG, "injected fields misaligned");
     if (!(p->inject_u < 1.0)) return fail(c, STAG_ERR_INVALID_ARG, "inject_u must be < 1 (negative = draw)");
+    if (p->coarse_force && (p->surrogate || p->exact_every < 1 || p->n_steps % p->exact_every))
+        return fail(c, STAG_ERR_INVALID_ARG, "coarse_force needs no model, exact_every >= 1 and n_steps % exact_every == 0");
+    if (p->record_pairs && (!p->surrogate || p->exact_every != 1))
+        return fail(c, STAG_ERR_INVALID_ARG, "record_pairs needs a model and exact_every == 1");
+    if (p->record_pairs && !c->mom_tmp) {
+        stag_status e2 = dmalloc(c, &c->mom_tmp, (size_t)64 * c->g.vh * sizeof(double));
+        if (e2) return e2;
+    }
     if ((e = enter(c))) return e;
     const Geom& g = c->g;
     const size_t mb = (size_t)64 * g.vh * sizeof(double);
@@ -587,27 +595,43 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         if ((e = finish_solve_status(c, res))) return e;
         acc(res);
     }
-    // step 2: leapfrog (kick k = 0..n_steps; exact pseudofermion force on
-    // kicks k % exact_every == 0 when a model or the ablation is in use)
+    // step 2: leapfrog, kicks k = 0..n_steps.  With a model or the coarse
+    // ablation, the exact pseudofermion force acts only on kicks
+    // k % exact_every == 0; the model covers the others, or (coarse) the
+    // exact kicks carry exact_every times the impulse, a two-time-scale
+    // leapfrog with the fermion force on the outer scale.
     const double dt = p->tau / p->n_steps;
     int kick_index = 0;
     const int every = p->exact_every < 1 ? 1 : p->exact_every;
+    const bool sched = p->surrogate != nullptr || p->coarse_force;
     auto kick = [&](double h) -> stag_status {
         launch_gauge_force(g, c->links, p->beta, c->mom, h, c->s);
-        const bool exact = (kick_index++ % every) == 0 || (!p->surrogate && !p->zero_force_between);
-        if (ferm && !exact) {
+        const bool exact = !sched || (kick_index % every) == 0;
+        ++kick_index;
+        if (!ferm) return STAG_OK;
+        if (!exact) {
             if (p->surrogate) {
                 stag_status e2 = stag_surrogate_force(p->surrogate, c->mom, h);
                 if (e2) return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
             }
             return STAG_OK;
         }
-        if (ferm) {
-            stag_status e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, h, res);
-            if (e2) return e2;
+        const double hf = p->coarse_force ? h * every : h;
+        stag_status e2;
+        if (p->record_pairs) {
+            if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom_tmp, 0.0, res)))
+                return e2;
             if ((e2 = finish_solve_status(c, res))) return e2;
-            acc(res);
+            if (stag_surrogate_pair_count(p->surrogate) < stag_surrogate_capacity(p->surrogate) &&
+                (e2 = stag_surrogate_add_pair(p->surrogate, c->mom_tmp)))
+                return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
+            launch_axpy_real((size_t)64 * g.vh, hf, c->mom_tmp, c->mom, c->s);
+        } else {
+            if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, hf, res)))
+                return e2;
+            if ((e2 = finish_solve_status(c, res))) return e2;
         }
+        acc(res);
         return STAG_OK;
     };
     if ((e = kick(0.5 * dt))) return e;

@@ -148,7 +148,7 @@ stag_status ensure_links32(stag_batch* c) {
 // kept from the previous solve (st.bb_given).
 template <class V>
 stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* masses, double tol, int maxiter,
-                     const double2* b, double2** x, bool from_fin, bool use_graph, int& iters_out) {
+                     const double2* b, double2** x, bool from_fin, bool use_graph, int& iters_out, bool& conv_out) {
     const BatchDev bd = bdev(c);
     const void* links = std::is_same<V, double2>::value ? (const void*)c->links64 : (const void*)c->links32;
     int base = 0;
@@ -224,9 +224,11 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
     std::vector<MsIter> fin(c->n_sys);
     BHIP(c, hipMemcpy(fin.data(), st.fin, c->n_sys * sizeof(MsIter), hipMemcpyDeviceToHost));
     iters_out = 0;
+    conv_out = true;
     for (auto& f : fin) {
         iters_out = std::max(iters_out, f.iter);
         if (f.nonfinite) return bfail(c, STAG_ERR_NONFINITE, "non-finite value in the batched solve");
+        for (int k = 0; k < n; ++k) conv_out &= !f.active[k];
     }
     return STAG_OK;
 }
@@ -392,21 +394,36 @@ stag_status stag_batch_solve(stag_batch_handle c, const double* masses, const st
     BHIP(c, hipStreamWaitEvent(c->s, c->ev_in, 0));
     stag_status e;
     if ((e = ensure_bpool(c, r->n))) return e;
+    // the residual kernels take 4 m_i^2 from the instance table
+    bool mass_changed = false;
+    for (int i = 0; i < c->n_inst; ++i) {
+        const double m2 = 4.0 * masses[i] * masses[i];
+        mass_changed |= c->inst_h[i].four_m2 != m2;
+        c->inst_h[i].four_m2 = m2;
+    }
+    if (mass_changed) {
+        BHIP(c, hipMemcpyAsync(c->inst_d, c->inst_h.data(), c->n_inst * sizeof(BInst), hipMemcpyHostToDevice, c->s));
+        BHIP(c, hipStreamSynchronize(c->s));
+    }
     const BatchDev bd = bdev(c);
     const size_t L = bvec_len(c);
     launch_bvec_import(bd, (const double2*)b_canon, c->b, c->s);
     std::vector<double2*> xs(r->n);
     for (int k = 0; k < r->n; ++k) xs[k] = c->pool_x + (size_t)k * L;
     int iters = 0, refine = 0;
+    bool conv = true;
     launch_b_timestamp(c->st.t_done + c->n_sys, c->s);
     if (o->precision == 0) {
         if ((e = bsolve_t<double2>(c, r->n, r->pole, masses, o->tol, o->maxiter, c->b, xs.data(), false, o->use_graph,
-                                   iters)))
+                                   iters, conv)))
             return e;
     } else {
+        // the sloppy stage only provides starting guesses: the refinement
+        // below decides convergence
+        bool sloppy_conv = true;
         if ((e = ensure_links32(c))) return e;
         if ((e = bsolve_t<float2>(c, r->n, r->pole, masses, std::max(o->tol, o->tol_sloppy), o->maxiter, c->b,
-                                  xs.data(), false, o->use_graph, iters)))
+                                  xs.data(), false, o->use_graph, iters, sloppy_conv)))
             return e;
     }
     std::vector<unsigned long long> td(c->n_sys + 1);
@@ -415,7 +432,9 @@ stag_status stag_batch_solve(stag_batch_handle c, const double* masses, const st
     BHIP(c, hipMemcpy(fin.data(), c->st.fin, c->n_sys * sizeof(MsIter), hipMemcpyDeviceToHost));
     if (o->precision == 1) {
         // FP64 CG refinement of every pole, all systems of the batch at once;
-        // convergence is measured against |b| of each system
+        // convergence is measured against |b| of each system.  The correction
+        // solve aims at tol/2 so that the rounding of x + e leaves the true
+        // residual below tol.
         for (int k = 0; k < r->n; ++k) {
             if ((e = bresid(c, r->pole[k], xs[k], c->b, true))) return e;
             bool all_ok = true;
@@ -424,28 +443,23 @@ stag_status stag_batch_solve(stag_batch_handle c, const double* masses, const st
             BHIP(c, hipMemcpy(c->st.fin, fin.data(), c->n_sys * sizeof(MsIter), hipMemcpyHostToDevice));
             double2* ev[1] = {c->e};
             int it = 0;
-            if ((e = bsolve_t<double2>(c, 1, &r->pole[k], masses, o->tol, o->maxiter, c->res, ev, true, o->use_graph,
-                                       it)))
+            bool rconv = true;
+            if ((e = bsolve_t<double2>(c, 1, &r->pole[k], masses, 0.5 * o->tol, o->maxiter, c->res, ev, true,
+                                       o->use_graph, it, rconv)))
                 return e;
+            conv &= rconv;
             launch_baxpy(L, xs[k], c->e, c->s);
             refine += it;
         }
     }
     for (int k = 0; k < r->n; ++k) launch_bvec_export(bd, xs[k], (double2*)x_canon + (size_t)k * L, c->s);
-    bool conv = true;
     if (info && info->true_resid) {
         for (int k = 0; k < r->n; ++k) {
             if ((e = bresid(c, r->pole[k], xs[k], c->b, false))) return e;
-            for (int s = 0; s < c->n_sys; ++s) {
-                const double rel = fin[s].bb > 0 ? std::sqrt(c->sums_host[s] / fin[s].bb) : 0.0;
-                info->true_resid[(size_t)s * r->n + k] = rel;
-                if (!(rel <= o->tol * 1.0000001)) conv = false;
-            }
+            for (int s = 0; s < c->n_sys; ++s)
+                info->true_resid[(size_t)s * r->n + k] = fin[s].bb > 0 ? std::sqrt(c->sums_host[s] / fin[s].bb) : 0.0;
         }
     }
-    for (int s = 0; s < c->n_sys && o->precision == 0; ++s)
-        for (int k = 0; k < r->n; ++k)
-            if (fin[s].active[k]) conv = false;
     BHIP(c, hipGetLastError());
     BHIP(c, hipEventRecord(c->ev_out, c->s));
     BHIP(c, hipStreamWaitEvent(c->user, c->ev_out, 0));
@@ -460,9 +474,11 @@ stag_status stag_batch_solve(stag_batch_handle c, const double* masses, const st
         for (int s = 0; s < c->n_sys; ++s) {
             if (info->latency) info->latency[s] = (double)(td[s] - td[c->n_sys]) / hz;
             if (info->iters_sys) info->iters_sys[s] = fin[s].iter;
+            if (info->iters_per_pole)
+                for (int k = 0; k < r->n; ++k) info->iters_per_pole[(size_t)s * r->n + k] = fin[s].iters_per_pole[k];
         }
     }
-    if (!conv) return bfail(c, STAG_ERR_NOT_CONVERGED, "some system did not reach the tolerance");
+    if (!conv) return bfail(c, STAG_ERR_NOT_CONVERGED, "some system reached maxiter before the tolerance");
     return STAG_OK;
 }
 

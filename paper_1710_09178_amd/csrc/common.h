@@ -265,6 +265,8 @@ void launch_mom_to_internal(const Geom& g, const double* canon, double* mom, int
 void launch_mom_to_canon(const Geom& g, const double* mom, double* canon, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+// y += a x over n doubles
+void launch_axpy_real(size_t n, double a, const double* x, double* y, hipStream_t s);
 
 // Multi-shift CG pieces
 int ms_update_grid(const Geom& g);

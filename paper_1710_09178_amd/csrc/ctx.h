@@ -25,6 +25,7 @@ struct stag_ctx {
     bool d12_ok = false, s18_ok = false, h12_ok = false;
     int fmt64 = STAG_LINKS_F64_18;  // storage used by the FP64 operator
     double* mom = nullptr;
+    double* mom_tmp = nullptr;   // force staging when a trajectory records training pairs
     // FP64 Krylov workspace
     double2 *r = nullptr, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
     double2 *xi = nullptr, *phi = nullptr;

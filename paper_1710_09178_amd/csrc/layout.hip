@@ -120,6 +120,11 @@ __global__ void k_links_to_h12(Geom g, const double2* __restrict__ d18, __half2*
     }
 }
 
+__global__ void k_axpy_real(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
 inline int blocks_for(size_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -172,6 +177,13 @@ void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
     int nb = blocks_for(n16);
     if (nb > 8192) nb = 8192;
     k_copy<<<nb, 256, 0, s>>>((uint4*)dst, (const uint4*)src, n16);
+}
+
+void launch_axpy_real(size_t n, double a, const double* x, double* y, hipStream_t s) {
+    if (n == 0) return;
+    int nb = blocks_for(n);
+    if (nb > 8192) nb = 8192;
+    k_axpy_real<<<nb, 256, 0, s>>>(n, a, x, y);
 }
 
 }  // namespace stag

@@ -481,11 +481,14 @@ __global__ void k_sur_adam(const float* __restrict__ gpart, int nwaves, float* _
     prm[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
-__global__ void k_sum_double(const double* __restrict__ p, int n, double* __restrict__ out) {
+// out[0] = sum of the n partials; out[1] += the same sum (epoch accumulator),
+// or out[1] = 0 first when reset is set
+__global__ void k_sum_double(const double* __restrict__ p, int n, double* __restrict__ out, int reset) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s = 0.0;
     for (int i = 0; i < n; ++i) s += p[i];
     out[0] = s;
+    out[1] = (reset ? 0.0 : out[1]) + s;
 }
 
 }  // namespace
@@ -547,7 +550,7 @@ void features_into(stag_surrogate* s, int k) {
 }
 
 // loss (and gradient sum / Adam step) over `rows` dataset rows starting at slot k
-void train_pass(stag_surrogate* s, int k, long long rows, bool grad, int adam_step, float lr) {
+void train_pass(stag_surrogate* s, int k, long long rows, bool grad, int adam_step, float lr, bool reset = true) {
     stag_ctx* c = s->lat;
     k_sur_train<<<s->nblocks, 64 * kWavesSur, 0, c->s>>>(slot_f(s, k), slot_B(s, k), slot_t(s, k), rows,
                                                          1.0 / (double)rows, s->prm, s->gpart, s->lpart, grad ? 1 : 0);
@@ -558,7 +561,7 @@ void train_pass(stag_surrogate* s, int k, long long rows, bool grad, int adam_st
         k_sur_adam<<<(NPAR + 255) / 256, 256, 0, c->s>>>(s->gpart, s->nblocks * kWavesSur, s->prm, s->m, s->v, s->grad,
                                                          lr, b1, b2, 1e-8f, c1, c2, adam_step);
     }
-    k_sum_double<<<1, 64, 0, c->s>>>(s->lpart, s->nblocks * kWavesSur, s->lsum);
+    k_sum_double<<<1, 64, 0, c->s>>>(s->lpart, s->nblocks * kWavesSur, s->lsum, reset ? 1 : 0);
 }
 
 }  // namespace
@@ -579,12 +582,12 @@ stag_status stag_surrogate_create(stag_surrogate_handle* out, stag_handle lat, i
         (e = salloc(s, &s->tgt, slots * s->links * 8 * 4)) || (e = salloc(s, &s->prm, NPAR * 4)) ||
         (e = salloc(s, &s->m, NPAR * 4)) || (e = salloc(s, &s->v, NPAR * 4)) ||
         (e = salloc(s, &s->gpart, (size_t)s->nblocks * kWavesSur * NPAR * 4)) || (e = salloc(s, &s->grad, NPAR * 4)) ||
-        (e = salloc(s, &s->lpart, (size_t)s->nblocks * kWavesSur * 8)) || (e = salloc(s, &s->lsum, 8))) {
+        (e = salloc(s, &s->lpart, (size_t)s->nblocks * kWavesSur * 8)) || (e = salloc(s, &s->lsum, 16))) {
         lat->err = s->err;
         stag_surrogate_destroy(s);
         return e;
     }
-    if (hipHostMalloc((void**)&s->lsum_host, 8, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&s->lsum_host, 16, hipHostMallocDefault) != hipSuccess) {
         stag_surrogate_destroy(s);
         return STAG_ERR_OOM;
     }
@@ -635,6 +638,10 @@ stag_status stag_surrogate_params(stag_surrogate_handle s, float* get_out, const
     return STAG_OK;
 }
 
+int stag_surrogate_pair_count(stag_surrogate_handle s) { return s ? s->pairs : 0; }
+
+int stag_surrogate_capacity(stag_surrogate_handle s) { return s ? s->capacity : 0; }
+
 stag_status stag_surrogate_add_pair(stag_surrogate_handle s, const void* force) {
     if (!s || !force || (uintptr_t)force % 16) return sfail(s, STAG_ERR_INVALID_ARG, "bad arguments");
     if (s->pairs >= s->capacity) return sfail(s, STAG_ERR_INVALID_ARG, "dataset is full");
@@ -653,15 +660,15 @@ stag_status stag_surrogate_train(stag_surrogate_handle s, int epochs, double lr,
     if (s->pairs == 0) return sfail(s, STAG_ERR_INVALID_ARG, "no training pairs");
     double last = 0.0;
     for (int ep = 0; ep < epochs; ++ep) {
-        double sum = 0.0;
+        // one Adam step per stored configuration; the loss is summed on the
+        // device and read once per epoch
         for (int k = 0; k < s->pairs; ++k) {
             s->adam_t += 1;
-            train_pass(s, k, s->links, true, s->adam_t, (float)lr);
-            SHIP(s, hipMemcpyAsync(s->lsum_host, s->lsum, 8, hipMemcpyDeviceToHost, s->lat->s));
-            SHIP(s, hipStreamSynchronize(s->lat->s));
-            sum += s->lsum_host[0] / (double)s->links;
+            train_pass(s, k, s->links, true, s->adam_t, (float)lr, k == 0);
         }
-        last = sum / s->pairs;
+        SHIP(s, hipMemcpyAsync(s->lsum_host, s->lsum, 16, hipMemcpyDeviceToHost, s->lat->s));
+        SHIP(s, hipStreamSynchronize(s->lat->s));
+        last = s->lsum_host[1] / (double)s->links / s->pairs;
     }
     if (loss_out) *loss_out = last;
     SHIP(s, hipGetLastError());

@@ -59,7 +59,7 @@ class CHMCParams(ctypes.Structure):
                 ("inject_mom", ctypes.c_void_p), ("inject_xi", ctypes.c_void_p),
                 ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("exact_every", ctypes.c_int),
-                ("zero_force_between", ctypes.c_int)]
+                ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int)]
 
 
 class CTrajInfo(ctypes.Structure):
@@ -77,7 +77,7 @@ class CBatchOpts(ctypes.Structure):
 class CBatchInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("refine_iters", ctypes.c_int), ("seconds", ctypes.c_double),
                 ("latency", ctypes.POINTER(ctypes.c_double)), ("true_resid", ctypes.POINTER(ctypes.c_double)),
-                ("iters_sys", ctypes.POINTER(ctypes.c_int))]
+                ("iters_sys", ctypes.POINTER(ctypes.c_int)), ("iters_per_pole", ctypes.POINTER(ctypes.c_int))]
 
 
 _lib = None
@@ -138,6 +138,8 @@ def load_library() -> ctypes.CDLL:
         "stag_surrogate_destroy": (S, [H]),
         "stag_surrogate_last_error": (ctypes.c_char_p, [H]),
         "stag_surrogate_param_count": (I, []),
+        "stag_surrogate_pair_count": (I, [H]),
+        "stag_surrogate_capacity": (I, [H]),
         "stag_surrogate_params": (S, [H, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
         "stag_surrogate_add_pair": (S, [H, P]),
         "stag_surrogate_train": (S, [H, I, D, ctypes.POINTER(D)]),
@@ -341,12 +343,13 @@ class Lattice:
 
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
-                   no_fermions=False, surrogate=None, exact_every=1, zero_force_between=False) -> dict:
+                   no_fermions=False, surrogate=None, exact_every=1, coarse_force=False,
+                   record_pairs=False) -> dict:
         a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
         prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
                          _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions),
                          surrogate.h if surrogate is not None else None, int(exact_every),
-                         int(zero_force_between))
+                         int(coarse_force), int(record_pairs))
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
@@ -422,7 +425,8 @@ class Batch:
         lat = (ctypes.c_double * nsys)()
         res = (ctypes.c_double * (nsys * n))()
         its = (ctypes.c_int * nsys)()
-        info = CBatchInfo(0, 0, 0.0, lat, res if true_resid else None, its)
+        ipp = (ctypes.c_int * (nsys * n))()
+        info = CBatchInfo(0, 0, 0.0, lat, res if true_resid else None, its, ipp)
         opts = CBatchOpts(int(precision), float(tol), float(tol_sloppy), int(maxiter), int(use_graph))
         code = self.lib.stag_batch_solve(self.h, m, ctypes.byref(r.c), _ptr(b), _ptr(x), ctypes.byref(opts),
                                          ctypes.byref(info))
@@ -431,7 +435,7 @@ class Batch:
         return x.view(n, -1), {"code": code, "iters": info.iters, "refine_iters": info.refine_iters,
                                "seconds": info.seconds, "latency": list(lat),
                                "true_resid": (np.array(list(res)).reshape(nsys, n) if true_resid else None),
-                               "iters_sys": list(its)}
+                               "iters_sys": list(its), "iters_per_pole": np.array(list(ipp)).reshape(nsys, n)}
 
     def tune(self, precision=0):
         us = (ctypes.c_double * 3)()
@@ -471,6 +475,14 @@ class Surrogate:
         arr = np.ascontiguousarray(p, dtype=np.float32)
         assert arr.size == self.n_params
         self._check(self.lib.stag_surrogate_params(self.h, None, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    @property
+    def pairs(self) -> int:
+        return int(self.lib.stag_surrogate_pair_count(self.h))
+
+    @property
+    def capacity(self) -> int:
+        return int(self.lib.stag_surrogate_capacity(self.h))
 
     def add_pair(self, force: torch.Tensor):
         self._check(self.lib.stag_surrogate_add_pair(self.h, _ptr(force)))
