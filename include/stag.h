@@ -342,6 +342,10 @@ stag_status stag_profile_enable(stag_handle h, int max_launches);
  * index 0 = D_oe (odd <- even), 1 = D_eo with the fused CG epilogue,
  * 2 = fused multi-shift vector update.  Host arrays of length 3, may be NULL. */
 stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
+/* Multi-shift solver: the shifted solutions and directions are updated once
+ * per window of `lag` iterations (1..8, default 4), each read and written once
+ * per window; the results do not depend on the window.  Measurement/tuning. */
+stag_status stag_set_shift_window(stag_handle h, int lag);
 /* Dslash work split: tps = threads cooperating on one output site (1, 2 or 4);
  * chunk = solver iterations enqueued between two convergence polls (>= 1). */
 stag_status stag_tune(stag_handle h, int tps, int chunk);

@@ -195,7 +195,7 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
     const size_t mb = (size_t)2 * 4 * 8 * g.vh * sizeof(double);
     stag_status s;
     if ((s = dmalloc(c, &c->links, lb)) || (s = dmalloc(c, &c->links_backup, lb)) || (s = dmalloc(c, &c->mom, mb)) ||
-        (s = dmalloc(c, &c->r, hb)) || (s = dmalloc(c, &c->p, hb)) || (s = dmalloc(c, &c->Ap, hb)) ||
+        (s = dmalloc(c, &c->r, kLagMax * hb)) || (s = dmalloc(c, &c->p, hb)) || (s = dmalloc(c, &c->Ap, hb)) ||
         (s = dmalloc(c, &c->w_o, hb)) || (s = dmalloc(c, &c->tmp_e, hb)) || (s = dmalloc(c, &c->tmp_o, hb)) ||
         (s = dmalloc(c, &c->xi, hb)) || (s = dmalloc(c, &c->phi, hb)) || (s = dmalloc(c, &c->st, sizeof(MsState))) ||
         (s = dmalloc(c, &c->scal, 64)))
@@ -697,6 +697,15 @@ stag_status stag_profile_read(stag_handle c, double ms[3], long counts[3]) {
         if (ms) ms[i] = c->prof_ms[i];
         if (counts) counts[i] = c->prof_cnt[i];
     }
+    return STAG_OK;
+}
+
+// Shift-update window of the multi-shift solver (1..8 iterations).
+stag_status stag_set_shift_window(stag_handle c, int lag) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (lag < 1 || lag > kLagMax) return fail(c, STAG_ERR_INVALID_ARG, "window must be 1..8");
+    c->lag = lag;
     return STAG_OK;
 }
 

@@ -71,17 +71,24 @@ __device__ __forceinline__ void nt_store(float2* p, float2 v) { __builtin_nontem
 
 constexpr int kEPT = 2;  // complex elements per thread in the vector kernels of the solve
 
-// Iteration k (parity par):
-//   rr_k   = sum of the <r,r> partials of the previous step (or of init)
-//   freeze every shift with zeta_k^2 rr_k <= tol^2 <b,b>; stop if none is left
-//   alpha  = rr_k / <p,Ap>,   rr_{k+1} = rr_k - 2 alpha <r,Ap> + alpha^2 <Ap,Ap>
-//   beta   = rr_{k+1} / rr_k, zeta', alpha_s, beta_s from the shifted-CG recurrences
-//   r -= alpha Ap; x_base += alpha p; p = r + beta p;
-//   x_s += alpha_s p_s; p_s = zeta_s' r + beta_s p_s      (active shifts)
+// Iteration j (parity par):
+//   rr_j   = sum of the <r,r> partials of the previous step (or of init)
+//   freeze every shift with zeta_k^2 rr_j <= tol^2 <b,b>; stop if none is left
+//   alpha  = rr_j / <p,Ap>,   rr_{j+1} = rr_j - 2 alpha <r,Ap> + alpha^2 <Ap,Ap>
+//   beta   = rr_{j+1} / rr_j, zeta', alpha_s, beta_s from the shifted-CG recurrences
+//   r_{j+1} = r_j - alpha Ap; x_base += alpha p; p = r_{j+1} + beta p;
+//   for every active shift s: x_s += alpha_s p_s; p_s = zeta_s' r_{j+1} + beta_s p_s
 // Every block evaluates the scalars itself (one thread per shift) from the
 // partial sums, so all blocks agree bitwise without a grid barrier.
+//
+// The shifted updates are deferred over windows of L = st->lag iterations:
+// r_j lives in ring slot j % L, the scalars of each iteration are kept in
+// st->hist, and the last iteration of a window (or the stopping one) applies
+// the window's updates to x_s and p_s in order, reading and writing each once
+// instead of L times.  The arithmetic and its order are unchanged, so the
+// results do not depend on L.
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, const V* __restrict__ Ap,
+__global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring, const V* __restrict__ Ap,
                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     MsState* __restrict__ st, const double* __restrict__ dpart,
                                                     int nb2, const double* __restrict__ qin, double* __restrict__ qout,
@@ -90,11 +97,14 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
     __shared__ double lds[16];
     __shared__ double sh_as[kMaxPoles], sh_bs[kMaxPoles], sh_zn[kMaxPoles];
     __shared__ int sh_act[kMaxPoles], sh_list[kMaxPoles];
+    __shared__ double w_as[kLagMax][kMaxPoles], w_bs[kLagMax][kMaxPoles], w_zn[kLagMax][kMaxPoles];
+    __shared__ int w_act[kLagMax][kMaxPoles];
     __shared__ double sh_rr, sh_bb, sh_alpha, sh_beta;
     __shared__ int sh_stop, sh_nact, sh_nonfinite;
-    const int n = st->n, base = st->base;
+    const int n = st->n, base = st->base, L = st->lag;
     const MsIter& s = st->it[par];
     const int iter = s.iter;
+    const int slot = iter % L;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int nbq = gridDim.x;  // init and step kernels use the same grid
     for (int b = threadIdx.x; b < nbq; b += kBlock) v[0] += qin[b];
@@ -148,19 +158,32 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int any = 0, m = 0;
-        for (int q = 0; q < n; ++q) {
-            any |= sh_act[q];
-            if (q != base && sh_act[q]) sh_list[m++] = q;
-        }
+        int any = 0;
+        for (int q = 0; q < n; ++q) any |= sh_act[q];
         int nonfinite = sh_nonfinite;
         if (any && !(isfinite(sh_alpha) && isfinite(sh_beta))) nonfinite = 1;
         sh_nonfinite = nonfinite;
         sh_stop = nonfinite || !any || iter >= st->maxiter;
-        sh_nact = m;
     }
     __syncthreads();
     const int stop = sh_stop;
+    // pending shifted updates: iterations iter - slot .. iter (.. iter - 1 when stopping)
+    const int npend = stop ? slot : slot + 1;
+    const bool flush = npend > 0 && (stop || slot == L - 1);
+    if (flush && k < n) {
+        for (int t = 0; t < slot; ++t) {
+            w_as[t][k] = st->hist[t].as[k];
+            w_bs[t][k] = st->hist[t].bs[k];
+            w_zn[t][k] = st->hist[t].zn[k];
+            w_act[t][k] = st->hist[t].act[k];
+        }
+        if (!stop) {
+            w_as[slot][k] = sh_as[k];
+            w_bs[slot][k] = sh_bs[k];
+            w_zn[slot][k] = sh_zn[k];
+            w_act[slot][k] = sh_act[k];
+        }
+    }
     if (blockIdx.x == 0) {
         // the state of the next iteration (or the final one)
         MsIter& o = stop ? st->fin : st->it[par ^ 1];
@@ -170,6 +193,12 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
             o.iters_per_pole[k] = (act && !stop) ? iter + 1 : (s.active[k] ? iter : s.iters_per_pole[k]);
             o.zeta[k] = stop ? s.zeta[k] : sh_zn[k];
             o.zeta_old[k] = stop ? s.zeta_old[k] : s.zeta[k];
+            if (!stop && !flush) {
+                st->hist[slot].as[k] = sh_as[k];
+                st->hist[slot].bs[k] = sh_bs[k];
+                st->hist[slot].zn[k] = sh_zn[k];
+                st->hist[slot].act[k] = sh_act[k];
+            }
         }
         if (threadIdx.x == 0) {
             o.alpha_old = stop ? s.alpha_old : sh_alpha;
@@ -181,31 +210,60 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
             if (stop) st->done = 1;
         }
     }
-    if (stop) return;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // shifts to touch: those active in the window's first iteration
+        int m = 0;
+        if (flush)
+            for (int q = 0; q < n; ++q)
+                if (q != base && w_act[0][q]) sh_list[m++] = q;
+        sh_nact = m;
+    }
+    __syncthreads();
+    if (stop && !flush) return;
     const double alpha = sh_alpha, beta = sh_beta;
     const bool base_on = sh_act[base];
     const int nact = sh_nact;
+    const V* r_cur = ring + (size_t)slot * n3;
+    V* r_next = ring + (size_t)((slot + 1) % L) * n3;
     double acc[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < kEPT; ++e) {
         const int i = (blockIdx.x * kEPT + e) * kBlock + threadIdx.x;
         if (i >= n3) continue;
         // r and p in the Krylov precision V, solutions accumulated in FP64
-        const double2 a = to_d2(Ap[i]);
-        double2 rv = to_d2(r[i]);
-        const double2 pv = to_d2(p[i]);
-        double2* xb = x.at<double2>(base);
-        rv.x -= alpha * a.x;
-        rv.y -= alpha * a.y;
-        const V rl = from_d2<V>(rv);
-        r[i] = rl;
-        rv = to_d2(rl);
-        acc[0] += rv.x * rv.x + rv.y * rv.y;
-        if (base_on) {
-            const double2 xbv = nt_load(xb + i);
-            nt_store(xb + i, make_double2(xbv.x + alpha * pv.x, xbv.y + alpha * pv.y));
+        const double2 r0 = to_d2(r_cur[i]);
+        double2 rv = r0;
+        if (!stop) {
+            const double2 a = to_d2(Ap[i]);
+            const double2 pv = to_d2(p[i]);
+            double2* xb = x.at<double2>(base);
+            rv.x -= alpha * a.x;
+            rv.y -= alpha * a.y;
+            const V rl = from_d2<V>(rv);
+            r_next[i] = rl;
+            rv = to_d2(rl);
+            acc[0] += rv.x * rv.x + rv.y * rv.y;
+            if (base_on) {
+                const double2 xbv = nt_load(xb + i);
+                nt_store(xb + i, make_double2(xbv.x + alpha * pv.x, xbv.y + alpha * pv.y));
+            }
+            p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
         }
-        p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
+        if (!flush) continue;
+        // residuals r_{i+1} of the pending iterations i = iter - slot + t
+        double2 rw[kLagMax];
+#pragma unroll
+        for (int t = 0; t < kLagMax; ++t) {
+            if (t >= npend) break;
+            const int it_next = iter - slot + t + 1;
+            if (it_next == iter + 1)
+                rw[t] = rv;
+            else if (it_next == iter)
+                rw[t] = r0;
+            else
+                rw[t] = to_d2(ring[(size_t)(it_next % L) * n3 + i]);
+        }
         // shifted poles in groups: all loads of a group are issued before its
         // stores (the pointers may not be proven distinct by the compiler)
         constexpr int G = 4;
@@ -220,13 +278,28 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ r, c
                 }
             }
 #pragma unroll
+            for (int t = 0; t < kLagMax; ++t) {
+                if (t >= npend) break;
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    if (g0 + j < nact) {
+                        const int q = sh_list[g0 + j];
+                        if (w_act[t][q]) {
+                            const double aq = w_as[t][q], bq = w_bs[t][q], zq = w_zn[t][q];
+                            xk[j] = make_double2(xk[j].x + aq * pk[j].x, xk[j].y + aq * pk[j].y);
+                            // p_s is kept in the Krylov precision between iterations
+                            pk[j] = to_d2(from_d2<V>(make_double2(zq * rw[t].x + bq * pk[j].x,
+                                                                  zq * rw[t].y + bq * pk[j].y)));
+                        }
+                    }
+                }
+            }
+#pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (g0 + j < nact) {
                     const int q = sh_list[g0 + j];
-                    const double aq = sh_as[q], bq = sh_bs[q], zq = sh_zn[q];
-                    nt_store(x.at<double2>(q) + i, make_double2(xk[j].x + aq * pk[j].x, xk[j].y + aq * pk[j].y));
-                    nt_store(ps.at<V>(q) + i,
-                             from_d2<V>(make_double2(zq * rv.x + bq * pk[j].x, zq * rv.y + bq * pk[j].y)));
+                    nt_store(x.at<double2>(q) + i, xk[j]);
+                    nt_store(ps.at<V>(q) + i, from_d2<V>(pk[j]));
                 }
             }
         }

@@ -208,9 +208,19 @@ struct MsIter {
     int nonfinite;
 };
 
+// Shifted systems are updated once per window of `lag` iterations (at most
+// kLagMax); the scalars of the pending iterations wait in MsState::hist.
+constexpr int kLagMax = 8;
+
+struct MsHist {
+    double as[kMaxPoles], bs[kMaxPoles], zn[kMaxPoles];
+    int act[kMaxPoles];
+};
+
 struct MsState {
     // constants of the solve, set by the host
     int n, base, maxiter;
+    int lag;            // shift-update window (1 = every iteration)
     double tol2;        // tol^2
     double mass_term;   // 4 m^2 + sigma_0
     double c0;          // rational constant term
@@ -222,6 +232,7 @@ struct MsState {
     int done;           // set once by block 0 of the update kernel
     MsIter fin;         // copy of the state at termination
     double true_res2[kMaxPoles];  // |b - (A+sigma_k) x_k|^2 (final check)
+    MsHist hist[kLagMax];         // scalars of iteration i at hist[i % lag]
 };
 
 // Pointer bundles passed by value to kernels.

@@ -27,7 +27,7 @@ struct stag_ctx {
     double* mom = nullptr;
     double* mom_tmp = nullptr;   // force staging when a trajectory records training pairs
     // FP64 Krylov workspace
-    double2 *r = nullptr, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
+    double2 *r = nullptr /* ring of kLagMax residuals */, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
     double2 *xi = nullptr, *phi = nullptr;
     // FP32 Krylov workspace (precision form)
     float2 *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *w32 = nullptr;
@@ -46,6 +46,7 @@ struct stag_ctx {
     bool has_gauge = false;
     int tps = 2;                         // threads per site in the Dslash
     int chunk = 16;                      // iterations enqueued between convergence polls
+    int lag = 4;                         // shift-update window of the multi-shift solver
     // profiling of the solver kernels (hipEvent pairs)
     int prof_on = 0;
     std::vector<hipEvent_t> prof_ev;

@@ -128,6 +128,7 @@ void init_state(MsState* h, int n, const double* pole, const double* residue, do
     h->n = n;
     h->base = base;
     h->maxiter = maxiter;
+    h->lag = 1;
     h->tol2 = tol * tol;
     h->mass_term = 4.0 * mass * mass + s0;
     h->c0 = c0;
@@ -150,6 +151,7 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
                            EvRec& rec, Between between_chunks, bool two_in_flight = true) {
     const Geom& g = c->g;
     const double mt = c->st_host->mass_term;
+    const int L = c->st_host->lag;
     const int nb2 = dslash_grid(g, c->tps);
     int it_issued = 0;
     auto issue_chunk = [&](int slot) {
@@ -160,7 +162,9 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             Krylov<V>::doe(g, ls, K.p, K.w, c->tps, c->st, c->s);
             prof_end(c, a, 0, rec);
             prof_begin(c, &a);
-            Krylov<V>::deo_cg(g, ls, K.w, K.p, K.r, K.Ap, c->st, c->dpart, c->tps, c->s, mt);
+            // residual r_j sits in slot j % L of the ring starting at K.r
+            const V* rj = K.r + (size_t)(it_issued % L) * 3 * g.vh;
+            Krylov<V>::deo_cg(g, ls, K.w, K.p, rj, K.Ap, c->st, c->dpart, c->tps, c->s, mt);
             prof_end(c, a, 1, rec);
             prof_begin(c, &a);
             launch_ms_step<V>(g, K.r, K.Ap, K.p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
@@ -196,6 +200,7 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
     MsState* h = c->st_host;
     int base;
     init_state(h, n, r->pole, r->residue, r->c0, mass, tol, maxiter, base);
+    h->lag = n > 1 ? c->lag : 1;
     HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
     Krylov<V> K(c);
     VecPtrs X{}, P{};
@@ -317,7 +322,7 @@ stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, dou
     if (e) return e;
     const Geom& g = c->g;
     if (!c->r32) {
-        if ((e = dmalloc(c, &c->r32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->p32, half_bytes(g) / 2)) ||
+        if ((e = dmalloc(c, &c->r32, kLagMax * half_bytes(g) / 2)) || (e = dmalloc(c, &c->p32, half_bytes(g) / 2)) ||
             (e = dmalloc(c, &c->Ap32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->w32, half_bytes(g) / 2)))
             return e;
     }

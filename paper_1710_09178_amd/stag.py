@@ -145,6 +145,7 @@ def load_library() -> ctypes.CDLL:
         "stag_surrogate_train": (S, [H, I, D, ctypes.POINTER(D)]),
         "stag_surrogate_eval": (S, [H, P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_float)]),
         "stag_surrogate_force": (S, [H, P, D]),
+        "stag_set_shift_window": (S, [H, I]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
         "stag_tune": (S, [H, I, I]),
@@ -355,6 +356,9 @@ class Lattice:
         return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
 
     # ---- measurement / tuning
+    def set_shift_window(self, lag: int):
+        self._check(self.lib.stag_set_shift_window(self.h, int(lag)))
+
     def profile_enable(self, max_launches: int):
         self._check(self.lib.stag_profile_enable(self.h, int(max_launches)))
 
