@@ -11,8 +11,11 @@ value    = algorithmic HBM bytes of the whole solve / wall time of the solve
 roofline = the D_oe Dslash kernel inside the solve: 1248 algorithmic bytes per
            output site / its average launch duration (hipEvents around every
            launch of one extra profiled solve), against 8 TB/s.
-Also reported: the other solver kernels, iterations, true residuals, and the
-seconds per RHMC trajectory at 16^3x8 (20 leapfrog steps, exact force).
+Also reported: the other solver kernels, iterations, true residuals, the
+precision forms (12-real FP64 links; mixed FP32/FP64 with FP32-18 or FP16-12
+links), the batched form (64 lattices x 4 right-hand sides), the seconds per
+thermalised RHMC trajectory at 16^3x8, and RHMC with and without the learned
+force model.
 """
 from __future__ import annotations
 
@@ -90,6 +93,30 @@ def cpu_baseline(U, b, rat, vh, lag, target_s=20.0):
             "seconds": dt, "iterations": iters}
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dslash_oe_fp64_32c3x8_hbm_traffic.md")
+DSLASH_SOURCES = ["paper_1710_09178_amd/csrc/dslash.hip", "paper_1710_09178_amd/csrc/dslash.h",
+                  "paper_1710_09178_amd/csrc/common.h"]
+
+
+def measured_traffic():
+    """HBM bytes per D_oe launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None once the Dslash sources differ from the ones profiled."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        h = hashlib.sha256()
+        for f in DSLASH_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+    except OSError:
+        return None
+    import re
+    t = re.search(r"traffic_bytes_per_launch dslash_oe (\d+)", text)
+    src = re.search(r"dslash_sources_sha256 ([0-9a-f]{64})", text)
+    if not t or not src or src.group(1) != h.hexdigest():
+        return None
+    return float(t.group(1))
+
+
 def _short(name: str) -> str:
     import re
     n = name.replace("stag::(anonymous namespace)::", "").replace("HIP_vector_type<double, 2u>", "double2")
@@ -162,7 +189,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tps", type=int, default=0, help="Dslash threads per site (0 = library default)")
-    ap.add_argument("--lag", type=int, default=4, help="shift-update window of the solver (1..8)")
+    ap.add_argument("--lag", type=int, default=8, help="shift-update window of the solver (1..8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trajectory", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
@@ -246,15 +273,10 @@ def main():
         log("batched form")
         batched = batched_form()
 
-    learned = None
-    if not args.no_surrogate:
-        log("learned force model RHMC")
-        learned = surrogate_rhmc()
-
-    traj = None
+    rh = None
     if not args.no_trajectory:
-        log("RHMC trajectory at 16^3x8")
-        traj = trajectory_timing()
+        log("RHMC at 16^3x8" + ("" if args.no_surrogate else " with and without the learned force model"))
+        rh = rhmc(with_model=not args.no_surrogate)
 
     out = {
         "metric": "multishift-CG Dslash GB/s (% HBM peak) at 32^3x8; sec/RHMC trajectory",
@@ -274,7 +296,7 @@ def main():
                    "lattice": list(DIMS), "poles": n, "mass": MASS, "tol": TOL, "links": "exp(i 0.2 H) in SU(3)"},
         "roofline": {"bound": "hbm", "kernel": "D_oe Dslash (in the multi-shift CG)",
                      "achieved": round(doe_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(doe_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(doe_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "avg_launch_us": round(avg_us[0], 3), "algorithmic_bytes_per_launch": B_DOE * vh},
         "kernels": {"dslash_oe": {"avg_us": round(avg_us[0], 3), "GB/s": round(doe_gbs, 1), "launches": cnt[0]},
                     "dslash_eo_cg": {"avg_us": round(avg_us[1], 3), "GB/s": round(deo_gbs, 1), "launches": cnt[1]},
@@ -283,14 +305,12 @@ def main():
         "true_resid_max": max(chk["true_resid"]),
         "dslash_gflops": round(570 * vh * 1e-9 / (avg_us[0] * 1e-6), 1),
     }
-    if traj:
-        out["sec_per_trajectory"] = traj
+    if rh:
+        out.update(rh)
     if forms:
         out["precision_forms"] = forms
     if batched:
         out["batched_form"] = batched
-    if learned:
-        out["learned_force_rhmc"] = learned
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(U, b, rat, vh, args.lag, args.cpu_seconds)
@@ -404,15 +424,21 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     return out
 
 
-def surrogate_rhmc(n_pairs=2000, n_traj=50, every=4, train_seconds=40.0):
+def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.0):
     """RHMC at 16^3x8 (beta 5.4, m 0.02, 12-pole rational tables, tau 1, 20
-    leapfrog steps) from a seeded hot start, with and without the learned
-    force model.  Exact-force trajectories record n_pairs (U, force) pairs;
-    the model is trained on them on the GPU, then three chains start from the
-    same configuration with the same momenta and pseudofermions: exact force
-    on every kick, the model on all kicks but every `every`-th, and the
-    ablation without a model (exact force on those kicks only, with `every`
-    times the impulse).  Accept/reject always uses the exact action."""
+    leapfrog steps, MD tolerance 1e-8, action 1e-10) from a seeded hot start,
+    thermalised by 60 pure-gauge and 5 dynamical trajectories (all accepted).
+    sec_per_trajectory: n_exact exact-force trajectories continuing the chain.
+
+    With the learned force model: exact-force trajectories record n_pairs
+    (U, force) pairs, the model is trained on them on the GPU, and chains of
+    n_traj trajectories start from the same configuration with the same
+    momenta and pseudofermions: exact force on every kick; for exact_every in
+    (2, 4) the model replacing the exact force between exact kicks, the model
+    on the inner scale of a two-time-scale leapfrog with the exact force
+    correcting it on the outer scale, and the ablation without a model (exact
+    force on the outer scale only).  Accept/reject always uses the exact
+    action."""
     import numpy as np
     import torch
 
@@ -426,14 +452,35 @@ def surrogate_rhmc(n_pairs=2000, n_traj=50, every=4, train_seconds=40.0):
     lat.set_gauge(torch.from_numpy(synth.haar_su3(dims, synth.make_rng(5, 0))).cuda())
     kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
     t = 0
-    # thermalisation: pure-gauge trajectories, then dynamical ones, all accepted
     for _ in range(60):
         lat.trajectory(beta, mass, 0.5, 20, r_f, r_f, r_h, no_fermions=True, inject_u=0.0, traj_index=t, **kw)
         t += 1
     for _ in range(5):
         lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, inject_u=0.0, traj_index=t, **kw)
         t += 1
-    # exact-force chain that records the training pairs
+
+    def summary(res, sec):
+        dH = np.array([r["dH"] for r in res])
+        return {"sec_per_traj": round(sec, 4), "traj_per_s": round(1.0 / sec, 3),
+                "acceptance": round(float(np.mean([r["accepted"] for r in res])), 3),
+                "mean_abs_dH": round(float(np.mean(np.abs(dH))), 4),
+                "mean_exp_minus_dH": round(float(np.mean(np.exp(-np.minimum(dH, 700.0)))), 4),
+                "cg_iters_per_traj": int(np.mean([r["cg_iters_total"] for r in res])),
+                "plaquette_end": round(res[-1]["plaquette"], 5), "trajectories": len(res)}
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(n_exact):
+        res.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=t, **kw))
+        t += 1
+    torch.cuda.synchronize()
+    out = {"sec_per_trajectory": dict(summary(res, (time.perf_counter() - t0) / n_exact),
+                                      workload="RHMC 16^3x8, beta 5.4, m 0.02, 12-pole x^(-1/2) and x^(1/4) "
+                                               "tables, tau 1, 20 leapfrog steps, thermalised from a hot start")}
+    if not with_model:
+        return out
+
     sur = Surrogate(lat, n_pairs, seed=1)
     rec = []
     t0 = time.perf_counter()
@@ -442,7 +489,6 @@ def surrogate_rhmc(n_pairs=2000, n_traj=50, every=4, train_seconds=40.0):
                                   traj_index=t, **kw))
         t += 1
     t_rec = time.perf_counter() - t0
-    # training on the GPU
     t0 = time.perf_counter()
     losses, epochs, lr = [], 0, 1e-3
     while time.perf_counter() - t0 < train_seconds and epochs < 30:
@@ -452,7 +498,6 @@ def surrogate_rhmc(n_pairs=2000, n_traj=50, every=4, train_seconds=40.0):
             lr = 3e-4
     t_train = time.perf_counter() - t0
 
-    # force error on held-out pseudofermions and configurations
     def force_error(n=4):
         errs = []
         xs = [lat.new_vec() for _ in r_h["pole"]]
@@ -478,54 +523,24 @@ def surrogate_rhmc(n_pairs=2000, n_traj=50, every=4, train_seconds=40.0):
         for i in range(n_traj):
             res.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=10 ** 6 + i, **kw, **extra))
         torch.cuda.synchronize()
-        sec = (time.perf_counter() - t1) / n_traj
-        dH = np.array([r["dH"] for r in res])
-        return {"traj_per_s": round(1.0 / sec, 3), "sec_per_traj": round(sec, 4),
-                "acceptance": round(float(np.mean([r["accepted"] for r in res])), 3),
-                "mean_abs_dH": round(float(np.mean(np.abs(dH))), 4),
-                "mean_exp_minus_dH": round(float(np.mean(np.exp(-dH))), 4),
-                "cg_iters_per_traj": int(np.mean([r["cg_iters_total"] for r in res])),
-                "plaquette_end": round(res[-1]["plaquette"], 5)}
+        return summary(res, (time.perf_counter() - t1) / n_traj)
 
-    exact = chain()
-    model = chain(surrogate=sur, exact_every=every)
-    ablation = chain(coarse_force=True, exact_every=every)
-    for v in (model, ablation):
-        v["speedup_vs_exact"] = round(exact["sec_per_traj"] / v["sec_per_traj"], 3)
-    return {"workload": f"RHMC 16^3x8, beta 5.4, m 0.02, 12-pole tables, tau 1, 20 steps, hot start; "
-                        f"model on all kicks but every {every}th; {n_traj} trajectories per chain",
-            "pairs": n_pairs, "recording_trajectories": len(rec), "recording_seconds": round(t_rec, 2),
-            "recording_acceptance": round(float(np.mean([r["accepted"] for r in rec])), 3),
-            "train_epochs": epochs, "train_seconds": round(t_train, 2),
-            "train_loss_first_last": [losses[0], losses[-1]],
-            "force_rel_error_model": [round(e, 4) for e in err],
-            "force_rel_error_without_model": 1.0,
-            "exact": exact, "model": model, "ablation_coarse_exact": ablation}
-
-
-def trajectory_timing():
-    """Seconds per exact-force RHMC trajectory: 16^3x8, beta 5.4, m 0.02, 12-pole
-    x^(-1/2) / x^(1/4) tables, tau 1, 20 leapfrog steps, tol 1e-10 (MD 1e-8)."""
-    import torch
-
-    import synth
-    from paper_1710_09178_amd.stag import Lattice
-    dims = (16, 16, 16, 8)
-    U = synth.random_su3_near_identity(dims, 0.2, synth.make_rng(4, 0))
-    lat = Lattice(dims)
-    lat.set_gauge(torch.from_numpy(U).cuda())
-    r_f = synth.load_rational("xm050_n12_m0.02")
-    r_h = synth.load_rational("xp025_n12_m0.02")
-    kw = dict(tol_md=1e-8, tol_action=1e-10, seed=7)
-    lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, traj_index=0, **kw)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = [lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, traj_index=i + 1, **kw) for i in range(2)]
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / 2
-    return {"seconds": round(dt, 4), "lattice": list(dims), "beta": 5.4, "mass": 0.02, "n_steps": 20, "tau": 1.0,
-            "cg_iters_per_traj": res[-1]["cg_iters_total"], "dH": [r["dH"] for r in res],
-            "accepted": [r["accepted"] for r in res]}
+    chains = {"exact": chain()}
+    for every in (2, 4):
+        chains[f"model_replaces_exact_every_{every}"] = chain(surrogate=sur, exact_every=every)
+        chains[f"model_inner_scale_exact_every_{every}"] = chain(surrogate=sur, exact_every=every, coarse_force=True)
+        chains[f"ablation_no_model_exact_every_{every}"] = chain(exact_every=every, coarse_force=True)
+    for k, v in chains.items():
+        v["speedup_vs_exact"] = round(chains["exact"]["sec_per_traj"] / v["sec_per_traj"], 3)
+    out["learned_force_rhmc"] = {
+        "workload": "the same RHMC; the learned model stands in for the pseudofermion force between exact kicks",
+        "pairs": n_pairs, "recording_trajectories": len(rec), "recording_seconds": round(t_rec, 2),
+        "recording_acceptance": round(float(np.mean([r["accepted"] for r in rec])), 3),
+        "train_epochs": epochs, "train_seconds": round(t_train, 2),
+        "train_loss_first_last": [losses[0], losses[-1]],
+        "force_rel_error_model": [round(e, 4) for e in err], "force_rel_error_without_model": 1.0,
+        "chains": chains}
+    return out
 
 
 if __name__ == "__main__":

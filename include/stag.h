@@ -257,9 +257,12 @@ typedef struct {
     int exact_every;              /* >= 1; with n_steps % exact_every == 0 the set of exact kicks is
                                      symmetric under k -> n_steps - k, keeping leapfrog reversible.
                                      The accept/reject step always uses the exact rational action. */
-    int coarse_force;             /* 1, with no model: the ablation without one.  The exact force acts
-                                     only on kicks k % exact_every == 0 with exact_every times the
-                                     impulse (two-time-scale leapfrog; needs n_steps % exact_every == 0) */
+    int coarse_force;             /* 1: two-time-scale leapfrog (needs n_steps % exact_every == 0).  The
+                                     kicks k % exact_every == 0 carry exact_every times the impulse of
+                                     the exact force minus the model's; the model alone acts on every
+                                     kick.  Without a model this is the ablation (exact force on the
+                                     outer scale only).  0 with a model: the model replaces the exact
+                                     force on the non-exact kicks. */
     int record_pairs;             /* 1, with a model and exact_every == 1: every pseudofermion force of
                                      the trajectory is also stored as a training pair of the model,
                                      until its dataset is full */
@@ -343,7 +346,7 @@ stag_status stag_profile_enable(stag_handle h, int max_launches);
  * 2 = fused multi-shift vector update.  Host arrays of length 3, may be NULL. */
 stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
 /* Multi-shift solver: the shifted solutions and directions are updated once
- * per window of `lag` iterations (1..8, default 4), each read and written once
+ * per window of `lag` iterations (1..8, default 8), each read and written once
  * per window; the results do not depend on the window.  Measurement/tuning. */
 stag_status stag_set_shift_window(stag_handle h, int lag);
 /* Dslash work split: tps = threads cooperating on one output site (1, 2 or 4);

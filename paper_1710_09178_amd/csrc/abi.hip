@@ -544,8 +544,8 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     if ((p->inject_mom && !aligned16(p->inject_mom)) || (p->inject_xi && !aligned16(p->inject_xi)))
         return fail(c, STAG_ERR_INVALID_ARG, "injected fields misaligned");
     if (!(p->inject_u < 1.0)) return fail(c, STAG_ERR_INVALID_ARG, "inject_u must be < 1 (negative = draw)");
-    if (p->coarse_force && (p->surrogate || p->exact_every < 1 || p->n_steps % p->exact_every))
-        return fail(c, STAG_ERR_INVALID_ARG, "coarse_force needs no model, exact_every >= 1 and n_steps % exact_every == 0");
+    if (p->coarse_force && (p->exact_every < 1 || p->n_steps % p->exact_every))
+        return fail(c, STAG_ERR_INVALID_ARG, "coarse_force needs exact_every >= 1 and n_steps % exact_every == 0");
     if (p->record_pairs && (!p->surrogate || p->exact_every != 1))
         return fail(c, STAG_ERR_INVALID_ARG, "record_pairs needs a model and exact_every == 1");
     if (p->record_pairs && !c->mom_tmp) {
@@ -596,10 +596,11 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         acc(res);
     }
     // step 2: leapfrog, kicks k = 0..n_steps.  With a model or the coarse
-    // ablation, the exact pseudofermion force acts only on kicks
-    // k % exact_every == 0; the model covers the others, or (coarse) the
-    // exact kicks carry exact_every times the impulse, a two-time-scale
-    // leapfrog with the fermion force on the outer scale.
+    // scheme, the exact pseudofermion force acts only on kicks
+    // k % exact_every == 0 and the model (if any) on all the others.  coarse:
+    // two-time-scale leapfrog, the exact kicks carry exact_every times the
+    // impulse of the exact force minus the model's (the model alone acts on
+    // the inner scale); without a model this is the ablation.
     const double dt = p->tau / p->n_steps;
     int kick_index = 0;
     const int every = p->exact_every < 1 ? 1 : p->exact_every;
@@ -618,6 +619,11 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         }
         const double hf = p->coarse_force ? h * every : h;
         stag_status e2;
+        if (p->coarse_force && p->surrogate && every > 1) {
+            // inner-scale model impulse h F_s, outer-scale correction hf (F - F_s)
+            if ((e2 = stag_surrogate_force(p->surrogate, c->mom, h - hf)))
+                return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
+        }
         if (p->record_pairs) {
             if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom_tmp, 0.0, res)))
                 return e2;

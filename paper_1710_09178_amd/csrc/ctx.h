@@ -46,7 +46,7 @@ struct stag_ctx {
     bool has_gauge = false;
     int tps = 2;                         // threads per site in the Dslash
     int chunk = 16;                      // iterations enqueued between convergence polls
-    int lag = 4;                         // shift-update window of the multi-shift solver
+    int lag = 8;                         // shift-update window of the multi-shift solver
     // profiling of the solver kernels (hipEvent pairs)
     int prof_on = 0;
     std::vector<hipEvent_t> prof_ev;

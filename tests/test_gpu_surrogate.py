@@ -174,6 +174,17 @@ def test_trajectory_schedules_and_pair_recording():
     assert d["n_solves"] < a["n_solves"]
     with pytest.raises(stag.StagError):
         lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, coarse_force=True, exact_every=3, **kw)
+    # model on the inner scale with the outer-scale correction: a zero model is the ablation
+    zero = stag.Surrogate(lat, 1)
+    zero.set_params(np.zeros(zero.n_params, dtype=np.float32))
+    lat.set_gauge(dev(U0))
+    z = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, coarse_force=True, exact_every=2, surrogate=zero, **kw)
+    assert z["dH"] == d["dH"]
+    live = stag.Surrogate(lat, 1)
+    live.set_params(_flat(_params(5)))
+    lat.set_gauge(dev(U0))
+    m = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, coarse_force=True, exact_every=2, surrogate=live, **kw)
+    assert np.isfinite(m["dH"]) and m["dH"] != d["dH"] and m["n_solves"] == d["n_solves"]
     # recording stores the exact forces of the kicks until the dataset is full
     sur = stag.Surrogate(lat, 3)
     lat.set_gauge(dev(U0))
