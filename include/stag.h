@@ -330,6 +330,9 @@ typedef struct {
  * k at byte offset k * stag_batch_vec_bytes).  Both device pointers. */
 stag_status stag_batch_solve(stag_batch_handle b, const double* masses, const stag_rational* r, const void* b_canon,
                              void* x_canon, const stag_batch_opts* opts, stag_batch_info* info);
+/* Shift-update window of the batched multi-shift solver: 1, 2, 4 or 8
+ * iterations (default 8); results do not depend on it.  Tuning. */
+stag_status stag_batch_set_shift_window(stag_batch_handle b, int lag);
 /* Autotune the Dslash work split for this batch: times the batched operator
  * for 1, 2 and 4 threads per site (precision 0 or 1) and keeps the fastest.
  * us_out: NULL or host [3] microseconds per application. */

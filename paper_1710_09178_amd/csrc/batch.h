@@ -31,10 +31,16 @@ struct BState {
     double shift[kMaxPoles];
     MsIter* it[2];        // [n_sys]
     MsIter* fin;          // [n_sys]
-    int* sys_done;        // [n_sys] 1 once the system has stopped
-    int* inst_done;       // [n_inst] 1 once every system of the instance has stopped
+    // [2][n_sys] by iteration parity like inst_done: 1 once the system has stopped
+    int* sys_done;
+    // [2][n_inst] by iteration parity: flag [j & 1] is read by the launches of
+    // iteration j; the step of iteration j writes [(j + 1) & 1]
+    int* inst_done;
     unsigned long long* t_done;  // [n_sys] device wall clock at the stop
     double* sigma0_term;  // [n_inst] 4 m_i^2 + sigma_0
+    int lag;              // shift-update window (1..kLagMax); residual ring of `lag` vectors
+    MsHist* hist;         // [n_sys][kLagMax] scalars of the pending iterations
+    size_t ring_stride;   // entries between ring slots (one batched vector)
 };
 
 // Internal batched vector: instance i's block starts at 3*R*off_i and holds
@@ -60,13 +66,14 @@ void launch_bdslash(const BatchDev& bd, int tps, const void* links, const V* in,
                     const int* inst_done, hipStream_t s);
 template <class V>
 void launch_bdslash_cg(const BatchDev& bd, int tps, const void* links, const V* w_o, const V* p, const V* r, V* Ap,
-                       BState st, double* dpart, hipStream_t s);
+                       BState st, const int* inst_done, double* dpart, hipStream_t s);
 // |b - (c_i x - D_eo w_o)|^2 per (tile, rhs), c_i = 4 m_i^2 + pole; optional residual output
 void launch_bdslash_resid(const BatchDev& bd, int tps, const double2* links, const double2* w_o, const double2* x,
                           const double2* b, double pole, double* part, double2* rout, hipStream_t s);
 template <class V>
 void launch_bms_init(const BatchDev& bd, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, BState st,
                      double* qout, hipStream_t s);
+// r: the residual ring (st.lag slots of st.ring_stride entries)
 template <class V>
 void launch_bms_step(const BatchDev& bd, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, BState st,
                      const double* dpart, const double* qin, double* qout, int par, hipStream_t s);

@@ -252,77 +252,100 @@ __global__ __launch_bounds__(kBlock) void k_bms_init(BatchDev bd, const double2*
 }
 
 // Scalars of system s from this iteration's sums (one thread per system).
-// Writes the per-rhs LDS tables; block `writer` also stores the next state.
+// The shifted updates are deferred over windows of st.lag iterations as in
+// the single-lattice solver: the scalars of each iteration go to the
+// system's history, and the window's last iteration (or the stopping one)
+// applies them in order.  w_*: this system's [lag][n] tables in LDS.
 struct BScal {
     double alpha, beta;
-    int stop, nact;
+    int stop, flush, npend, nact, base_on, slot;
     int list[kMaxPoles];
-    double as[kMaxPoles], bs[kMaxPoles], zn[kMaxPoles];
-    int base_on;
 };
 
 __device__ void bsystem_scalars(BState& st, int s, int par, double rr, double pAp, double rAp, double ApAp,
-                                bool writer, BScal& o) {
-    const int n = st.n, base = st.base;
+                                bool writer, BScal& o, double* w_as, double* w_bs, double* w_zn, int* w_act) {
+    const int n = st.n, base = st.base, L = st.lag;
     const MsIter& S = st.it[par][s];
     const int iter = S.iter;
+    const int slot = iter % L;
     const double bb = (iter == 0 && !st.bb_given) ? rr : S.bb;
     int nonfinite = !isfinite(rr);
-    int act[kMaxPoles];
     int any = 0;
     for (int k = 0; k < n; ++k) {
-        act[k] = S.active[k];
-        if (act[k] && S.zeta[k] * S.zeta[k] * rr <= st.tol2 * bb) act[k] = 0;
-        any |= act[k];
+        const int a = S.active[k] && !(S.zeta[k] * S.zeta[k] * rr <= st.tol2 * bb);
+        w_act[slot * n + k] = a;
+        any |= a;
     }
     int stop = nonfinite || !any || iter >= st.maxiter;
     double alpha = 0.0, beta = 0.0;
-    double zn[kMaxPoles];
     if (!stop) {
         alpha = rr / pAp;
         double rr1 = rr - 2.0 * alpha * rAp + alpha * alpha * ApAp;
         if (rr1 < 0.0) rr1 = 0.0;
         beta = rr1 / rr;
-        const double a_old = S.alpha_old, b_old = S.beta_old;
-        for (int k = 0; k < n; ++k) {
-            const double z = S.zeta[k], zo = S.zeta_old[k];
-            if (k == base) {
-                zn[k] = 1.0;
-                o.as[k] = alpha;
-                o.bs[k] = beta;
-            } else if (!act[k]) {
-                zn[k] = z;
-                o.as[k] = o.bs[k] = 0.0;
-            } else {
-                const double znk = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st.shift[k] * alpha));
-                const double q = znk / z;
-                zn[k] = znk;
-                o.as[k] = alpha * q;
-                o.bs[k] = beta * q * q;
-            }
-        }
         if (!isfinite(alpha) || !isfinite(beta)) {
             nonfinite = 1;
             stop = 1;
         }
     }
+    const double a_old = S.alpha_old, b_old = S.beta_old;
+    for (int k = 0; k < n; ++k) {
+        const double z = S.zeta[k], zo = S.zeta_old[k];
+        double zn = z, as = 0.0, bs = 0.0;
+        if (!stop) {
+            if (k == base) {
+                zn = 1.0;
+                as = alpha;
+                bs = beta;
+            } else if (w_act[slot * n + k]) {
+                zn = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st.shift[k] * alpha));
+                const double q = zn / z;
+                as = alpha * q;
+                bs = beta * q * q;
+            }
+        }
+        w_as[slot * n + k] = as;
+        w_bs[slot * n + k] = bs;
+        w_zn[slot * n + k] = zn;
+    }
+    const int npend = stop ? slot : slot + 1;
+    const int flush = npend > 0 && (stop || slot == L - 1);
+    if (flush)
+        for (int t = 0; t < slot; ++t)
+            for (int k = 0; k < n; ++k) {
+                const MsHist& h = st.hist[(size_t)s * kLagMax + t];
+                w_as[t * n + k] = h.as[k];
+                w_bs[t * n + k] = h.bs[k];
+                w_zn[t * n + k] = h.zn[k];
+                w_act[t * n + k] = h.act[k];
+            }
     o.alpha = alpha;
     o.beta = beta;
     o.stop = stop;
-    o.base_on = act[base] && !stop;
+    o.flush = flush;
+    o.npend = npend;
+    o.slot = slot;
+    o.base_on = !stop && w_act[slot * n + base];
     int m = 0;
-    for (int k = 0; k < n; ++k) {
-        o.zn[k] = zn[k];
-        if (k != base && act[k]) o.list[m++] = k;
-    }
-    o.nact = stop ? 0 : m;
+    if (flush)
+        for (int k = 0; k < n; ++k)
+            if (k != base && w_act[k]) o.list[m++] = k;  // active at the window's first iteration
+    o.nact = m;
     if (writer) {
         MsIter& N = stop ? st.fin[s] : st.it[par ^ 1][s];
         for (int k = 0; k < n; ++k) {
-            N.active[k] = act[k];
-            N.iters_per_pole[k] = (act[k] && !stop) ? iter + 1 : (S.active[k] ? iter : S.iters_per_pole[k]);
-            N.zeta[k] = stop ? S.zeta[k] : zn[k];
+            const int a = stop ? 0 : w_act[slot * n + k];
+            N.active[k] = w_act[slot * n + k];
+            N.iters_per_pole[k] = (a && !stop) ? iter + 1 : (S.active[k] ? iter : S.iters_per_pole[k]);
+            N.zeta[k] = stop ? S.zeta[k] : w_zn[slot * n + k];
             N.zeta_old[k] = stop ? S.zeta_old[k] : S.zeta[k];
+            if (!stop && !flush) {
+                MsHist& h = st.hist[(size_t)s * kLagMax + slot];
+                h.as[k] = w_as[slot * n + k];
+                h.bs[k] = w_bs[slot * n + k];
+                h.zn[k] = w_zn[slot * n + k];
+                h.act[k] = w_act[slot * n + k];
+            }
         }
         N.alpha_old = stop ? S.alpha_old : alpha;
         N.beta_old = stop ? S.beta_old : beta;
@@ -331,23 +354,35 @@ __device__ void bsystem_scalars(BState& st, int s, int par, double rr, double pA
         N.iter = stop ? iter : iter + 1;
         N.nonfinite = nonfinite;
         if (stop) {
-            st.sys_done[s] = 1;
+            st.sys_done[(size_t)(par ^ 1) * st.n_inst * st.nrhs + s] = 1;
             st.t_done[s] = wall_clock64();
         }
     }
 }
 
 template <class V>
-__global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict__ r, const V* __restrict__ Ap,
+__global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict__ ring, const V* __restrict__ Ap,
                                                      V* __restrict__ p, VecPtrs x, VecPtrs ps, BState st,
                                                      const double* __restrict__ dpart, const double* __restrict__ qin,
                                                      double* __restrict__ qout, int par) {
     const BTile tl = bd.tiles[blockIdx.x];
-    if (st.inst_done[tl.inst]) return;
+    const int* done_in = st.inst_done + par * st.n_inst;
+    int* done_out = st.inst_done + (par ^ 1) * st.n_inst;
+    if (done_in[tl.inst]) {
+        if (blockIdx.x == bd.inst[tl.inst].tile0 && threadIdx.x == 0) done_out[tl.inst] = 1;
+        return;
+    }
     const BInst I = bd.inst[tl.inst];
-    const int R = bd.nrhs, SB = bd.tile_sites;
+    const int R = bd.nrhs, SB = bd.tile_sites, n = st.n, L = st.lag;
     __shared__ BScal sc[kMaxRhs];
     __shared__ double lds[4 * 4 * kMaxRhs];
+    // window tables [rhs][lag][n]: as, bs, zn (double) then act (int)
+    extern __shared__ double wdyn[];
+    const int wsz = L * n;
+    double* w_as = wdyn;
+    double* w_bs = w_as + kMaxRhs * wsz;
+    double* w_zn = w_bs + kMaxRhs * wsz;
+    int* w_act = (int*)(w_zn + kMaxRhs * wsz);
     // sums over the lattice's tiles: [rhs] rr, [rhs][3] dots
     double v[4 * kMaxRhs];
 #pragma unroll
@@ -368,22 +403,28 @@ __global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict_
     }
     __syncthreads();
     const bool writer = (blockIdx.x == I.tile0);
+    // stopped before this launch; a stop in this launch is written to the other parity
+    const int* sys_in = st.sys_done + (size_t)par * st.n_inst * R;
+    int* sys_out = st.sys_done + (size_t)(par ^ 1) * st.n_inst * R;
     if (threadIdx.x < R) {
         const int q = threadIdx.x;
         const int s = tl.inst * R + q;
-        if (st.sys_done[s]) {
+        if (sys_in[s]) {
+            if (writer) sys_out[s] = 1;
             sc[q].stop = 1;
+            sc[q].flush = 0;
             sc[q].nact = 0;
             sc[q].base_on = 0;
         } else {
-            bsystem_scalars(st, s, par, lds[4 * q], lds[4 * q + 1], lds[4 * q + 2], lds[4 * q + 3], writer, sc[q]);
+            bsystem_scalars(st, s, par, lds[4 * q], lds[4 * q + 1], lds[4 * q + 2], lds[4 * q + 3], writer, sc[q],
+                            w_as + q * wsz, w_bs + q * wsz, w_zn + q * wsz, w_act + q * wsz);
         }
     }
     __syncthreads();
     if (writer && threadIdx.x == 0) {
         int all = 1;
-        for (int q = 0; q < R; ++q) all &= (st.sys_done[tl.inst * R + q] | sc[q].stop);
-        if (all) st.inst_done[tl.inst] = 1;
+        for (int q = 0; q < R; ++q) all &= (sys_in[tl.inst * R + q] | sc[q].stop);
+        if (all) done_out[tl.inst] = 1;
     }
     double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
     const int base = st.base;
@@ -392,26 +433,49 @@ __global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict_
         const int site = tl.cb0 + jj;
         if (site >= I.g.vh) continue;
         const BScal& S = sc[rh];
-        if (S.stop) continue;
+        if (S.stop && !S.flush) continue;
         const size_t i = bvec_off(I, R, rh, c) + site;
-        const double alpha = S.alpha, beta = S.beta;
-        const double2 a = to_d2(Ap[i]);
-        double2 rv = to_d2(r[i]);
-        const double2 pv = to_d2(p[i]);
-        rv.x -= alpha * a.x;
-        rv.y -= alpha * a.y;
-        const V rl = from_d2<V>(rv);
-        r[i] = rl;
-        rv = to_d2(rl);
+        const int slot = S.slot;
+        const double2 r0 = to_d2(ring[(size_t)slot * st.ring_stride + i]);
+        double2 rv = r0;
+        if (!S.stop) {
+            const double alpha = S.alpha, beta = S.beta;
+            const double2 a = to_d2(Ap[i]);
+            const double2 pv = to_d2(p[i]);
+            rv.x -= alpha * a.x;
+            rv.y -= alpha * a.y;
+            const V rl = from_d2<V>(rv);
+            ring[(size_t)((slot + 1) % L) * st.ring_stride + i] = rl;
+            rv = to_d2(rl);
 #pragma unroll
-        for (int q = 0; q < kMaxRhs; ++q)
-            if (q == rh) acc[q] += rv.x * rv.x + rv.y * rv.y;
-        if (S.base_on) {
-            double2* xb = x.at<double2>(base);
-            double2 xv = xb[i];
-            xb[i] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+            for (int q = 0; q < kMaxRhs; ++q)
+                if (q == rh) acc[q] += rv.x * rv.x + rv.y * rv.y;
+            if (S.base_on) {
+                double2* xb = x.at<double2>(base);
+                const double2 xv = xb[i];
+                xb[i] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+            }
+            p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
         }
-        p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
+        if (!S.flush) continue;
+        const int npend = S.npend;
+        const int iter0 = S.slot;  // position of the current iteration in its window
+        double2 rw[kLagMax];
+#pragma unroll
+        for (int t = 0; t < kLagMax; ++t) {
+            if (t >= npend) break;
+            const int pos_next = t + 1;  // window position of r_{i+1}
+            if (pos_next == iter0 + 1)
+                rw[t] = rv;
+            else if (pos_next == iter0)
+                rw[t] = r0;
+            else
+                rw[t] = to_d2(ring[(size_t)(pos_next % L) * st.ring_stride + i]);
+        }
+        const double* was = w_as + rh * wsz;
+        const double* wbs = w_bs + rh * wsz;
+        const double* wzn = w_zn + rh * wsz;
+        const int* wact = w_act + rh * wsz;
         constexpr int G = 4;
         for (int g0 = 0; g0 < S.nact; g0 += G) {
             double2 pk[G], xk[G];
@@ -423,12 +487,26 @@ __global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict_
                     xk[jq] = x.at<double2>(k)[i];
                 }
 #pragma unroll
+            for (int t = 0; t < kLagMax; ++t) {
+                if (t >= npend) break;
+#pragma unroll
+                for (int jq = 0; jq < G; ++jq)
+                    if (g0 + jq < S.nact) {
+                        const int k = S.list[g0 + jq];
+                        if (wact[t * n + k]) {
+                            const double aq = was[t * n + k], bq = wbs[t * n + k], zq = wzn[t * n + k];
+                            xk[jq] = make_double2(xk[jq].x + aq * pk[jq].x, xk[jq].y + aq * pk[jq].y);
+                            pk[jq] = to_d2(from_d2<V>(make_double2(zq * rw[t].x + bq * pk[jq].x,
+                                                                   zq * rw[t].y + bq * pk[jq].y)));
+                        }
+                    }
+            }
+#pragma unroll
             for (int jq = 0; jq < G; ++jq)
                 if (g0 + jq < S.nact) {
                     const int k = S.list[g0 + jq];
-                    x.at<double2>(k)[i] = make_double2(xk[jq].x + S.as[k] * pk[jq].x, xk[jq].y + S.as[k] * pk[jq].y);
-                    ps.at<V>(k)[i] = from_d2<V>(make_double2(S.zn[k] * rv.x + S.bs[k] * pk[jq].x,
-                                                              S.zn[k] * rv.y + S.bs[k] * pk[jq].y));
+                    x.at<double2>(k)[i] = xk[jq];
+                    ps.at<V>(k)[i] = from_d2<V>(pk[jq]);
                 }
         }
     }
@@ -499,8 +577,12 @@ __global__ void k_bstate_init(BState st, int from_fin) {
     S.iter = 0;
     S.nonfinite = 0;
     st.sys_done[s] = 0;
+    st.sys_done[nsys + s] = 0;
     st.t_done[s] = 0;
-    if (s % st.nrhs == 0) st.inst_done[s / st.nrhs] = 0;
+    if (s % st.nrhs == 0) {
+        st.inst_done[s / st.nrhs] = 0;
+        st.inst_done[st.n_inst + s / st.nrhs] = 0;
+    }
 }
 
 __global__ void k_baxpy(size_t n, double2* __restrict__ x, const double2* __restrict__ e) {
@@ -528,13 +610,13 @@ template void launch_bdslash<float2>(const BatchDev&, int, const void*, const fl
 
 template <class V>
 void launch_bdslash_cg(const BatchDev& bd, int tps, const void* links, const V* w_o, const V* p, const V* r, V* Ap,
-                       BState st, double* dpart, hipStream_t s) {
-    bdslash_tps<V>(bd, tps, (const V*)links, w_o, 0, BEpiCG<V>{Ap, p, r, st.sigma0_term, dpart}, st.inst_done, s);
+                       BState st, const int* inst_done, double* dpart, hipStream_t s) {
+    bdslash_tps<V>(bd, tps, (const V*)links, w_o, 0, BEpiCG<V>{Ap, p, r, st.sigma0_term, dpart}, inst_done, s);
 }
 template void launch_bdslash_cg<double2>(const BatchDev&, int, const void*, const double2*, const double2*,
-                                         const double2*, double2*, BState, double*, hipStream_t);
+                                         const double2*, double2*, BState, const int*, double*, hipStream_t);
 template void launch_bdslash_cg<float2>(const BatchDev&, int, const void*, const float2*, const float2*, const float2*,
-                                        float2*, BState, double*, hipStream_t);
+                                        float2*, BState, const int*, double*, hipStream_t);
 
 void launch_bdslash_resid(const BatchDev& bd, int tps, const double2* links, const double2* w_o, const double2* x,
                           const double2* b, double pole, double* part, double2* rout, hipStream_t s) {
@@ -554,7 +636,8 @@ template void launch_bms_init<float2>(const BatchDev&, const double2*, float2*, 
 template <class V>
 void launch_bms_step(const BatchDev& bd, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, BState st,
                      const double* dpart, const double* qin, double* qout, int par, hipStream_t s) {
-    k_bms_step<V><<<bd.ntiles, kBlock, 0, s>>>(bd, r, Ap, p, x, ps, st, dpart, qin, qout, par);
+    const size_t lds = (size_t)kMaxRhs * st.lag * st.n * (3 * sizeof(double) + sizeof(int));
+    k_bms_step<V><<<bd.ntiles, kBlock, lds, s>>>(bd, r, Ap, p, x, ps, st, dpart, qin, qout, par);
 }
 template void launch_bms_step<double2>(const BatchDev&, double2*, const double2*, double2*, VecPtrs, VecPtrs, BState,
                                        const double*, const double*, double*, int, hipStream_t);

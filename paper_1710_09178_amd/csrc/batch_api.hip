@@ -28,6 +28,7 @@ struct stag_batch {
     BInst* inst_d = nullptr;
     BTile* tiles_d = nullptr;
     int tps = 2;
+    int lag = 8;                 // shift-update window (divides the 16-iteration chunk)
     int tiles_cap = 0;
     size_t total_vh = 0;
     double2* links64 = nullptr;
@@ -35,6 +36,7 @@ struct stag_batch {
     bool l32_ok = false;
     std::vector<int> gauge_set;
     // batched vectors (3 * nrhs * total_vh complex entries)
+    // r: ring of kLagMax residuals (batched vectors); the others one batched vector each
     double2 *b = nullptr, *r = nullptr, *p = nullptr, *Ap = nullptr, *w = nullptr, *e = nullptr, *res = nullptr;
     double2* pool_x = nullptr;   // n_cap solution vectors (FP64)
     double2* pool_p = nullptr;   // n_cap shifted search directions (FP64 or FP32)
@@ -160,6 +162,8 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
     st.maxiter = maxiter;
     st.tol2 = tol * tol;
     st.bb_given = from_fin ? 1 : 0;
+    st.lag = n > 1 ? c->lag : 1;
+    st.ring_stride = bvec_len(c);
     for (int k = 0; k < n; ++k) st.shift[k] = poles[k] - poles[base];
     std::vector<double> s0(c->n_inst);
     for (int i = 0; i < c->n_inst; ++i) s0[i] = 4.0 * masses[i] * masses[i] + poles[base];
@@ -175,12 +179,15 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
         P.p[k] = (V*)c->pool_p + (size_t)k * bvec_len(c);
     }
     launch_bms_init<V>(bd, b, r, p, X, P, st, c->qpart[0], c->s);
-    const int chunk = 16;  // even: the parity pattern repeats across chunks
+    // a multiple of 2 and of the window: the parity and ring patterns repeat across chunks
+    const int chunk = 16;
     auto enqueue_chunk = [&]() {
         for (int it = 0; it < chunk; ++it) {
             const int par = it & 1;
-            launch_bdslash<V>(bd, c->tps, links, p, w, 1, st.inst_done, c->s);
-            launch_bdslash_cg<V>(bd, c->tps, links, w, p, r, Ap, st, c->dpart, c->s);
+            const V* rj = r + (size_t)(it % st.lag) * st.ring_stride;
+            const int* gate = st.inst_done + par * c->n_inst;
+            launch_bdslash<V>(bd, c->tps, links, p, w, 1, gate, c->s);
+            launch_bdslash_cg<V>(bd, c->tps, links, w, p, rj, Ap, st, gate, c->dpart, c->s);
             launch_bms_step<V>(bd, r, Ap, p, X, P, st, c->dpart, c->qpart[par], c->qpart[par ^ 1], par, c->s);
         }
     };
@@ -198,6 +205,7 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
             hipGraphLaunch(exec, c->s);
         else
             enqueue_chunk();
+        // chunks are even: the next iteration reads the parity-0 flags
         hipMemcpyAsync(dh + slot * c->n_inst, st.inst_done, c->n_inst * sizeof(int), hipMemcpyDeviceToHost, c->s);
         hipEventRecord(c->chunk_ev[slot], c->s);
     };
@@ -303,13 +311,14 @@ stag_status stag_batch_create(stag_batch_handle* out, int n_inst, const int* dim
     st.nrhs = nrhs;
     if ((s = balloc(c, &c->inst_d, n_inst * sizeof(BInst))) ||
         (s = balloc(c, &c->links64, (size_t)72 * c->total_vh * sizeof(double2))) || (s = balloc(c, &c->b, vb)) ||
-        (s = balloc(c, &c->r, vb)) || (s = balloc(c, &c->p, vb)) || (s = balloc(c, &c->Ap, vb)) ||
+        (s = balloc(c, &c->r, kLagMax * vb)) || (s = balloc(c, &c->p, vb)) || (s = balloc(c, &c->Ap, vb)) ||
         (s = balloc(c, &c->w, vb)) || (s = balloc(c, &c->e, vb)) || (s = balloc(c, &c->res, vb)) ||
         (s = balloc(c, &st.it[0], c->n_sys * sizeof(MsIter))) || (s = balloc(c, &st.it[1], c->n_sys * sizeof(MsIter))) ||
-        (s = balloc(c, &st.fin, c->n_sys * sizeof(MsIter))) || (s = balloc(c, &st.sys_done, c->n_sys * sizeof(int))) ||
-        (s = balloc(c, &st.inst_done, n_inst * sizeof(int))) ||
+        (s = balloc(c, &st.fin, c->n_sys * sizeof(MsIter))) || (s = balloc(c, &st.sys_done, 2 * c->n_sys * sizeof(int))) ||
+        (s = balloc(c, &st.inst_done, 2 * n_inst * sizeof(int))) ||
         (s = balloc(c, &st.t_done, (c->n_sys + 1) * sizeof(unsigned long long))) ||
-        (s = balloc(c, &st.sigma0_term, n_inst * sizeof(double))) || (s = balloc(c, &c->sums, c->n_sys * sizeof(double))))
+        (s = balloc(c, &st.sigma0_term, n_inst * sizeof(double))) ||
+        (s = balloc(c, &st.hist, (size_t)c->n_sys * kLagMax * sizeof(MsHist))) || (s = balloc(c, &c->sums, c->n_sys * sizeof(double))))
         return bail(s);
     if (hipHostMalloc((void**)&c->done_host, 2 * n_inst * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->sums_host, c->n_sys * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -332,7 +341,7 @@ stag_status stag_batch_destroy(stag_batch_handle c) {
     if (c->s) hipStreamSynchronize(c->s);
     void* bufs[] = {c->inst_d, c->tiles_d, c->links64, c->links32, c->b, c->r, c->p, c->Ap, c->w, c->e, c->res,
                     c->pool_x, c->pool_p, c->st.it[0], c->st.it[1], c->st.fin, c->st.sys_done, c->st.inst_done,
-                    c->st.t_done, c->st.sigma0_term, c->dpart, c->qpart[0], c->qpart[1], c->gpart, c->sums};
+                    c->st.t_done, c->st.sigma0_term, c->st.hist, c->dpart, c->qpart[0], c->qpart[1], c->gpart, c->sums};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (c->done_host) hipHostFree(c->done_host);
@@ -479,6 +488,13 @@ stag_status stag_batch_solve(stag_batch_handle c, const double* masses, const st
         }
     }
     if (!conv) return bfail(c, STAG_ERR_NOT_CONVERGED, "some system reached maxiter before the tolerance");
+    return STAG_OK;
+}
+
+stag_status stag_batch_set_shift_window(stag_batch_handle c, int lag) {
+    if (!c) return bfail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
+    if (lag != 1 && lag != 2 && lag != 4 && lag != 8) return bfail(c, STAG_ERR_INVALID_ARG, "window must be 1, 2, 4 or 8");
+    c->lag = lag;
     return STAG_OK;
 }
 

@@ -93,7 +93,10 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
                                                     MsState* __restrict__ st, const double* __restrict__ dpart,
                                                     int nb2, const double* __restrict__ qin, double* __restrict__ qout,
                                                     int par) {
-    if (st->done) return;
+    if (st->done[par]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->done[par ^ 1] = 1;
+        return;
+    }
     __shared__ double lds[16];
     __shared__ double sh_as[kMaxPoles], sh_bs[kMaxPoles], sh_zn[kMaxPoles];
     __shared__ int sh_act[kMaxPoles], sh_list[kMaxPoles];
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
             o.rr = sh_rr;
             o.iter = stop ? iter : iter + 1;
             o.nonfinite = sh_nonfinite;
-            if (stop) st->done = 1;
+            if (stop) st->done[par ^ 1] = 1;
         }
     }
     __syncthreads();

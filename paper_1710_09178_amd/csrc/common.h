@@ -229,7 +229,10 @@ struct MsState {
     int bb_given;       // 1: it[0].bb is set by the host (refinement of a residual)
     // iteration state
     MsIter it[2];
-    int done;           // set once by block 0 of the update kernel
+    // done[j & 1] is read by the launches of iteration j; the step kernel of
+    // iteration j sets done[(j + 1) & 1] when the solve stops and carries a
+    // set flag forward, so no launch reads a flag that its own blocks write
+    int done[2];
     MsIter fin;         // copy of the state at termination
     double true_res2[kMaxPoles];  // |b - (A+sigma_k) x_k|^2 (final check)
     MsHist hist[kLagMax];         // scalars of iteration i at hist[i % lag]

@@ -20,22 +20,22 @@ int dslash_grid(const Geom& g, int tps);
 
 // FP64 operator (format fmt64)
 void launch_dslash(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int out_par, int tps,
-                   const MsState* gate, hipStream_t s);
+                   const int* gate, hipStream_t s);
 // out = c*in - D_eo w_o
 void launch_dslash_axpy(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* in, double c,
                         double2* out, int tps, hipStream_t s);
 // Ap = mt p - D_eo w_o and block partials of <p,Ap>, <r,Ap>, <Ap,Ap>
 void launch_dslash_cg(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
-                      double2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mass_term);
+                      double2* Ap, const int* gate, double* dpart, int tps, hipStream_t s, double mass_term);
 // res = b - (c x - D_eo w_o): block partials of |res|^2; res stored as float2 when r32_out != NULL
 void launch_dslash_resid(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* x, const double2* b,
                          double c, double* part, int tps, hipStream_t s, float2* r32_out = nullptr);
 
 // FP32 operator (format fmt32)
 void launch_dslash32(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int out_par, int tps,
-                     const MsState* gate, hipStream_t s);
+                     const int* gate, hipStream_t s);
 void launch_dslash32_cg(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* p, const float2* r,
-                        float2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mass_term);
+                        float2* Ap, const int* gate, double* dpart, int tps, hipStream_t s, double mass_term);
 void launch_dslash32_axpy(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* in, double c,
                           float2* out, int tps, hipStream_t s);
 

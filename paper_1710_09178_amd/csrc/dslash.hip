@@ -223,11 +223,11 @@ struct EpiResid {
 
 template <int TPS, class Link, class Epi>
 __global__ __launch_bounds__(kBlock) void k_dslash(Geom g, Link L, const typename Link::C* __restrict__ in,
-                                                   int out_par, Epi epi, const MsState* __restrict__ gate) {
+                                                   int out_par, Epi epi, const int* __restrict__ gate) {
     using C = typename Link::C;
     constexpr int SB = kBlock / TPS;
     constexpr int DPT = 4 / TPS;
-    if (gate && gate->done) return;  // converged solve: the whole grid skips
+    if (gate && *gate) return;  // converged solve: the whole grid skips
     __shared__ C part[TPS * 3 * SB];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slice = wave % TPS, sgrp = wave / TPS;
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash(Geom g, Link L, const typenam
 
 template <class Link, class Epi>
 void launch_tps(const Geom& g, const Link& L, const typename Link::C* in, int out_par, const Epi& epi, int tps,
-                const MsState* gate, hipStream_t s) {
+                const int* gate, hipStream_t s) {
     const int grid = dslash_grid(g, tps);
     switch (tps) {
         case 1: timed_launch(k_dslash<1, Link, Epi>, dim3(grid), dim3(kBlock), s, g, L, in, out_par, epi, gate); break;
@@ -297,7 +297,7 @@ int dslash_grid(const Geom& g, int tps) {
 
 // ---- FP64 operator
 void launch_dslash(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int out_par, int tps,
-                   const MsState* gate, hipStream_t s) {
+                   const int* gate, hipStream_t s) {
     with_link64(ls, [&](auto L) { launch_tps(g, L, in, out_par, EpiStore<double2>{out, g.vh}, tps, gate, s); });
 }
 
@@ -307,7 +307,7 @@ void launch_dslash_axpy(const Geom& g, const LinkSet& ls, const double2* w_o, co
 }
 
 void launch_dslash_cg(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
-                      double2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mass_term) {
+                      double2* Ap, const int* gate, double* dpart, int tps, hipStream_t s, double mass_term) {
     with_link64(ls, [&](auto L) {
         launch_tps(g, L, w_o, 0, EpiCG<double2>{Ap, p, r, dpart, mass_term, g.vh}, tps, gate, s);
     });
@@ -325,12 +325,12 @@ void launch_dslash_resid(const Geom& g, const LinkSet& ls, const double2* w_o, c
 
 // ---- FP32 (sloppy) operator
 void launch_dslash32(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int out_par, int tps,
-                     const MsState* gate, hipStream_t s) {
+                     const int* gate, hipStream_t s) {
     with_link32(ls, [&](auto L) { launch_tps(g, L, in, out_par, EpiStore<float2>{out, g.vh}, tps, gate, s); });
 }
 
 void launch_dslash32_cg(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* p, const float2* r,
-                        float2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mass_term) {
+                        float2* Ap, const int* gate, double* dpart, int tps, hipStream_t s, double mass_term) {
     with_link32(ls, [&](auto L) {
         launch_tps(g, L, w_o, 0, EpiCG<float2>{Ap, p, r, dpart, mass_term, g.vh}, tps, gate, s);
     });

@@ -93,12 +93,12 @@ template <>
 struct Krylov<double2> {
     double2 *r, *p, *Ap, *w;
     explicit Krylov(stag_ctx* c) : r(c->r), p(c->p), Ap(c->Ap), w(c->w_o) {}
-    static void doe(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int tps, const MsState* gate,
+    static void doe(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int tps, const int* gate,
                     hipStream_t s) {
         launch_dslash(g, ls, in, out, 1, tps, gate, s);
     }
     static void deo_cg(const Geom& g, const LinkSet& ls, const double2* w, const double2* p, const double2* r,
-                       double2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mt) {
+                       double2* Ap, const int* gate, double* dpart, int tps, hipStream_t s, double mt) {
         launch_dslash_cg(g, ls, w, p, r, Ap, gate, dpart, tps, s, mt);
     }
 };
@@ -107,12 +107,12 @@ template <>
 struct Krylov<float2> {
     float2 *r, *p, *Ap, *w;
     explicit Krylov(stag_ctx* c) : r(c->r32), p(c->p32), Ap(c->Ap32), w(c->w32) {}
-    static void doe(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int tps, const MsState* gate,
+    static void doe(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int tps, const int* gate,
                     hipStream_t s) {
         launch_dslash32(g, ls, in, out, 1, tps, gate, s);
     }
     static void deo_cg(const Geom& g, const LinkSet& ls, const float2* w, const float2* p, const float2* r,
-                       float2* Ap, const MsState* gate, double* dpart, int tps, hipStream_t s, double mt) {
+                       float2* Ap, const int* gate, double* dpart, int tps, hipStream_t s, double mt) {
         launch_dslash32_cg(g, ls, w, p, r, Ap, gate, dpart, tps, s, mt);
     }
 };
@@ -159,12 +159,13 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             const int par = it_issued & 1;
             hipEvent_t a;
             prof_begin(c, &a);
-            Krylov<V>::doe(g, ls, K.p, K.w, c->tps, c->st, c->s);
+            const int* gate = &c->st->done[par];
+            Krylov<V>::doe(g, ls, K.p, K.w, c->tps, gate, c->s);
             prof_end(c, a, 0, rec);
             prof_begin(c, &a);
             // residual r_j sits in slot j % L of the ring starting at K.r
             const V* rj = K.r + (size_t)(it_issued % L) * 3 * g.vh;
-            Krylov<V>::deo_cg(g, ls, K.w, K.p, rj, K.Ap, c->st, c->dpart, c->tps, c->s, mt);
+            Krylov<V>::deo_cg(g, ls, K.w, K.p, rj, K.Ap, gate, c->dpart, c->tps, c->s, mt);
             prof_end(c, a, 1, rec);
             prof_begin(c, &a);
             launch_ms_step<V>(g, K.r, K.Ap, K.p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
@@ -172,7 +173,8 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             prof_end(c, a, 2, rec);
         }
         between_chunks(it_issued & 1);
-        hipMemcpyAsync(&c->done_host[slot], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, c->s);
+        // the flag the next iteration would read
+        hipMemcpyAsync(&c->done_host[slot], &c->st->done[it_issued & 1], sizeof(int), hipMemcpyDeviceToHost, c->s);
         hipEventRecord(c->chunk_ev[slot], c->s);
     };
     issue_chunk(0);

@@ -146,6 +146,7 @@ def load_library() -> ctypes.CDLL:
         "stag_surrogate_eval": (S, [H, P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_float)]),
         "stag_surrogate_force": (S, [H, P, D]),
         "stag_set_shift_window": (S, [H, I]),
+        "stag_batch_set_shift_window": (S, [H, I]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
         "stag_tune": (S, [H, I, I]),
@@ -440,6 +441,9 @@ class Batch:
                                "seconds": info.seconds, "latency": list(lat),
                                "true_resid": (np.array(list(res)).reshape(nsys, n) if true_resid else None),
                                "iters_sys": list(its), "iters_per_pole": np.array(list(ipp)).reshape(nsys, n)}
+
+    def set_shift_window(self, lag: int):
+        self._check(self.lib.stag_batch_set_shift_window(self.h, int(lag)))
 
     def tune(self, precision=0):
         us = (ctypes.c_double * 3)()

@@ -88,3 +88,50 @@ def test_tune_and_errors():
     with pytest.raises(stag.StagError) as e:
         C.solve([0.1, 0.1], rat, dev(np.zeros(C.vec_len(), dtype=np.complex128)))
     assert e.value.code == stag.STAG_ERR_NO_GAUGE
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shift_window_does_not_change_results(precision):
+    """Windows of 1, 2, 4 and 8 iterations give bitwise the same solutions."""
+    B, Us, masses, bs, bd = _setup(3, seed=3)
+    rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
+    ref = None
+    for lag in (1, 2, 4, 8):
+        log(f"batched window {lag} precision={precision}")
+        B.set_shift_window(lag)
+        x, info = B.solve(masses, rat, bd, precision=precision)
+        got = host(x)
+        if ref is None:
+            ref, ref_info = got, info
+        else:
+            assert info["iters_sys"] == ref_info["iters_sys"]
+            assert np.array_equal(got, ref), lag
+    with pytest.raises(stag.StagError):
+        B.set_shift_window(3)
+
+
+def test_large_instances_window_and_residuals():
+    """Many more tiles than the GPU runs at once (6 x 24^3x6 + 2 x 16^3x8 +
+    8^4, 4 right-hand sides: 2216 tiles of 128 sites) and the 12-pole table:
+    window 8 equals window 1 bitwise and every system reaches the FP64 true
+    residual.  This is where a block that starts after another block of the
+    same launch has recorded a stop must still apply the pending window."""
+    dims = [(24, 24, 24, 6)] * 6 + [(16, 16, 16, 8)] * 2 + [(8, 8, 8, 8)]
+    rng = synth.make_rng(501, 0)
+    Us = [synth.random_su3_near_identity(d, 0.2, rng) for d in dims]
+    masses = list(rng.uniform(0.005, 0.05, len(dims)))
+    nrhs = 4
+    b = np.concatenate([synth.gaussian_half_vector(d, rng).reshape(-1) for d in dims for _ in range(nrhs)])
+    B = stag.Batch(dims, nrhs)
+    for i, U in enumerate(Us):
+        B.set_gauge(i, dev(U))
+    rat = synth.load_rational("xm025_n12_m0.005")
+    out = {}
+    for lag in (1, 8):
+        log(f"large batch, window {lag}")
+        B.set_shift_window(lag)
+        x, info = B.solve(masses, rat, dev(b), precision=0, tol=1e-10)
+        out[lag] = (host(x), info)
+        assert info["true_resid"].max() < 1e-10, info["true_resid"].max()
+    assert out[1][1]["iters_sys"] == out[8][1]["iters_sys"]
+    assert np.array_equal(out[1][0], out[8][0])

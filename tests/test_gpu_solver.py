@@ -83,6 +83,13 @@ def test_full_size_32c8_twelve_poles():
     assert np.allclose(info["true_resid"], res, rtol=1e-2, atol=1e-14)
     expect_sum = rat["c0"] * b + sum(c * x for c, x in zip(rat["residue"], xs))
     assert rel_err(s, expect_sum) < 1e-13
+    # the default window (8) against per-iteration updates, bitwise, at the
+    # full size where the step kernel runs many more blocks than the GPU holds
+    lat.set_shift_window(1)
+    xs1, s1, info1 = _solve(lat, dims, 0.005, rat, 1e-10, b)
+    assert info1["iters"] == info["iters"]
+    for x, x1 in zip(xs, xs1):
+        assert np.array_equal(x, x1)
 
 
 def test_krylov_bound_unit_gauge():
