@@ -190,6 +190,34 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// Tiles of SB consecutive half-lattice sites for a kernel whose neighbour
+// reads reach +-1 in every direction.  When tiles tile the (z, t) planes
+// evenly (W tiles per plane, or one tile per SB/plane planes) and the number
+// of tile rows along z is a multiple of 8, XCD k gets the z-slab k of 8 over
+// all t, so only the two z faces of each slab are read from another XCD's part
+// of the lattice (t-slices, the contiguous ranges, would put both t faces of
+// every slice there).  Otherwise the contiguous-range map above.  A
+// permutation of [0, nb).
+__device__ __forceinline__ int xcd_tile_slab(int b, int nb, const Geom& g, int SB) {
+    const int plane = g.nx * g.ny / 2;  // half-lattice sites of one (z, t) plane
+    int NZ = 0, W = 0;                  // tile rows along z, tiles per row
+    if (plane % SB == 0) {
+        NZ = g.nz;
+        W = plane / SB;
+    } else if (SB % plane == 0 && g.nz % (SB / plane) == 0) {
+        NZ = g.nz / (SB / plane);
+        W = 1;
+    }
+    if (NZ > 0 && NZ % 8 == 0 && nb % 8 == 0 && (long long)nb * SB == g.vh) {
+        const int nz8 = NZ / 8;
+        const int xcd = b % 8, j = b / 8;
+        const int w = j % W, rest = j / W;
+        const int zl = rest % nz8, t = rest / nz8;
+        return (t * NZ + xcd * nz8 + zl) * W + w;
+    }
+    return xcd_tile(b, nb);
+}
+
 // ---------------------------------------------------------------------------
 // Multi-shift CG state kept on the device (scalars never leave the GPU inside
 // the iteration loop).

@@ -44,7 +44,7 @@ struct stag_ctx {
     double* scal_host = nullptr;         // pinned
     int* done_host = nullptr;            // pinned [2]
     bool has_gauge = false;
-    int tps = 2;                         // threads per site in the Dslash
+    int tps = 4;                         // threads per site in the Dslash
     int chunk = 16;                      // iterations enqueued between convergence polls
     int lag = 8;                         // shift-update window of the multi-shift solver
     // profiling of the solver kernels (hipEvent pairs)

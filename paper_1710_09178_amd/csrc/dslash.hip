@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash(Geom g, Link L, const typenam
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int slice = wave % TPS, sgrp = wave / TPS;
     const int j = sgrp * 64 + lane;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile_slab(blockIdx.x, gridDim.x, g, SB);
     const int cb = tile * SB + j;
     C acc[3];
 #pragma unroll

@@ -15,6 +15,8 @@ CASES = [
     ((2, 2, 2, 2), 0.5),      # smallest lattice: every neighbour wraps
     ((8, 6, 4, 10), 0.4),     # Vh = 960: several tiles and a ragged tail
     ((6, 2, 8, 4), 1.0),      # strongly disordered links
+    ((8, 8, 16, 4), 0.3),     # z-slab tile map with two (z, t) planes per tile (4 threads per site)
+    ((16, 16, 16, 8), 0.2),   # z-slab tile map for every work split
 ]
 
 
@@ -51,13 +53,15 @@ def test_mdagm_matches_oracle(dims, eps):
     assert rel_err(got, exp) < 1e-14
 
 
-def test_full_size_32c8():
+@pytest.mark.parametrize("tps", [1, 2, 4])
+def test_full_size_32c8(tps):
     """32^3x8, eps = 0.2: every output element of D_oe and D_eo."""
     dims = (32, 32, 32, 8)
-    log("dslash parity at 32^3x8")
+    log(f"dslash parity at 32^3x8 tps={tps}")
     rng = synth.make_rng(1, 0)
     U = synth.random_su3_near_identity(dims, 0.2, rng)
     lat = lattice(dims, U)
+    lat.tune(tps, 16)
     for out_par in (1, 0):
         vin = synth.gaussian_half_vector(dims, rng)
         x = lat.vec_import(dev(vin), 1 - out_par)
