@@ -348,6 +348,11 @@ stag_status stag_profile_enable(stag_handle h, int max_launches);
  * index 0 = D_oe (odd <- even), 1 = D_eo with the fused CG epilogue,
  * 2 = fused multi-shift vector update.  Host arrays of length 3, may be NULL. */
 stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
+/* Solvers replay each chunk of iterations from a hipGraph captured on first
+ * use (kernel nodes only; up to 8 cached per handle, keyed by every launch
+ * argument) unless profiling or reliable updates need per-launch work.  on = 0
+ * launches every kernel individually.  Results are identical either way. */
+stag_status stag_set_graphs(stag_handle h, int on);
 /* Multi-shift solver: the shifted solutions and directions are updated once
  * per window of `lag` iterations (1..8, default 8), each read and written once
  * per window; the results do not depend on the window.  Measurement/tuning. */

@@ -236,6 +236,7 @@ stag_status stag_destroy(stag_handle c) {
     if (c->scal_host) hipHostFree(c->scal_host);
     if (c->done_host) hipHostFree(c->done_host);
     for (auto ev : c->prof_ev) hipEventDestroy(ev);
+    for (auto& gr : c->graphs) hipGraphExecDestroy(gr.exec);
     hipEvent_t evs[] = {c->ev_in, c->ev_out, c->chunk_ev[0], c->chunk_ev[1]};
     for (auto ev : evs)
         if (ev) hipEventDestroy(ev);
@@ -703,6 +704,14 @@ stag_status stag_profile_read(stag_handle c, double ms[3], long counts[3]) {
         if (ms) ms[i] = c->prof_ms[i];
         if (counts) counts[i] = c->prof_cnt[i];
     }
+    return STAG_OK;
+}
+
+// Replay of captured iteration chunks on (1) or off (0).
+stag_status stag_set_graphs(stag_handle c, int on) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    c->use_graph = on ? 1 : 0;
     return STAG_OK;
 }
 

@@ -47,6 +47,15 @@ struct stag_ctx {
     int tps = 4;                         // threads per site in the Dslash
     int chunk = 16;                      // iterations enqueued between convergence polls
     int lag = 8;                         // shift-update window of the multi-shift solver
+    int use_graph = 1;                   // replay iteration chunks from captured hipGraphs
+    // captured iteration chunks, keyed by every argument their launches take
+    struct ChunkGraph {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec = nullptr;
+        unsigned long long used = 0;
+    };
+    std::vector<ChunkGraph> graphs;
+    unsigned long long graph_clock = 0;
     // profiling of the solver kernels (hipEvent pairs)
     int prof_on = 0;
     std::vector<hipEvent_t> prof_ev;

@@ -142,19 +142,63 @@ void init_state(MsState* h, int n, const double* pole, const double* residue, do
     h->it[0].beta_old = 0.0;
 }
 
+// Everything the launches of one chunk depend on; two chunks with equal keys
+// enqueue identical work, so a captured graph of one can replay the other.
+struct ChunkKey {
+    Geom g;
+    LinkSet ls;
+    const void* vec[4];
+    VecPtrs X, P;
+    const void* st;
+    const void* dpart;
+    const void* qpart[2];
+    double mt;
+    int tps, lag, chunk, nb2, v64;
+};
+
+hipGraphExec_t cached_graph(stag_ctx* c, const ChunkKey& key) {
+    const unsigned char* k = reinterpret_cast<const unsigned char*>(&key);
+    for (auto& e : c->graphs)
+        if (e.key.size() == sizeof(ChunkKey) && std::memcmp(e.key.data(), k, sizeof(ChunkKey)) == 0) {
+            e.used = ++c->graph_clock;
+            return e.exec;
+        }
+    return nullptr;
+}
+
+void store_graph(stag_ctx* c, const ChunkKey& key, hipGraphExec_t exec) {
+    constexpr size_t kMaxGraphs = 8;
+    if (c->graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < c->graphs.size(); ++i)
+            if (c->graphs[i].used < c->graphs[lru].used) lru = i;
+        hipGraphExecDestroy(c->graphs[lru].exec);
+        c->graphs.erase(c->graphs.begin() + lru);
+    }
+    stag_ctx::ChunkGraph e;
+    const unsigned char* k = reinterpret_cast<const unsigned char*>(&key);
+    e.key.assign(k, k + sizeof(ChunkKey));
+    e.exec = exec;
+    e.used = ++c->graph_clock;
+    c->graphs.push_back(std::move(e));
+}
+
 // Enqueue iterations in chunks and poll the device "done" flag once per chunk,
 // keeping two chunks in flight.  between_chunks(par_next) may enqueue extra
 // work after every chunk (reliable updates); it receives the parity of the
-// next iteration.
+// next iteration.  Without extra work or profiling, a chunk is captured once
+// into a hipGraph (kernel nodes only) and replayed: the chunk length is a
+// multiple of 2 and of the window, so every chunk repeats the same launches.
 template <class V, class Between>
 stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtrs X, VecPtrs P, int chunk,
-                           EvRec& rec, Between between_chunks, bool two_in_flight = true) {
+                           EvRec& rec, Between between_chunks, bool two_in_flight = true,
+                           bool extra_work = false) {
     const Geom& g = c->g;
     const double mt = c->st_host->mass_term;
     const int L = c->st_host->lag;
     const int nb2 = dslash_grid(g, c->tps);
     int it_issued = 0;
-    auto issue_chunk = [&](int slot) {
+    auto enqueue_chunk = [&]() {
         for (int it = 0; it < chunk; ++it, ++it_issued) {
             const int par = it_issued & 1;
             hipEvent_t a;
@@ -171,6 +215,49 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             launch_ms_step<V>(g, K.r, K.Ap, K.p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
                               c->s);
             prof_end(c, a, 2, rec);
+        }
+    };
+    hipGraphExec_t exec = nullptr;
+    if (c->use_graph && !c->prof_on && !extra_work && chunk % 2 == 0 && chunk % L == 0) {
+        ChunkKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.g = g;
+        key.ls = ls;
+        key.vec[0] = K.r;
+        key.vec[1] = K.p;
+        key.vec[2] = K.Ap;
+        key.vec[3] = K.w;
+        key.X = X;
+        key.P = P;
+        key.st = c->st;
+        key.dpart = c->dpart;
+        key.qpart[0] = c->qpart[0];
+        key.qpart[1] = c->qpart[1];
+        key.mt = mt;
+        key.tps = c->tps;
+        key.lag = L;
+        key.chunk = chunk;
+        key.nb2 = nb2;
+        key.v64 = sizeof(V) == sizeof(double2);
+        exec = cached_graph(c, key);
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            HIP_OR_FAIL(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+            enqueue_chunk();
+            HIP_OR_FAIL(c, hipStreamEndCapture(c->s, &graph));
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(c, STAG_ERR_HIP, "hipGraphInstantiate failed");
+            store_graph(c, key, exec);
+            it_issued = 0;
+        }
+    }
+    auto issue_chunk = [&](int slot) {
+        if (exec) {
+            hipGraphLaunch(exec, c->s);
+            it_issued += chunk;
+        } else {
+            enqueue_chunk();
         }
         between_chunks(it_issued & 1);
         // the flag the next iteration would read
@@ -273,7 +360,7 @@ stag_status refine_pole(stag_ctx* c, const LinkSet& ls, double mass, double pole
         VecPtrs X{}, P{};
         X.p[0] = x;
         stag_status e = run_iterations<float2>(
-            c, ls, K, X, P, every, rec, [&](int par_next) { reliable(c->qpart[par_next]); }, false);
+            c, ls, K, X, P, every, rec, [&](int par_next) { reliable(c->qpart[par_next]); }, false, true);
         if (e) return e;
         HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
         HIP_OR_FAIL(c, hipStreamSynchronize(c->s));

@@ -146,6 +146,7 @@ def load_library() -> ctypes.CDLL:
         "stag_surrogate_eval": (S, [H, P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_float)]),
         "stag_surrogate_force": (S, [H, P, D]),
         "stag_set_shift_window": (S, [H, I]),
+        "stag_set_graphs": (S, [H, I]),
         "stag_batch_set_shift_window": (S, [H, I]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
@@ -359,6 +360,9 @@ class Lattice:
     # ---- measurement / tuning
     def set_shift_window(self, lag: int):
         self._check(self.lib.stag_set_shift_window(self.h, int(lag)))
+
+    def set_graphs(self, on: bool):
+        self._check(self.lib.stag_set_graphs(self.h, int(bool(on))))
 
     def profile_enable(self, max_launches: int):
         self._check(self.lib.stag_profile_enable(self.h, int(max_launches)))
