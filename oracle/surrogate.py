@@ -8,13 +8,16 @@ is gauge covariant by construction:
       S_dn = U_nu(x+mu-nu)^dag U_mu(x-nu)^dag U_nu(x-nu)
   in the order nu = the three directions other than mu ascending, up then down
   (6 channels; U_mu(x) S_j is a closed loop through the link);
+* an optional seventh channel: an auxiliary force field G(x, mu) supplied by
+  the caller (8 components per link, transforming like a force), used as is;
 * invariant inputs: Re and Im tr(U_mu(x) S_j) for the 6 channels, the site
-  parity (+-1) and the staggered sign of the link (+-1), padded with zeros
-  to F_IN = 16;
+  parity (+-1), the staggered sign of the link (+-1), and the cosine of the
+  angle between G and the sum of the six staple forces (0 without G), padded
+  with zeros to F_IN = 16;
 * MLP: h1 = silu(W1 f + b1), h2 = silu(W2 h1 + b2), c = W3 h2 + b3, widths
-  16 -> 64 -> 64 -> 8 (only the first 6 outputs are used);
-* force: F_a(x, mu) = sum_j c_j Im tr(T_a U_mu(x) S_j), i.e. a learned
-  combination of plaquette-type forces, each transforming like the gauge force.
+  16 -> 64 -> 64 -> 8 (the first 7 outputs are used);
+* force: F_a(x, mu) = sum_{j<6} c_j Im tr(T_a U_mu(x) S_j) + c_6 G_a(x, mu):
+  a learned, link-dependent combination of covariant force fields.
 
 Loss: L = (1/N) sum over links and a of (F_s - F_target)^2, N = number of
 links.  Gradients are written out by hand (the reference for the GPU's
@@ -32,13 +35,14 @@ import numpy as np
 from . import lattice as L
 from .su3 import T
 
-F_IN, HID, N_OUT, N_CH = 16, 64, 8, 6
+F_IN, HID, N_OUT, N_CH = 16, 64, 8, 7
+N_STAPLE = 6
 
 
 def channels(U: np.ndarray, dims) -> np.ndarray:
     """Staple channels, shape (Nt,Nz,Ny,Nx,4,6,3,3)."""
     nx, ny, nz, nt = dims
-    out = np.zeros((nt, nz, ny, nx, 4, N_CH, 3, 3), dtype=np.complex128)
+    out = np.zeros((nt, nz, ny, nx, 4, N_STAPLE, 3, 3), dtype=np.complex128)
     dag = lambda m: np.swapaxes(m, -1, -2).conj()
     mm = lambda a, b: np.einsum("...ij,...jk->...ik", a, b)
     for mu in range(4):
@@ -55,26 +59,38 @@ def channels(U: np.ndarray, dims) -> np.ndarray:
     return out
 
 
-def features(U: np.ndarray, dims):
+def features(U: np.ndarray, dims, aux=None):
     """Per-link inputs (N_links, F_IN) in canonical link order (site, mu), and
-    the loops U S_j (N_links, 6, 3, 3)."""
+    the loops U S_j (N_links, 6, 3, 3).  aux: optional auxiliary force field
+    (Nt,Nz,Ny,Nx,4,8)."""
     S = channels(U, dims)
     loops = np.einsum("...ij,...cjk->...cik", U, S)
     tr = np.trace(loops, axis1=-2, axis2=-1)
     V = L.volume(dims)
     f = np.zeros((V, 4, F_IN))
-    f[..., 0:12:2] = tr.real.reshape(V, 4, N_CH)
-    f[..., 1:12:2] = tr.imag.reshape(V, 4, N_CH)
+    f[..., 0:12:2] = tr.real.reshape(V, 4, N_STAPLE)
+    f[..., 1:12:2] = tr.imag.reshape(V, 4, N_STAPLE)
     par = L.parity(dims).reshape(V)
     f[..., 12] = np.where(par == 0, 1.0, -1.0)[:, None]
     for mu in range(4):
         f[:, mu, 13] = L.staggered_sign(dims, mu).reshape(V)
-    return f.reshape(4 * V, F_IN), loops.reshape(4 * V, N_CH, 3, 3)
+    f = f.reshape(4 * V, F_IN)
+    loops = loops.reshape(4 * V, N_STAPLE, 3, 3)
+    if aux is not None:
+        g = np.asarray(aux, dtype=np.float64).reshape(4 * V, 8)
+        gs = basis(loops)[:, :N_STAPLE, :].sum(1)
+        f[:, 14] = np.einsum("na,na->n", g, gs) / (np.linalg.norm(g, axis=1) * np.linalg.norm(gs, axis=1) + 1e-30)
+    return f, loops
 
 
-def basis(loops: np.ndarray) -> np.ndarray:
-    """B[l, j, a] = Im tr(T_a loop_j) (the force of channel j), shape (N, 6, 8)."""
-    return np.einsum("aij,ncji->nca", T, loops).imag
+def basis(loops: np.ndarray, aux=None) -> np.ndarray:
+    """B[l, j, a]: Im tr(T_a loop_j) (the force of staple channel j) for j < 6
+    and the auxiliary force for j = 6 (zero without one), shape (N, 7, 8)."""
+    B = np.zeros((loops.shape[0], N_CH, 8))
+    B[:, :N_STAPLE, :] = np.einsum("aij,ncji->nca", T, loops).imag
+    if aux is not None:
+        B[:, N_STAPLE, :] = np.asarray(aux, dtype=np.float64).reshape(-1, 8)
+    return B
 
 
 def silu(x):
@@ -153,9 +169,9 @@ def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         params[key] -= lr * mh / (np.sqrt(vh) + eps)
 
 
-def surrogate_force(params, U, dims, mode="fp64") -> np.ndarray:
+def surrogate_force(params, U, dims, mode="fp64", aux=None) -> np.ndarray:
     """The model's force field, shape (Nt,Nz,Ny,Nx,4,8)."""
-    f, loops = features(U, dims)
-    F, _ = forward(params, f, basis(loops), mode)
+    f, loops = features(U, dims, aux)
+    F, _ = forward(params, f, basis(loops, aux), mode)
     nx, ny, nz, nt = dims
     return F.reshape(nt, nz, ny, nx, 4, 8)

@@ -1,7 +1,9 @@
 """Pins for the oracle of the learned force model: the channel basis
-reproduces the gauge force, gauge covariance, finite-difference gradients,
-bfloat16 rounding and Adam."""
+reproduces the gauge force, the auxiliary channel passes a force through,
+gauge covariance (with and without the auxiliary field), finite-difference
+gradients, bfloat16 rounding and Adam."""
 import numpy as np
+import pytest
 
 import synth
 from oracle import gauge, lattice as L, surrogate as S
@@ -28,7 +30,32 @@ def test_basis_with_constant_coefficients_is_the_gauge_force():
     assert abs(f[:, 0:12:2].sum() - 4 * plaq_sum) < 1e-9
 
 
-def test_model_force_is_gauge_covariant():
+def _rotate(Om, F):
+    """A force field transformed by the gauge transformation Om (adjoint at x)."""
+    return to_coords(np.einsum("...ij,...mjk,...lk->...mil", Om, to_matrix(F), Om.conj()))
+
+
+def test_auxiliary_channel_alone_reproduces_the_auxiliary_force():
+    """With W3 = 0 and b3 = e_6 every link takes c_6 = 1 and nothing else, so
+    the model force is the auxiliary field itself; its feature is the cosine
+    of the angle with the staple sum, so the field along the staple sum gives 1."""
+    U = _U(4)
+    rng = synth.make_rng(600, 5)
+    params = S.init_params(rng)
+    params["W3"][:] = 0.0
+    params["b3"][:] = 0.0
+    params["b3"][6] = 1.0
+    aux = rng.standard_normal((DIMS[3], DIMS[2], DIMS[1], DIMS[0], 4, 8))
+    assert np.abs(S.surrogate_force(params, U, DIMS, aux=aux) - aux).max() < 1e-13
+    gforce = gauge.gauge_force(U, DIMS, 3.0)     # -(beta/3) times the staple sum
+    f, _ = S.features(U, DIMS, aux=-gforce)
+    assert np.abs(f[:, 14] - 1.0).max() < 1e-12
+    f0, _ = S.features(U, DIMS)
+    assert np.array_equal(f0[:, 14], np.zeros(f0.shape[0]))
+
+
+@pytest.mark.parametrize("with_aux", [False, True])
+def test_model_force_is_gauge_covariant(with_aux):
     U = _U(1)
     rng = synth.make_rng(600, 9)
     params = S.init_params(rng)
@@ -37,10 +64,10 @@ def test_model_force_is_gauge_covariant():
     Ug = np.empty_like(U)
     for mu in range(4):
         Ug[..., mu, :, :] = np.einsum("...ij,...jk,...lk->...il", Om, U[..., mu, :, :], L.fwd(Om, mu).conj())
-    F = S.surrogate_force(params, U, DIMS)
-    Fg = S.surrogate_force(params, Ug, DIMS)
-    rot = to_coords(np.einsum("...ij,...mjk,...lk->...mil", Om, to_matrix(F), Om.conj()))
-    assert np.abs(rot - Fg).max() < 1e-10 * np.abs(F).max()
+    aux = rng.standard_normal((DIMS[3], DIMS[2], DIMS[1], DIMS[0], 4, 8)) if with_aux else None
+    F = S.surrogate_force(params, U, DIMS, aux=aux)
+    Fg = S.surrogate_force(params, Ug, DIMS, aux=None if aux is None else _rotate(Om, aux))
+    assert np.abs(_rotate(Om, F) - Fg).max() < 1e-10 * np.abs(F).max()
 
 
 def test_gradients_match_finite_differences():
@@ -49,8 +76,9 @@ def test_gradients_match_finite_differences():
     params = S.init_params(rng)
     params["W3"] = rng.standard_normal(params["W3"].shape) * 0.3
     params["b1"] = rng.standard_normal(S.HID) * 0.1
-    f, loops = S.features(U, DIMS)
-    B = S.basis(loops)
+    aux = rng.standard_normal((DIMS[3], DIMS[2], DIMS[1], DIMS[0], 4, 8))
+    f, loops = S.features(U, DIMS, aux)
+    B = S.basis(loops, aux)
     target = rng.standard_normal((f.shape[0], 8))
     _, g = S.loss_and_grad(params, f, B, target)
     h = 1e-6
