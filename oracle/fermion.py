@@ -52,11 +52,16 @@ def fermion_force(U, dims, mass, phi, rat, tol) -> np.ndarray:
     """F_a(x, mu) = 2 Im tr(T_a s U_mu(x) W(x, mu)), shape (Nt,Nz,Ny,Nx,4,8)."""
     res = rat["residue"] if isinstance(rat, dict) else rat.residue
     sol = rational_solve(U, dims, mass, phi, rat, tol)
+    return force_from_solutions(U, dims, sol["x"], res)
+
+
+def force_from_solutions(U, dims, xs, res) -> np.ndarray:
+    """The force above from given X_k (even half vectors) and residues c_k."""
     par = L.parity(dims)
     eps = np.where(par == 0, 1.0, -1.0)
     # chi_k: X_k on even sites, Y_k = D_oe X_k on odd sites
     chis = []
-    for x in sol["x"]:
+    for x in xs:
         y = dirac.dslash_half(U, x, dims, 1)
         chis.append(L.half_to_full(x, dims, 0) + L.half_to_full(y, dims, 1))
     ut = dirac.dressed_links(U, dims)
