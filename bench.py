@@ -425,21 +425,22 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     return out
 
 
-def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.0):
+def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.0, inner_iters=100):
     """RHMC at 16^3x8 (beta 5.4, m 0.02, 12-pole rational tables, tau 1, 20
     leapfrog steps, MD tolerance 1e-8, action 1e-10) from a seeded hot start,
     thermalised by 60 pure-gauge and 5 dynamical trajectories (all accepted).
     sec_per_trajectory: n_exact exact-force trajectories continuing the chain.
 
     With the learned force model: exact-force trajectories record n_pairs
-    (U, force) pairs, the model is trained on them on the GPU, and chains of
-    n_traj trajectories start from the same configuration with the same
-    momenta and pseudofermions: exact force on every kick; for exact_every in
-    (2, 4) the model replacing the exact force between exact kicks, the model
-    on the inner scale of a two-time-scale leapfrog with the exact force
-    correcting it on the outer scale, and the ablation without a model (exact
-    force on the outer scale only).  Accept/reject always uses the exact
-    action."""
+    (U, force) pairs, each with the force of a solve stopped after
+    inner_iters iterations as the model's auxiliary channel; the model is
+    trained on them on the GPU; then chains of n_traj trajectories start from
+    the same configuration with the same momenta and pseudofermions: exact
+    force on every kick, and for exact_every in (2, 4) a two-time-scale
+    leapfrog with the exact force on the outer scale and on the inner scale
+    (a) nothing (the ablation), (b) the truncated-solve force alone, (c) the
+    trained model (which also sees the truncated-solve force).
+    Accept/reject always uses the exact action."""
     import numpy as np
     import torch
 
@@ -487,7 +488,7 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
     t0 = time.perf_counter()
     while sur.pairs < n_pairs:
         rec.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, surrogate=sur, record_pairs=True,
-                                  traj_index=t, **kw))
+                                  inner_iters=inner_iters, traj_index=t, **kw))
         t += 1
     t_rec = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -498,23 +499,32 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
         if epochs == 10:
             lr = 3e-4
     t_train = time.perf_counter() - t0
+    # the model that is the truncated-solve force alone (c_6 = 1)
+    ident = Surrogate(lat, 0)
+    p = np.zeros(ident.n_params, dtype=np.float32)
+    p[-8 + 6] = 1.0
+    ident.set_params(p)
 
-    def force_error(n=4):
-        errs = []
+    def force_errors(n=4):
+        out_m, out_t = [], []
         xs = [lat.new_vec() for _ in r_h["pole"]]
         phi = lat.new_vec()
-        mom = lat.new_mom()
+        mom, aux = lat.new_mom(), lat.new_mom()
         for j in range(n):
             xi = lat.random_source(99, 100000 + j)
             lat.multishift_solve(mass, r_h, 1e-10, 100000, xi, xs, phi, true_resid=False)
             lat.fermion_force(mass, r_f, 1e-10, 100000, phi, mom, 0.0)
+            lat.fermion_force(mass, r_f, 1e-30, inner_iters, phi, aux, 0.0, allow_not_converged=True)
+            sur.set_aux(aux)
             loss, _ = sur.eval(mom)
-            ref = float((mom * mom).sum().item()) / (lat.V * 4)
-            errs.append(float(np.sqrt(loss / ref)))
-        return errs
+            sur.set_aux(None)
+            ref = float((mom * mom).sum().item())
+            out_m.append(float(np.sqrt(loss * lat.V * 4 / ref)))
+            out_t.append(float(torch.linalg.vector_norm(mom - aux).item() / np.sqrt(ref)))
+        return out_m, out_t
 
     U_start = lat.get_gauge()
-    err = force_error()
+    err_model, err_trunc = force_errors()
 
     def chain(**extra):
         lat.set_gauge(U_start)
@@ -528,18 +538,22 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
 
     chains = {"exact": chain()}
     for every in (2, 4):
-        chains[f"model_replaces_exact_every_{every}"] = chain(surrogate=sur, exact_every=every)
-        chains[f"model_inner_scale_exact_every_{every}"] = chain(surrogate=sur, exact_every=every, coarse_force=True)
-        chains[f"ablation_no_model_exact_every_{every}"] = chain(exact_every=every, coarse_force=True)
+        ms = dict(exact_every=every, coarse_force=True)
+        chains[f"ablation_no_inner_force_exact_every_{every}"] = chain(**ms)
+        chains[f"inner_truncated_solve_exact_every_{every}"] = chain(surrogate=ident, inner_iters=inner_iters, **ms)
+        chains[f"inner_learned_model_exact_every_{every}"] = chain(surrogate=sur, inner_iters=inner_iters, **ms)
     for k, v in chains.items():
         v["speedup_vs_exact"] = round(chains["exact"]["sec_per_traj"] / v["sec_per_traj"], 3)
     out["learned_force_rhmc"] = {
-        "workload": "the same RHMC; the learned model stands in for the pseudofermion force between exact kicks",
-        "pairs": n_pairs, "recording_trajectories": len(rec), "recording_seconds": round(t_rec, 2),
+        "workload": "the same RHMC; two-time-scale leapfrog, exact force on the outer scale",
+        "inner_iters": inner_iters, "pairs": n_pairs, "recording_trajectories": len(rec),
+        "recording_seconds": round(t_rec, 2),
         "recording_acceptance": round(float(np.mean([r["accepted"] for r in rec])), 3),
         "train_epochs": epochs, "train_seconds": round(t_train, 2),
         "train_loss_first_last": [losses[0], losses[-1]],
-        "force_rel_error_model": [round(e, 4) for e in err], "force_rel_error_without_model": 1.0,
+        "force_rel_error_model": [round(e, 4) for e in err_model],
+        "force_rel_error_truncated_solve": [round(e, 4) for e in err_trunc],
+        "force_rel_error_without_inner_force": 1.0,
         "chains": chains}
     return out
 

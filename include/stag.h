@@ -213,9 +213,12 @@ stag_status stag_philox(const uint32_t ctr[4], const uint32_t key[2], size_t n, 
 
 /* A gauge-covariant force model tied to lattice h: per link, an MLP
  * (16 -> 64 -> 64 -> 8, SiLU; bf16 matrix-core products, FP32 accumulation)
- * maps gauge-invariant loop traces of the link's six plaquette staples S_j to
- * coefficients c_j, and F_a = sum_j c_j Im tr(T_a U S_j).  capacity = number
- * of (gauge field, force) training pairs the device dataset can hold. */
+ * maps gauge-invariant inputs (Re/Im tr of U S_j for the link's six plaquette
+ * staples S_j, site parity, staggered sign, and the cosine of the auxiliary
+ * force G with the staple sum) to coefficients c_j, and
+ * F_a = sum_{j<6} c_j Im tr(T_a U S_j) + c_6 G_a (G = 0 without one).
+ * capacity = number of (gauge field, force) training pairs the device dataset
+ * can hold. */
 typedef struct stag_surrogate* stag_surrogate_handle;
 stag_status stag_surrogate_create(stag_surrogate_handle* out, stag_handle h, int capacity, uint64_t seed);
 stag_status stag_surrogate_destroy(stag_surrogate_handle s);
@@ -224,6 +227,10 @@ const char* stag_surrogate_last_error(stag_surrogate_handle s);
 int stag_surrogate_param_count(void);
 /* Read (get_out) and/or replace (set_in, resets the optimiser) the parameters; host arrays. */
 stag_status stag_surrogate_params(stag_surrogate_handle s, float* get_out, const float* set_in);
+/* Auxiliary force field of the model (device, internal momentum layout, read
+ * by later add_pair / eval / force calls) or NULL for none: the seventh
+ * channel, weighted per link like the six staple forces. */
+stag_status stag_surrogate_set_aux(stag_surrogate_handle s, const void* aux_force);
 /* Training pairs stored so far, and the dataset capacity (0 for a NULL handle). */
 int stag_surrogate_pair_count(stag_surrogate_handle s);
 int stag_surrogate_capacity(stag_surrogate_handle s);
@@ -266,6 +273,10 @@ typedef struct {
     int record_pairs;             /* 1, with a model and exact_every == 1: every pseudofermion force of
                                      the trajectory is also stored as a training pair of the model,
                                      until its dataset is full */
+    int inner_iters;              /* > 0, with a model: wherever the model is evaluated (and for every
+                                     recorded pair) its auxiliary force is the pseudofermion force of
+                                     a multi-shift solve of r_md stopped after inner_iters iterations;
+                                     the model's auxiliary field is left NULL afterwards */
 } stag_hmc_params;
 
 typedef struct {

@@ -229,7 +229,7 @@ stag_status stag_destroy(stag_handle c) {
     void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->r32, c->p32, c->Ap32, c->w32,
                     c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
-                    c->gpart, c->scal, c->mom_tmp};
+                    c->gpart, c->scal, c->mom_tmp, c->mom_aux};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (c->st_host) hipHostFree(c->st_host);
@@ -553,6 +553,12 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         stag_status e2 = dmalloc(c, &c->mom_tmp, (size_t)64 * c->g.vh * sizeof(double));
         if (e2) return e2;
     }
+    if (p->inner_iters < 0 || (p->inner_iters > 0 && !p->surrogate))
+        return fail(c, STAG_ERR_INVALID_ARG, "inner_iters must be >= 0 and needs a model");
+    if (p->inner_iters > 0 && !c->mom_aux) {
+        stag_status e2 = dmalloc(c, &c->mom_aux, (size_t)64 * c->g.vh * sizeof(double));
+        if (e2) return e2;
+    }
     if ((e = enter(c))) return e;
     const Geom& g = c->g;
     const size_t mb = (size_t)64 * g.vh * sizeof(double);
@@ -606,29 +612,38 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     int kick_index = 0;
     const int every = p->exact_every < 1 ? 1 : p->exact_every;
     const bool sched = p->surrogate != nullptr || p->coarse_force;
+    // the model's auxiliary channel: the pseudofermion force of the current
+    // links from the multi-shift solve of r_md stopped after inner_iters
+    // iterations (a deterministic function of the links and phi)
+    auto truncated_aux = [&]() -> stag_status {
+        SolveResult rt;
+        stag_status e2 = fermion_force_impl(c, p->mass, &p->r_md, 0.0, p->inner_iters, c->phi, c->mom_aux, 0.0, rt);
+        if (e2) return e2;
+        if (rt.nonfinite) return fail(c, STAG_ERR_NONFINITE, "non-finite value in the truncated solve");
+        acc(rt);
+        return stag_surrogate_set_aux(p->surrogate, c->mom_aux);
+    };
+    auto model_force = [&](double h) -> stag_status {
+        stag_status e2 = p->inner_iters > 0 ? truncated_aux() : STAG_OK;
+        if (!e2) e2 = stag_surrogate_force(p->surrogate, c->mom, h);
+        if (e2) return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
+        return STAG_OK;
+    };
     auto kick = [&](double h) -> stag_status {
         launch_gauge_force(g, c->links, p->beta, c->mom, h, c->s);
         const bool exact = !sched || (kick_index % every) == 0;
         ++kick_index;
         if (!ferm) return STAG_OK;
-        if (!exact) {
-            if (p->surrogate) {
-                stag_status e2 = stag_surrogate_force(p->surrogate, c->mom, h);
-                if (e2) return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
-            }
-            return STAG_OK;
-        }
+        if (!exact) return p->surrogate ? model_force(h) : STAG_OK;
         const double hf = p->coarse_force ? h * every : h;
         stag_status e2;
-        if (p->coarse_force && p->surrogate && every > 1) {
-            // inner-scale model impulse h F_s, outer-scale correction hf (F - F_s)
-            if ((e2 = stag_surrogate_force(p->surrogate, c->mom, h - hf)))
-                return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
-        }
+        // inner-scale model impulse h F_s, outer-scale correction hf (F - F_s)
+        if (p->coarse_force && p->surrogate && every > 1 && (e2 = model_force(h - hf))) return e2;
         if (p->record_pairs) {
             if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom_tmp, 0.0, res)))
                 return e2;
             if ((e2 = finish_solve_status(c, res))) return e2;
+            if (p->inner_iters > 0 && (e2 = truncated_aux())) return e2;
             if (stag_surrogate_pair_count(p->surrogate) < stag_surrogate_capacity(p->surrogate) &&
                 (e2 = stag_surrogate_add_pair(p->surrogate, c->mom_tmp)))
                 return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
@@ -656,6 +671,7 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         if ((e = finish_solve_status(c, res))) return e;
         acc(res);
     }
+    if (p->inner_iters > 0) stag_surrogate_set_aux(p->surrogate, nullptr);
     I.dH = (I.K_new + I.Sg_new + I.Sf_new) - (I.K_old + I.Sg_old + I.Sf_old);
     double u = p->inject_u;
     if (u < 0.0) {

@@ -26,6 +26,7 @@ struct stag_ctx {
     int fmt64 = STAG_LINKS_F64_18;  // storage used by the FP64 operator
     double* mom = nullptr;
     double* mom_tmp = nullptr;   // force staging when a trajectory records training pairs
+    double* mom_aux = nullptr;   // truncated-solve force fed to a learned model
     // FP64 Krylov workspace
     double2 *r = nullptr /* ring of kLagMax residuals */, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
     double2 *xi = nullptr, *phi = nullptr;

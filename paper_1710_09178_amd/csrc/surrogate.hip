@@ -1,6 +1,8 @@
 // Learned force model: a gauge-covariant combination of the six plaquette
-// staple forces of each link, with coefficients from an MLP (16 -> 64 -> 64
-// -> 8, SiLU) over gauge-invariant loop traces.  Matrix products run on the
+// staple forces of each link and of an optional auxiliary force field, with
+// coefficients from an MLP (16 -> 64 -> 64 -> 8, SiLU) over gauge-invariant
+// inputs (loop traces, parity and sign, the cosine of the auxiliary force
+// with the staple sum).  Matrix products run on the
 // bf16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation); everything
 // else is FP32, the reductions of the loss and the gradients are fixed-order.
 //
@@ -20,7 +22,7 @@ namespace stag {
 
 namespace {
 
-constexpr int FI = 16, HD = 64, NO = 8, NCH = 6;
+constexpr int FI = 16, HD = 64, NO = 8, NCH = 7, NSTAPLE = 6;
 // parameter offsets in one float array: W[out][in] row-major
 constexpr int OW1 = 0, OB1 = OW1 + HD * FI, OW2 = OB1 + HD, OB2 = OW2 + HD * HD, OW3 = OB2 + HD,
               OB3 = OW3 + NO * HD, NPAR = OB3 + NO;
@@ -71,6 +73,7 @@ __device__ __forceinline__ M3 sload(const double2* __restrict__ links, const Geo
 }
 
 __global__ __launch_bounds__(kBlock) void k_sur_features(Geom g, const double2* __restrict__ links,
+                                                         const double* __restrict__ aux,
                                                          unsigned short* __restrict__ f, float* __restrict__ B) {
     const int V = 2 * g.vh;
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -86,6 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_sur_features(Geom g, const double2* 
     float feat[FI];
 #pragma unroll
     for (int k = 0; k < FI; ++k) feat[k] = 0.f;
+    double gsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sum of the staple forces
     int j = 0;
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == mu) continue;
@@ -117,7 +121,10 @@ __global__ __launch_bounds__(kBlock) void k_sur_features(Geom g, const double2* 
             double b8[8];
             im_tr_ta(L, b8);
 #pragma unroll
-            for (int a = 0; a < 8; ++a) B[(row * NCH + ch) * 8 + a] = (float)b8[a];
+            for (int a = 0; a < 8; ++a) {
+                B[(row * NCH + ch) * 8 + a] = (float)b8[a];
+                gsum[a] += b8[a];
+            }
         }
         ++j;
     }
@@ -130,6 +137,17 @@ __global__ __launch_bounds__(kBlock) void k_sur_features(Geom g, const double2* 
         if (c[3] == g.nt - 1) sg = -sg;
     }
     feat[13] = sg;
+    // auxiliary channel and the cosine of its angle with the staple sum
+    double ga[8], gg = 0.0, aa = 0.0, ag = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        ga[a] = aux ? aux[mom_off(g, par, mu, a) + cb] : 0.0;
+        B[(row * NCH + NSTAPLE) * 8 + a] = (float)ga[a];
+        gg += gsum[a] * gsum[a];
+        aa += ga[a] * ga[a];
+        ag += ga[a] * gsum[a];
+    }
+    feat[14] = aux ? (float)(ag / (sqrt(aa) * sqrt(gg) + 1e-30)) : 0.f;
 #pragma unroll
     for (int k = 0; k < FI; ++k) f[row * FI + k] = f2bf(feat[k]);
 }
@@ -507,6 +525,7 @@ struct stag_surrogate {
     float* m = nullptr;
     float* v = nullptr;
     float* gpart = nullptr;            // [nwaves][NPAR]
+    const double* aux = nullptr;       // auxiliary force field (internal momentum layout) or NULL
     float* grad = nullptr;             // [NPAR]
     double* lpart = nullptr;
     double* lsum = nullptr;
@@ -546,7 +565,7 @@ float* slot_t(stag_surrogate* s, int k) { return s->tgt + (size_t)k * s->links *
 void features_into(stag_surrogate* s, int k) {
     stag_ctx* c = s->lat;
     const int grid = (int)((s->links + kBlock - 1) / kBlock);
-    k_sur_features<<<grid, kBlock, 0, c->s>>>(c->g, c->links, slot_f(s, k), slot_B(s, k));
+    k_sur_features<<<grid, kBlock, 0, c->s>>>(c->g, c->links, s->aux, slot_f(s, k), slot_B(s, k));
 }
 
 // loss (and gradient sum / Adam step) over `rows` dataset rows starting at slot k
@@ -635,6 +654,12 @@ stag_status stag_surrogate_params(stag_surrogate_handle s, float* get_out, const
         s->adam_t = 0;
     }
     if (get_out) SHIP(s, hipMemcpy(get_out, s->prm, NPAR * 4, hipMemcpyDeviceToHost));
+    return STAG_OK;
+}
+
+stag_status stag_surrogate_set_aux(stag_surrogate_handle s, const void* aux) {
+    if (!s || (uintptr_t)aux % 16) return sfail(s, STAG_ERR_INVALID_ARG, "bad arguments");
+    s->aux = (const double*)aux;
     return STAG_OK;
 }
 

@@ -59,7 +59,7 @@ class CHMCParams(ctypes.Structure):
                 ("inject_mom", ctypes.c_void_p), ("inject_xi", ctypes.c_void_p),
                 ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("exact_every", ctypes.c_int),
-                ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int)]
+                ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int), ("inner_iters", ctypes.c_int)]
 
 
 class CTrajInfo(ctypes.Structure):
@@ -139,6 +139,7 @@ def load_library() -> ctypes.CDLL:
         "stag_surrogate_last_error": (ctypes.c_char_p, [H]),
         "stag_surrogate_param_count": (I, []),
         "stag_surrogate_pair_count": (I, [H]),
+        "stag_surrogate_set_aux": (S, [H, P]),
         "stag_surrogate_capacity": (I, [H]),
         "stag_surrogate_params": (S, [H, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
         "stag_surrogate_add_pair": (S, [H, P]),
@@ -311,12 +312,13 @@ class Lattice:
                                                  _ptr(phi), ctypes.byref(S), ctypes.byref(info)))
         return S.value
 
-    def fermion_force(self, mass, rat, tol, maxiter, phi, mom, dt=0.0) -> dict:
+    def fermion_force(self, mass, rat, tol, maxiter, phi, mom, dt=0.0, allow_not_converged=False) -> dict:
         r = RationalArg(rat)
         info = CSolveInfo()
-        self._check(self.lib.stag_fermion_force(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
-                                                _ptr(phi), _ptr(mom), float(dt), ctypes.byref(info)))
-        return {"iters": info.iters, "seconds": info.seconds}
+        code = self.lib.stag_fermion_force(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
+                                           _ptr(phi), _ptr(mom), float(dt), ctypes.byref(info))
+        self._check(code, (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,))
+        return {"code": code, "iters": info.iters, "seconds": info.seconds}
 
     def gauge_force(self, beta, mom, dt=0.0):
         self._check(self.lib.stag_gauge_force(self.h, float(beta), _ptr(mom), float(dt)))
@@ -347,12 +349,12 @@ class Lattice:
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
                    no_fermions=False, surrogate=None, exact_every=1, coarse_force=False,
-                   record_pairs=False) -> dict:
+                   record_pairs=False, inner_iters=0) -> dict:
         a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
         prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
                          _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions),
                          surrogate.h if surrogate is not None else None, int(exact_every),
-                         int(coarse_force), int(record_pairs))
+                         int(coarse_force), int(record_pairs), int(inner_iters))
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
@@ -495,6 +497,9 @@ class Surrogate:
     @property
     def capacity(self) -> int:
         return int(self.lib.stag_surrogate_capacity(self.h))
+
+    def set_aux(self, aux: torch.Tensor | None):
+        self._check(self.lib.stag_surrogate_set_aux(self.h, _ptr(aux) if aux is not None else None))
 
     def add_pair(self, force: torch.Tensor):
         self._check(self.lib.stag_surrogate_add_pair(self.h, _ptr(force)))

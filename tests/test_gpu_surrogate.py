@@ -40,18 +40,28 @@ def _unflat(g):
     return out
 
 
+def _aux(dims, seed):
+    nx, ny, nz, nt = dims
+    return synth.make_rng(704, seed).standard_normal((nt, nz, ny, nx, 4, 8))
+
+
+@pytest.mark.parametrize("with_aux", [False, True])
 @pytest.mark.parametrize("dims", [DIMS, (6, 4, 4, 8)])
-def test_force_matches_bf16_oracle(dims):
-    log(f"surrogate force dims={dims}")
+def test_force_matches_bf16_oracle(dims, with_aux):
+    log(f"surrogate force dims={dims} aux={with_aux}")
     U = synth.random_su3_near_identity(dims, 0.6, synth.make_rng(701, 0))
     lat = lattice(dims, U)
     sur = stag.Surrogate(lat, 1)
     p = _params(1)
     sur.set_params(_flat(p))
+    aux = _aux(dims, 0) if with_aux else None
+    if with_aux:
+        aux_dev = lat.mom_import(dev(aux))
+        sur.set_aux(aux_dev)
     mom = lat.new_mom()
     sur.force(mom, 0.0)
     got = host(lat.mom_export(mom))
-    exp = S.surrogate_force(p, U, dims, mode="bf16")
+    exp = S.surrogate_force(p, U, dims, mode="bf16", aux=aux)
     scale = np.abs(exp).max()
     assert np.abs(got - exp).max() < 3e-3 * scale, np.abs(got - exp).max() / scale
     assert np.sqrt(np.mean((got - exp) ** 2)) < 2e-4 * scale
@@ -65,10 +75,14 @@ def test_loss_and_gradient_match_bf16_oracle():
     sur.set_params(_flat(p))
     nx, ny, nz, nt = DIMS
     target = synth.make_rng(701, 2).standard_normal((nt, nz, ny, nx, 4, 8))
+    aux = _aux(DIMS, 1)
+    aux_dev = lat.mom_import(dev(aux))
+    sur.set_aux(aux_dev)
     loss, g = sur.eval(lat.mom_import(dev(target)), want_grad=True)
-    f, loops = S.features(U, DIMS)
+    f, loops = S.features(U, DIMS, aux)
     tf = target.reshape(-1, 8).astype(np.float32).astype(np.float64)
-    lref, gref = S.loss_and_grad(p, f, S.basis(loops), tf, mode="bf16")
+    B = S.basis(loops, aux).astype(np.float32).astype(np.float64)   # the device keeps the channels in FP32
+    lref, gref = S.loss_and_grad(p, f, B, tf, mode="bf16")
     assert abs(loss - lref) < 1e-4 * lref
     gg = _unflat(g.astype(np.float64))
     for k in KEYS:
@@ -193,3 +207,54 @@ def test_trajectory_schedules_and_pair_recording():
     assert abs(rec["dH"] - a["dH"]) < 1e-9 * max(1.0, abs(a["dH"]))
     with pytest.raises(stag.StagError):
         lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, surrogate=sur, record_pairs=True, exact_every=2, **kw)
+
+
+def test_truncated_force_matches_oracle():
+    """The pseudofermion force of a multi-shift solve stopped after N
+    iterations (the model's auxiliary channel in trajectories) against the
+    oracle's solver stopped after the same N iterations."""
+    from oracle import fermion
+    dims = (6, 4, 4, 8)
+    rng = synth.make_rng(705, 0)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    phi = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    lat = lattice(dims, U)
+    mom = lat.new_mom()
+    for n in (5, 20):
+        info = lat.fermion_force(0.1, rat, 1e-30, n, lat.vec_import(dev(phi), 0), mom, 0.0,
+                                 allow_not_converged=True)
+        assert info["code"] == stag.STAG_ERR_NOT_CONVERGED and info["iters"] == n
+        got = host(lat.mom_export(mom))
+        sol = fermion.rational_solve(U, dims, 0.1, phi, rat, 1e-30, maxiter=n)
+        assert sol["iters"] == n
+        exp = fermion.force_from_solutions(U, dims, sol["x"], rat["residue"])
+        assert np.abs(got - exp).max() < 1e-10 * np.abs(exp).max(), n
+
+
+def test_trajectory_with_truncated_inner_force():
+    """Schedules with the auxiliary channel: a model that is the truncated
+    force alone (c_6 = 1) on the inner scale, exact force correcting on the
+    outer scale; recording stores the truncated force with every pair."""
+    dims = (4, 4, 2, 4)
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(706, 0))
+    r_f = synth.load_rational("xm050_n8_m0.1")
+    r_h = synth.load_rational("xp025_n8_m0.1")
+    lat = lattice(dims, U0)
+    kw = dict(seed=5, traj_index=3)
+    ident = stag.Surrogate(lat, 2)
+    p = {k: np.zeros_like(v) for k, v in _params(0).items()}
+    p["b3"][6] = 1.0
+    ident.set_params(_flat(p))
+    a = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, coarse_force=True, exact_every=2, **kw)
+    lat.set_gauge(dev(U0))
+    b = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, coarse_force=True, exact_every=2, surrogate=ident,
+                       inner_iters=10, **kw)
+    assert np.isfinite(b["dH"]) and b["dH"] != a["dH"]
+    # 5 kicks, exact on 0, 2, 4; the model on every kick: 5 truncated solves
+    assert b["n_solves"] == a["n_solves"] + 5
+    lat.set_gauge(dev(U0))
+    rec = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, surrogate=ident, record_pairs=True, inner_iters=10, **kw)
+    assert ident.pairs == 2 and np.isfinite(rec["dH"])
+    with pytest.raises(stag.StagError):
+        lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, inner_iters=10, **kw)
