@@ -470,16 +470,27 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
                 "cg_iters_per_traj": int(np.mean([r["cg_iters_total"] for r in res])),
                 "plaquette_end": round(res[-1]["plaquette"], 5), "trajectories": len(res)}
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = []
-    for _ in range(n_exact):
-        res.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=t, **kw))
-        t += 1
-    torch.cuda.synchronize()
-    out = {"sec_per_trajectory": dict(summary(res, (time.perf_counter() - t0) / n_exact),
+    U_therm = lat.get_gauge()
+    t_first = t
+
+    def timed_chain(**extra):
+        lat.set_gauge(U_therm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = [lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=t_first + i, **kw, **extra)
+               for i in range(n_exact)]
+        torch.cuda.synchronize()
+        return summary(res, (time.perf_counter() - t1) / n_exact)
+
+    out = {"sec_per_trajectory": dict(timed_chain(),
                                       workload="RHMC 16^3x8, beta 5.4, m 0.02, 12-pole x^(-1/2) and x^(1/4) "
                                                "tables, tau 1, 20 leapfrog steps, thermalised from a hot start")}
+    # precision form in the trajectory: MD force solves with FP32 Krylov vectors
+    md = {"fp32_links18": timed_chain(md_link_format=2), "fp32_fp16links12": timed_chain(md_link_format=3)}
+    for v in md.values():
+        v["speedup_vs_fp64"] = round(out["sec_per_trajectory"]["sec_per_traj"] / v["sec_per_traj"], 3)
+    out["md_precision_forms"] = md
+    t = t_first + n_exact
     if not with_model:
         return out
 

@@ -277,6 +277,12 @@ typedef struct {
                                      recorded pair) its auxiliary force is the pseudofermion force of
                                      a multi-shift solve of r_md stopped after inner_iters iterations;
                                      the model's auxiliary field is left NULL afterwards */
+    int md_link_format;           /* 0: the MD force solves in FP64.  STAG_LINKS_F32_18 or
+                                     STAG_LINKS_F16_12: FP32 Krylov vectors with links in that format
+                                     (FP64 solutions and reductions), to tol_md on the recursive
+                                     residual, no refinement.  The force stays a deterministic
+                                     function of the links, so the algorithm stays exact; heat bath
+                                     and actions are always FP64. */
 } stag_hmc_params;
 
 typedef struct {

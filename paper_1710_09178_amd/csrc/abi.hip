@@ -106,15 +106,18 @@ stag_status fermion_action_impl(stag_ctx* c, double mass, const stag_rational* r
     return reduce_to_host(c, S);
 }
 
-// mom = F (dt == 0) or mom += dt F
+// mom = F (dt == 0) or mom += dt F; sloppy != 0: the solve runs with FP32
+// Krylov vectors and links in that format (no refinement)
 stag_status fermion_force_impl(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
-                               const double2* phi, double* mom, double dt, SolveResult& res) {
+                               const double2* phi, double* mom, double dt, SolveResult& res, int sloppy = 0) {
     stag_status e = ensure_pool(c, r->n);
     if (e != STAG_OK) return e;
     const Geom& g = c->g;
     std::vector<double2*> xs(r->n);
     for (int k = 0; k < r->n; ++k) xs[k] = pool_vec(c->pool_x, g, k);
-    if ((e = ms_solve(c, mass, r, tol, maxiter, phi, xs.data(), false, nullptr, nullptr, res)) != STAG_OK) return e;
+    e = sloppy ? ms_solve_sloppy(c, sloppy, mass, r, tol, maxiter, phi, xs.data(), res)
+               : ms_solve(c, mass, r, tol, maxiter, phi, xs.data(), false, nullptr, nullptr, res);
+    if (e != STAG_OK) return e;
     LinkSet ls;
     if ((e = get_links(c, -1, ls))) return e;
     VecPtrs X{}, Y{};
@@ -555,6 +558,9 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     }
     if (p->inner_iters < 0 || (p->inner_iters > 0 && !p->surrogate))
         return fail(c, STAG_ERR_INVALID_ARG, "inner_iters must be >= 0 and needs a model");
+    if (p->md_link_format != 0 && p->md_link_format != STAG_LINKS_F32_18 && p->md_link_format != STAG_LINKS_F16_12)
+        return fail(c, STAG_ERR_INVALID_ARG, "md_link_format must be 0, STAG_LINKS_F32_18 or STAG_LINKS_F16_12");
+    const int mdf = p->md_link_format;
     if (p->inner_iters > 0 && !c->mom_aux) {
         stag_status e2 = dmalloc(c, &c->mom_aux, (size_t)64 * c->g.vh * sizeof(double));
         if (e2) return e2;
@@ -640,7 +646,8 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         // inner-scale model impulse h F_s, outer-scale correction hf (F - F_s)
         if (p->coarse_force && p->surrogate && every > 1 && (e2 = model_force(h - hf))) return e2;
         if (p->record_pairs) {
-            if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom_tmp, 0.0, res)))
+            if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom_tmp, 0.0, res,
+                                         mdf)))
                 return e2;
             if ((e2 = finish_solve_status(c, res))) return e2;
             if (p->inner_iters > 0 && (e2 = truncated_aux())) return e2;
@@ -649,7 +656,7 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
                 return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
             launch_axpy_real((size_t)64 * g.vh, hf, c->mom_tmp, c->mom, c->s);
         } else {
-            if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, hf, res)))
+            if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, hf, res, mdf)))
                 return e2;
             if ((e2 = finish_solve_status(c, res))) return e2;
         }

@@ -109,6 +109,10 @@ stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double to
 // FP32 multi-shift (x_k in FP64) down to opts->tol_sloppy, then per-pole CG in
 // FP32 with FP64 reliable updates every opts->reliable_every iterations until
 // the FP64 true residual of every pole is below tol
+// FP32 Krylov multi-shift (links in `sloppy` format, FP64 solutions and
+// reductions) to the recursive tolerance tol, without refinement.
+stag_status ms_solve_sloppy(stag_ctx* c, int sloppy, double mass, const stag_rational* r, double tol, int maxiter,
+                            const double2* b, double2* const* x, SolveResult& res);
 stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
                            const double2* b, double2* const* x, const stag_mixed_opts* opts, bool want_resid,
                            double* resid_out, int* ipp_out, SolveResult& res);

@@ -403,18 +403,38 @@ stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double to
     return STAG_OK;
 }
 
-stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
-                           const double2* b, double2* const* x, const stag_mixed_opts* opts, bool want_resid,
-                           double* resid_out, int* ipp_out, SolveResult& res) {
-    LinkSet ls;
-    stag_status e = get_links(c, opts->sloppy, ls);
-    if (e) return e;
+namespace {
+stag_status ensure_fp32_workspace(stag_ctx* c) {
     const Geom& g = c->g;
+    stag_status e;
     if (!c->r32) {
         if ((e = dmalloc(c, &c->r32, kLagMax * half_bytes(g) / 2)) || (e = dmalloc(c, &c->p32, half_bytes(g) / 2)) ||
             (e = dmalloc(c, &c->Ap32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->w32, half_bytes(g) / 2)))
             return e;
     }
+    return STAG_OK;
+}
+}  // namespace
+
+stag_status ms_solve_sloppy(stag_ctx* c, int sloppy, double mass, const stag_rational* r, double tol, int maxiter,
+                            const double2* b, double2* const* x, SolveResult& res) {
+    LinkSet ls;
+    stag_status e = get_links(c, sloppy, ls);
+    if (e || (e = ensure_fp32_workspace(c))) return e;
+    EvRec rec;
+    c->prof_used = 0;
+    int ipp[kMaxPoles];
+    if ((e = ms_solve_t<float2>(c, ls, mass, r, tol, maxiter, b, x, ipp, res, rec))) return e;
+    c->last_iters = res.iters;
+    return STAG_OK;
+}
+
+stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, double tol, int maxiter,
+                           const double2* b, double2* const* x, const stag_mixed_opts* opts, bool want_resid,
+                           double* resid_out, int* ipp_out, SolveResult& res) {
+    LinkSet ls;
+    stag_status e = get_links(c, opts->sloppy, ls);
+    if (e || (e = ensure_fp32_workspace(c))) return e;
     EvRec rec;
     c->prof_used = 0;
     int ipp[kMaxPoles];

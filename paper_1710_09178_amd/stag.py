@@ -59,7 +59,8 @@ class CHMCParams(ctypes.Structure):
                 ("inject_mom", ctypes.c_void_p), ("inject_xi", ctypes.c_void_p),
                 ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("exact_every", ctypes.c_int),
-                ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int), ("inner_iters", ctypes.c_int)]
+                ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int), ("inner_iters", ctypes.c_int),
+                ("md_link_format", ctypes.c_int)]
 
 
 class CTrajInfo(ctypes.Structure):
@@ -349,12 +350,12 @@ class Lattice:
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
                    no_fermions=False, surrogate=None, exact_every=1, coarse_force=False,
-                   record_pairs=False, inner_iters=0) -> dict:
+                   record_pairs=False, inner_iters=0, md_link_format=0) -> dict:
         a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
         prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
                          _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions),
                          surrogate.h if surrogate is not None else None, int(exact_every),
-                         int(coarse_force), int(record_pairs), int(inner_iters))
+                         int(coarse_force), int(record_pairs), int(inner_iters), int(md_link_format))
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}

@@ -76,3 +76,29 @@ def test_pure_gauge_trajectory():
                          seed=seed, traj_index=traj, no_fermions=True)
     assert abs(out["dH"] - ref["dH"]) < 1e-9
     assert np.abs(host(lat.get_gauge()) - ref["U"]).max() < 1e-11
+
+
+@pytest.mark.parametrize("fmt", [2, 3])
+def test_fp32_md_forces(fmt):
+    """MD force solves with FP32 Krylov vectors (FP32-18 or FP16-12 links):
+    the trajectory is deterministic (same dH twice) and its dH stays close
+    to the oracle's FP64 trajectory with the same fields; the actions, and
+    so the Metropolis test, are FP64 as before."""
+    dims = (6, 4, 4, 8)
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(300, 1))
+    seed, traj = 77, 2
+    prm = _params(6, 0.5)
+    ref = hmc.trajectory(U0, dims, prm, philox.momentum(dims, seed, traj), philox.source(dims, seed, traj),
+                         philox.uniform(seed, traj))
+    lat = lattice(dims, U0)
+    outs = []
+    for _ in range(2):
+        lat.set_gauge(dev(U0))
+        outs.append(lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action,
+                                   prm.r_heatbath, tol_md=1e-8, tol_action=1e-12, seed=seed, traj_index=traj,
+                                   md_link_format=fmt))
+    assert outs[0]["dH"] == outs[1]["dH"]
+    log(f"  fmt {fmt}: dH {outs[0]['dH']:.6e} oracle FP64 {ref['dH']:.6e}")
+    assert abs(outs[0]["Sf_old"] - ref["H0"][2]) <= 1e-10 * abs(ref["H0"][2])
+    tol = 1e-4 if fmt == 2 else 5e-2
+    assert abs(outs[0]["dH"] - ref["dH"]) < tol * max(1.0, abs(ref["dH"]))
