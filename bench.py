@@ -425,7 +425,8 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     return out
 
 
-def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.0, inner_iters=100):
+def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.0, inner_iters=100,
+         chain_steps=40):
     """RHMC at 16^3x8 (beta 5.4, m 0.02, 12-pole rational tables, tau 1, 20
     leapfrog steps, MD tolerance 1e-8, action 1e-10) from a seeded hot start,
     thermalised by 60 pure-gauge and 5 dynamical trajectories (all accepted).
@@ -434,12 +435,13 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
     With the learned force model: exact-force trajectories record n_pairs
     (U, force) pairs, each with the force of a solve stopped after
     inner_iters iterations as the model's auxiliary channel; the model is
-    trained on them on the GPU; then chains of n_traj trajectories start from
-    the same configuration with the same momenta and pseudofermions: exact
-    force on every kick, and for exact_every in (2, 4) a two-time-scale
-    leapfrog with the exact force on the outer scale and on the inner scale
-    (a) nothing (the ablation), (b) the truncated-solve force alone, (c) the
-    trained model (which also sees the truncated-solve force).
+    trained on them on the GPU; then chains of n_traj trajectories of
+    chain_steps leapfrog steps (a step size at which the exact force accepts
+    well) start from the same configuration with the same momenta and
+    pseudofermions: exact force on every kick, and for exact_every in (2, 4)
+    a two-time-scale leapfrog with the exact force on the outer scale and on
+    the inner scale (a) nothing (the ablation), (b) the truncated-solve force
+    alone, (c) the trained model (which also sees the truncated-solve force).
     Accept/reject always uses the exact action."""
     import numpy as np
     import torch
@@ -543,7 +545,8 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
         res = []
         t1 = time.perf_counter()
         for i in range(n_traj):
-            res.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=10 ** 6 + i, **kw, **extra))
+            res.append(lat.trajectory(beta, mass, tau, chain_steps, r_f, r_f, r_h, traj_index=10 ** 6 + i,
+                                      **kw, **extra))
         torch.cuda.synchronize()
         return summary(res, (time.perf_counter() - t1) / n_traj)
 
@@ -556,8 +559,9 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.
     for k, v in chains.items():
         v["speedup_vs_exact"] = round(chains["exact"]["sec_per_traj"] / v["sec_per_traj"], 3)
     out["learned_force_rhmc"] = {
-        "workload": "the same RHMC; two-time-scale leapfrog, exact force on the outer scale",
-        "inner_iters": inner_iters, "pairs": n_pairs, "recording_trajectories": len(rec),
+        "workload": f"the same RHMC with {chain_steps} leapfrog steps; two-time-scale leapfrog, exact force "
+                    f"on the outer scale",
+        "chain_steps": chain_steps, "inner_iters": inner_iters, "pairs": n_pairs, "recording_trajectories": len(rec),
         "recording_seconds": round(t_rec, 2),
         "recording_acceptance": round(float(np.mean([r["accepted"] for r in rec])), 3),
         "train_epochs": epochs, "train_seconds": round(t_train, 2),
