@@ -48,10 +48,11 @@ template <class V>
 struct BEpiStore {
     static constexpr int K = 1;
     V* out;
-    __device__ void item(const BInst& I, int, int R, int rh, int site, int c, V v, double*) const {
+    __device__ __forceinline__ void item(const BInst& I, int, int R, int rh, int site, int c, V v,
+                                         double (&)[K]) const {
         out[bvec_off(I, R, rh, c) + site] = v;
     }
-    __device__ void finish(int, double*) const {}
+    __device__ __forceinline__ void finish(int, double (&)[K]) const {}
 };
 
 // Ap = (4 m_i^2 + sigma_0) p - v and per-rhs partials of <p,Ap>, <r,Ap>, <Ap,Ap>
@@ -63,7 +64,8 @@ struct BEpiCG {
     const V* r;
     const double* sigma0_term;  // [inst] 4 m_i^2 + sigma_0
     double* part;  // [tile][kMaxRhs][3]
-    __device__ void item(const BInst& I, int inst, int R, int rh, int site, int c, V v, double* acc) const {
+    __device__ __forceinline__ void item(const BInst& I, int inst, int R, int rh, int site, int c, V v,
+                                         double (&acc)[K]) const {
         const size_t i = bvec_off(I, R, rh, c) + site;
         const V pv = p[i], rv = r[i];
         using Rl = typename BPrec<V>::R;
@@ -73,14 +75,13 @@ struct BEpiCG {
         const double2 pd = to_d2(pv), rd = to_d2(rv), ad = to_d2(a);
         const double d0 = pd.x * ad.x + pd.y * ad.y, d1 = rd.x * ad.x + rd.y * ad.y, d2 = ad.x * ad.x + ad.y * ad.y;
 #pragma unroll
-        for (int q = 0; q < kMaxRhs; ++q)  // predicated: no dynamic register indexing
-            if (q == rh) {
-                acc[3 * q + 0] += d0;
-                acc[3 * q + 1] += d1;
-                acc[3 * q + 2] += d2;
-            }
+        for (int q = 0; q < kMaxRhs; ++q) {  // selects: no dynamic register indexing
+            acc[3 * q + 0] += (q == rh) ? d0 : 0.0;
+            acc[3 * q + 1] += (q == rh) ? d1 : 0.0;
+            acc[3 * q + 2] += (q == rh) ? d2 : 0.0;
+        }
     }
-    __device__ void finish(int tile, double* acc) const {
+    __device__ __forceinline__ void finish(int tile, double (&acc)[K]) const {
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = acc[k];
@@ -100,7 +101,8 @@ struct BEpiResid {
     double2* rout;
     double pole;
     double* part;  // [tile][kMaxRhs]
-    __device__ void item(const BInst& I, int, int R, int rh, int site, int c, double2 v, double* acc) const {
+    __device__ __forceinline__ void item(const BInst& I, int, int R, int rh, int site, int c, double2 v,
+                                         double (&acc)[K]) const {
         const size_t i = bvec_off(I, R, rh, c) + site;
         const double coef = I.four_m2 + pole;
         const double2 xv = x[i], bv = b[i];
@@ -110,7 +112,7 @@ struct BEpiResid {
         for (int q = 0; q < kMaxRhs; ++q)
             if (q == rh) acc[q] += rx * rx + ry * ry;
     }
-    __device__ void finish(int tile, double* acc) const {
+    __device__ __forceinline__ void finish(int tile, double (&acc)[K]) const {
         double v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = acc[k];
