@@ -135,3 +135,49 @@ def test_large_instances_window_and_residuals():
         assert info["true_resid"].max() < 1e-10, info["true_resid"].max()
     assert out[1][1]["iters_sys"] == out[8][1]["iters_sys"]
     assert np.array_equal(out[1][0], out[8][0])
+
+
+def test_full_size_64_lattices_against_oracle():
+    """The batched workload at its full size: 64 lattices (16 each of 8^4,
+    12^3x6, 16^3x8, 24^3x6) x 4 right-hand sides x the 12-pole x^(-1/4)
+    table, masses uniform in [0.005, 0.05].  FP64: for every lattice (one
+    right-hand side each, rotating) the oracle's operator gives every pole's
+    true residual below 1e-10 and matches the library's own FP64 residual;
+    mixed precision: the same for one lattice of each volume."""
+    from concurrent.futures import ThreadPoolExecutor
+    classes = [(8, 8, 8, 8), (12, 12, 12, 6), (16, 16, 16, 8), (24, 24, 24, 6)]
+    dims = [d for d in classes for _ in range(16)]
+    nrhs = 4
+    rng = synth.make_rng(502, 0)
+    masses = list(rng.uniform(0.005, 0.05, len(dims)))
+    with ThreadPoolExecutor(8) as ex:
+        Us = list(ex.map(lambda i: synth.random_su3_near_identity(dims[i], 0.2, synth.make_rng(502, 1000 + i)),
+                         range(len(dims))))
+    srcs = [[synth.gaussian_half_vector(d, synth.make_rng(502, 5000 + 8 * i + j)) for j in range(nrhs)]
+            for i, d in enumerate(dims)]
+    B = stag.Batch(dims, nrhs)
+    for i, U in enumerate(Us):
+        B.set_gauge(i, dev(U))
+    b = dev(np.concatenate([v.reshape(-1) for per in srcs for v in per]))
+    rat = synth.load_rational("xm025_n12_m0.005")
+    offs = np.cumsum([0] + [nrhs * 3 * (d[0] * d[1] * d[2] * d[3] // 2) for d in dims])
+
+    def system(xh, i, j):
+        vh = dims[i][0] * dims[i][1] * dims[i][2] * dims[i][3] // 2
+        o = offs[i] + j * 3 * vh
+        return [xh[k][o:o + 3 * vh].reshape(vh, 3) for k in range(len(rat["pole"]))]
+
+    for precision, sample in ((0, range(len(dims))), (1, [0, 16, 32, 48])):
+        log(f"full-size batch precision={precision}")
+        x, info = B.solve(masses, rat, b, precision=precision, tol=1e-10)
+        xh = host(x)
+        for i in sample:
+            j = i % nrhs
+            op = lambda v, i=i: dirac.apply_A(Us[i], v, dims[i], masses[i])
+            res = true_residuals(op, srcs[i][j], rat["pole"], system(xh, i, j))
+            assert res.max() < 1e-10, (precision, i, j, res.max())
+            lib = info["true_resid"][i * nrhs + j]
+            # both residuals are computed in FP64; near 1e-10 their rounding
+            # (about 1e-16 |A| |x|) is a visible fraction of the residual itself
+            assert np.all(np.abs(lib - res) <= 0.1 * res + 1e-12), (precision, i, j)
+        del x, xh
