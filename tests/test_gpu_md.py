@@ -90,3 +90,42 @@ def test_philox_known_answers_and_fields():
     assert np.abs(P - philox.momentum(dims, seed, traj)).max() < 1e-13
     xi = host(lat.vec_export(lat.random_source(seed, traj), 0))
     assert np.abs(xi - philox.source(dims, seed, traj)).max() < 1e-13
+
+
+def test_leapfrog_reversible_at_16c8():
+    """A property that holds at any size, checked at the RHMC workload's
+    16^3x8: leapfrog (gauge and fermion forces, link updates) run forward,
+    momenta flipped, run again, returns to the starting links and the
+    negated starting momenta."""
+    dims = (16, 16, 16, 8)
+    log("leapfrog reversibility at 16^3x8")
+    rng = synth.make_rng(310, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.3, rng)
+    phi = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm050_n12_m0.02")
+    lat = lattice(dims, U0)
+    phid = lat.vec_import(dev(phi), 0)
+    mom = lat.random_momentum(9, 1)
+    P0 = host(lat.mom_export(mom))
+    dt, n = 0.05, 4
+
+    def kick(h):
+        lat.gauge_force(5.4, mom, h)
+        lat.fermion_force(0.02, rat, 1e-12, 100000, phid, mom, h)
+
+    def leapfrog():
+        kick(0.5 * dt)
+        for s in range(n):
+            lat.link_update(mom, dt)
+            kick(dt if s < n - 1 else 0.5 * dt)
+
+    leapfrog()
+    U1 = host(lat.get_gauge())
+    assert np.abs(U1 - U0).max() > 1e-3        # the links did move
+    flipped = lat.mom_import(dev(-host(lat.mom_export(mom))))
+    mom.copy_(flipped)
+    leapfrog()
+    U2 = host(lat.get_gauge())
+    P2 = host(lat.mom_export(mom))
+    assert np.abs(U2 - U0).max() < 1e-9, np.abs(U2 - U0).max()
+    assert np.abs(P2 + P0).max() < 1e-8 * np.abs(P0).max(), np.abs(P2 + P0).max()
