@@ -108,6 +108,24 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     const MsIter& s = st->it[par];
     const int iter = s.iter;
     const int slot = iter % L;
+    // The base system's streams do not depend on this iteration's scalars:
+    // issue their loads before the scalar prologue so that their latency
+    // overlaps it.
+    double2 pre_r[kEPT], pre_a[kEPT], pre_p[kEPT], pre_x[kEPT];
+    {
+        const V* rc = ring + (size_t)slot * n3;
+        const double2* xb = x.at<double2>(base);
+#pragma unroll
+        for (int e = 0; e < kEPT; ++e) {
+            const int i = (blockIdx.x * kEPT + e) * kBlock + threadIdx.x;
+            if (i < n3) {
+                pre_r[e] = to_d2(rc[i]);
+                pre_a[e] = to_d2(Ap[i]);
+                pre_p[e] = to_d2(p[i]);
+                pre_x[e] = nt_load(xb + i);
+            }
+        }
+    }
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int nbq = gridDim.x;  // init and step kernels use the same grid
     for (int b = threadIdx.x; b < nbq; b += kBlock) v[0] += qin[b];
@@ -227,7 +245,6 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     const double alpha = sh_alpha, beta = sh_beta;
     const bool base_on = sh_act[base];
     const int nact = sh_nact;
-    const V* r_cur = ring + (size_t)slot * n3;
     V* r_next = ring + (size_t)((slot + 1) % L) * n3;
     double acc[1] = {0.0};
 #pragma unroll
@@ -235,11 +252,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
         const int i = (blockIdx.x * kEPT + e) * kBlock + threadIdx.x;
         if (i >= n3) continue;
         // r and p in the Krylov precision V, solutions accumulated in FP64
-        const double2 r0 = to_d2(r_cur[i]);
+        const double2 r0 = pre_r[e];
         double2 rv = r0;
         if (!stop) {
-            const double2 a = to_d2(Ap[i]);
-            const double2 pv = to_d2(p[i]);
+            const double2 a = pre_a[e];
+            const double2 pv = pre_p[e];
             double2* xb = x.at<double2>(base);
             rv.x -= alpha * a.x;
             rv.y -= alpha * a.y;
@@ -248,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
             rv = to_d2(rl);
             acc[0] += rv.x * rv.x + rv.y * rv.y;
             if (base_on) {
-                const double2 xbv = nt_load(xb + i);
+                const double2 xbv = pre_x[e];
                 nt_store(xb + i, make_double2(xbv.x + alpha * pv.x, xbv.y + alpha * pv.y));
             }
             p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
