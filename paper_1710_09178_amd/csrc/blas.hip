@@ -98,12 +98,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
         return;
     }
     __shared__ double lds[16];
-    __shared__ double sh_as[kMaxPoles], sh_bs[kMaxPoles], sh_zn[kMaxPoles];
-    __shared__ int sh_act[kMaxPoles], sh_list[kMaxPoles];
+    __shared__ int sh_list[kMaxPoles];
     __shared__ double w_as[kLagMax][kMaxPoles], w_bs[kLagMax][kMaxPoles], w_zn[kLagMax][kMaxPoles];
     __shared__ int w_act[kLagMax][kMaxPoles];
-    __shared__ double sh_rr, sh_bb, sh_alpha, sh_beta;
-    __shared__ int sh_stop, sh_nact, sh_nonfinite;
+    __shared__ double sh_alpha, sh_beta;
+    __shared__ int sh_stop, sh_nact, sh_base_on;
     const int n = st->n, base = st->base, L = st->lag;
     const MsIter& s = st->it[par];
     const int iter = s.iter;
@@ -134,9 +133,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
         v[2] += dpart[nb2 + b];
         v[3] += dpart[2 * nb2 + b];
     }
-    block_sum<4>(v, lds);
-    if (threadIdx.x == 0) {
-        const double rr = v[0], pAp = v[1], rAp = v[2], ApAp = v[3];
+    block_sum<4>(v, lds);  // thread 0 holds the totals
+    // Wave 0 evaluates the iteration's scalars, one lane per shift (n <= 48 < 64):
+    // every lane computes alpha and beta from the same broadcast totals, and the
+    // freezing test, the stop decision and the shift list use wave ballots.
+    const int k = threadIdx.x;
+    if (k < 64) {
+        const double rr = __shfl(v[0], 0), pAp = __shfl(v[1], 0), rAp = __shfl(v[2], 0), ApAp = __shfl(v[3], 0);
         const double bb = (iter == 0 && !st->bb_given) ? rr : s.bb;
         int nonfinite = !isfinite(rr);
         double alpha = 0.0, beta = 0.0;
@@ -146,104 +149,93 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
             if (rr1 < 0.0) rr1 = 0.0;
             beta = rr1 / rr;
         }
-        sh_rr = rr;
-        sh_bb = bb;
-        sh_alpha = alpha;
-        sh_beta = beta;
-        sh_nonfinite = nonfinite;
-    }
-    __syncthreads();
-    // one thread per shift: freezing test and recurrences
-    const int k = threadIdx.x;
-    if (k < n) {
-        const double rr = sh_rr, alpha = sh_alpha, beta = sh_beta;
-        int act = s.active[k];
-        if (act && s.zeta[k] * s.zeta[k] * rr <= st->tol2 * sh_bb) act = 0;
-        const double z = s.zeta[k], zo = s.zeta_old[k];
-        double zn = z, as = 0.0, bs = 0.0;
-        if (k == base) {
-            zn = 1.0;
-            as = alpha;
-            bs = beta;
-        } else if (act) {
-            const double a_old = s.alpha_old, b_old = s.beta_old;
-            zn = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st->shift[k] * alpha));
-            const double q = zn / z;
-            as = alpha * q;
-            bs = beta * q * q;
+        // freezing test and recurrences of shift k
+        int act = 0;
+        double zn = 0.0, as = 0.0, bs = 0.0;
+        if (k < n) {
+            act = s.active[k];
+            if (act && s.zeta[k] * s.zeta[k] * rr <= st->tol2 * bb) act = 0;
+            const double z = s.zeta[k], zo = s.zeta_old[k];
+            zn = z;
+            if (k == base) {
+                zn = 1.0;
+                as = alpha;
+                bs = beta;
+            } else if (act) {
+                const double a_old = s.alpha_old, b_old = s.beta_old;
+                zn = z * zo * a_old / (alpha * b_old * (zo - z) + zo * a_old * (1.0 + st->shift[k] * alpha));
+                const double q = zn / z;
+                as = alpha * q;
+                bs = beta * q * q;
+            }
         }
-        sh_act[k] = act;
-        sh_zn[k] = zn;
-        sh_as[k] = as;
-        sh_bs[k] = bs;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int any = 0;
-        for (int q = 0; q < n; ++q) any |= sh_act[q];
-        int nonfinite = sh_nonfinite;
-        if (any && !(isfinite(sh_alpha) && isfinite(sh_beta))) nonfinite = 1;
-        sh_nonfinite = nonfinite;
-        sh_stop = nonfinite || !any || iter >= st->maxiter;
+        const unsigned long long any = __ballot(act != 0);
+        if (any && !(isfinite(alpha) && isfinite(beta))) nonfinite = 1;
+        const int stop = nonfinite || !any || iter >= st->maxiter;
+        // pending shifted updates: iterations iter - slot .. iter (.. iter - 1 when stopping)
+        const int npend = stop ? slot : slot + 1;
+        const int flush = npend > 0 && (stop || slot == L - 1);
+        if (k < n) {
+            if (flush) {
+                for (int t = 0; t < slot; ++t) {
+                    w_as[t][k] = st->hist[t].as[k];
+                    w_bs[t][k] = st->hist[t].bs[k];
+                    w_zn[t][k] = st->hist[t].zn[k];
+                    w_act[t][k] = st->hist[t].act[k];
+                }
+                if (!stop) {
+                    w_as[slot][k] = as;
+                    w_bs[slot][k] = bs;
+                    w_zn[slot][k] = zn;
+                    w_act[slot][k] = act;
+                }
+            }
+            if (blockIdx.x == 0) {
+                // the state of the next iteration (or the final one)
+                MsIter& o = stop ? st->fin : st->it[par ^ 1];
+                o.active[k] = act;
+                o.iters_per_pole[k] = (act && !stop) ? iter + 1 : (s.active[k] ? iter : s.iters_per_pole[k]);
+                o.zeta[k] = stop ? s.zeta[k] : zn;
+                o.zeta_old[k] = stop ? s.zeta_old[k] : s.zeta[k];
+                if (!stop && !flush) {
+                    st->hist[slot].as[k] = as;
+                    st->hist[slot].bs[k] = bs;
+                    st->hist[slot].zn[k] = zn;
+                    st->hist[slot].act[k] = act;
+                }
+            }
+        }
+        // shifts to touch in a flush: those active in the window's first
+        // iteration, in increasing order (this lane's own LDS write above)
+        const int mine = flush && k < n && k != base && w_act[0][k];
+        const unsigned long long lmask = __ballot(mine != 0);
+        if (mine) sh_list[__popcll(lmask & ((1ull << k) - 1ull))] = k;
+        const int base_act = __shfl(act, base);
+        if (k == 0) {
+            sh_alpha = alpha;
+            sh_beta = beta;
+            sh_stop = stop;
+            sh_nact = __popcll(lmask);
+            sh_base_on = base_act;
+            if (blockIdx.x == 0) {
+                MsIter& o = stop ? st->fin : st->it[par ^ 1];
+                o.alpha_old = stop ? s.alpha_old : alpha;
+                o.beta_old = stop ? s.beta_old : beta;
+                o.bb = bb;
+                o.rr = rr;
+                o.iter = stop ? iter : iter + 1;
+                o.nonfinite = nonfinite;
+                if (stop) st->done[par ^ 1] = 1;
+            }
+        }
     }
     __syncthreads();
     const int stop = sh_stop;
-    // pending shifted updates: iterations iter - slot .. iter (.. iter - 1 when stopping)
     const int npend = stop ? slot : slot + 1;
     const bool flush = npend > 0 && (stop || slot == L - 1);
-    if (flush && k < n) {
-        for (int t = 0; t < slot; ++t) {
-            w_as[t][k] = st->hist[t].as[k];
-            w_bs[t][k] = st->hist[t].bs[k];
-            w_zn[t][k] = st->hist[t].zn[k];
-            w_act[t][k] = st->hist[t].act[k];
-        }
-        if (!stop) {
-            w_as[slot][k] = sh_as[k];
-            w_bs[slot][k] = sh_bs[k];
-            w_zn[slot][k] = sh_zn[k];
-            w_act[slot][k] = sh_act[k];
-        }
-    }
-    if (blockIdx.x == 0) {
-        // the state of the next iteration (or the final one)
-        MsIter& o = stop ? st->fin : st->it[par ^ 1];
-        if (k < n) {
-            const int act = sh_act[k];
-            o.active[k] = act;
-            o.iters_per_pole[k] = (act && !stop) ? iter + 1 : (s.active[k] ? iter : s.iters_per_pole[k]);
-            o.zeta[k] = stop ? s.zeta[k] : sh_zn[k];
-            o.zeta_old[k] = stop ? s.zeta_old[k] : s.zeta[k];
-            if (!stop && !flush) {
-                st->hist[slot].as[k] = sh_as[k];
-                st->hist[slot].bs[k] = sh_bs[k];
-                st->hist[slot].zn[k] = sh_zn[k];
-                st->hist[slot].act[k] = sh_act[k];
-            }
-        }
-        if (threadIdx.x == 0) {
-            o.alpha_old = stop ? s.alpha_old : sh_alpha;
-            o.beta_old = stop ? s.beta_old : sh_beta;
-            o.bb = sh_bb;
-            o.rr = sh_rr;
-            o.iter = stop ? iter : iter + 1;
-            o.nonfinite = sh_nonfinite;
-            if (stop) st->done[par ^ 1] = 1;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // shifts to touch: those active in the window's first iteration
-        int m = 0;
-        if (flush)
-            for (int q = 0; q < n; ++q)
-                if (q != base && w_act[0][q]) sh_list[m++] = q;
-        sh_nact = m;
-    }
-    __syncthreads();
     if (stop && !flush) return;
     const double alpha = sh_alpha, beta = sh_beta;
-    const bool base_on = sh_act[base];
+    const bool base_on = sh_base_on;
     const int nact = sh_nact;
     V* r_next = ring + (size_t)((slot + 1) % L) * n3;
     double acc[1] = {0.0};
