@@ -37,8 +37,10 @@
  *   describes the problem.  STAG_ERR_NOT_CONVERGED is non-fatal: outputs hold
  *   the last iterate and the info structure is filled.
  * Threading: a handle must not be used by two threads at once.
- * Memory: the library allocates its workspace in stag_create, stag_set_gauge
- *   and on the first solve that needs more shift vectors than any earlier one;
+ * Memory: the library allocates its workspace in stag_create, on the first
+ *   solve that needs more shift vectors than any earlier one, and on the first
+ *   use of an optional feature (compressed or FP32/FP16 link copies, the FP32
+ *   Krylov workspace, trajectory staging buffers, captured iteration graphs);
  *   it never allocates inside an iteration.
  */
 #ifndef STAG_H
@@ -145,8 +147,8 @@ stag_status stag_multishift_solve(stag_handle h, double mass, const stag_rationa
 typedef enum {
     STAG_LINKS_F64_18 = 0,   /* FP64, 18 reals per link (default) */
     STAG_LINKS_F64_12 = 1,   /* FP64, 12 reals per link */
-    STAG_LINKS_F32_18 = 2,   /* FP32, 18 reals (mixed-precision solver only) */
-    STAG_LINKS_F16_12 = 3    /* IEEE FP16, 12 reals (mixed-precision solver only) */
+    STAG_LINKS_F32_18 = 2,   /* FP32, 18 reals (FP32 Krylov solves only) */
+    STAG_LINKS_F16_12 = 3    /* IEEE FP16, 12 reals (FP32 Krylov solves only) */
 } stag_link_format;
 
 /* Storage used by every FP64 operator application of h (Dslash, A, solves,
@@ -259,8 +261,8 @@ typedef struct {
     const void* inject_xi;        /* NULL or internal even vector used instead of the RNG */
     double inject_u;              /* Metropolis uniform in [0,1), or < 0 to draw it */
     int no_fermions;              /* 1: pure gauge trajectory (tests) */
-    stag_surrogate_handle surrogate;  /* NULL, or a model used for the pseudofermion force on kicks
-                                         k (0..n_steps) with k % exact_every != 0 */
+    stag_surrogate_handle surrogate;  /* NULL, or a model standing in for the pseudofermion force
+                                         (kicks k = 0..n_steps; see exact_every, coarse_force) */
     int exact_every;              /* >= 1; with n_steps % exact_every == 0 the set of exact kicks is
                                      symmetric under k -> n_steps - k, keeping leapfrog reversible.
                                      The accept/reject step always uses the exact rational action. */
