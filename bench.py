@@ -207,8 +207,8 @@ def main():
         pmc_mode()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the domain-decomposed design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (one process, one device).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
