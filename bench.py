@@ -425,7 +425,7 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     return out
 
 
-def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=20, train_seconds=25.0, inner_iters=100,
+def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.0, inner_iters=200,
          chain_steps=40):
     """RHMC at 16^3x8 (beta 5.4, m 0.02, 12-pole rational tables, tau 1, 20
     leapfrog steps, MD tolerance 1e-8, action 1e-10) from a seeded hot start,
