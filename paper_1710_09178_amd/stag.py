@@ -488,7 +488,8 @@ class Surrogate:
 
     def set_params(self, p):
         arr = np.ascontiguousarray(p, dtype=np.float32)
-        assert arr.size == self.n_params
+        if arr.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {arr.size}")
         self._check(self.lib.stag_surrogate_params(self.h, None, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
     @property

@@ -216,3 +216,25 @@ def test_graph_replay_matches_direct_launches():
                     out[(j, rep)] = (got, info["iters"])
     for j in range(2):
         assert np.array_equal(out[(j, 0)][0], out[(j, 1)][0])
+
+
+@pytest.mark.parametrize("poles", [[0.05], [1e-3, 1e-3, 0.5], list(np.logspace(-4, 2, 48))],
+                         ids=["one_pole", "repeated_pole", "48_poles"])
+def test_pole_count_edge_cases(poles):
+    """One pole (plain CG), a repeated pole (identical solutions) and the
+    maximum of 48 poles, against the oracle."""
+    dims = (4, 4, 4, 4)
+    rng = synth.make_rng(0, 11)
+    U = synth.random_su3_near_identity(dims, 0.3, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    lat = lattice(dims, U)
+    xs, _, info = _solve(lat, dims, 0.1, _rat(poles), 1e-12, b)
+    op = lambda v: dirac.apply_A(U, v, dims, 0.1)
+    res = true_residuals(op, b, poles, xs)
+    assert res.max() < 1e-11
+    ref = multishift_cg(op, b, poles, 1e-12)
+    for sig, x, xr in zip(poles, xs, ref["x"]):
+        kappa = (0.04 + 64 + sig) / (0.04 + sig)
+        assert np.linalg.norm(x - xr) <= 2e-12 * kappa * np.linalg.norm(xr)
+    if len(poles) == 3:
+        assert np.array_equal(xs[0], xs[1])

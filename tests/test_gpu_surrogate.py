@@ -258,3 +258,21 @@ def test_trajectory_with_truncated_inner_force():
     assert ident.pairs == 2 and np.isfinite(rec["dH"])
     with pytest.raises(stag.StagError):
         lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, inner_iters=10, **kw)
+
+
+def test_model_error_paths():
+    lat = lattice(DIMS, synth.random_su3_near_identity(DIMS, 0.3, synth.make_rng(707, 0)))
+    sur = stag.Surrogate(lat, 1)
+    with pytest.raises(stag.StagError):
+        sur.train(1, 1e-3)                      # no training pairs yet
+    mom = lat.new_mom()
+    sur.add_pair(mom)
+    with pytest.raises(stag.StagError):
+        sur.add_pair(mom)                       # dataset full
+    with pytest.raises(stag.StagError):
+        sur.set_aux(mom[1:])                    # misaligned device pointer
+    with pytest.raises(stag.StagError):
+        sur.train(1, -1.0)                      # learning rate must be positive
+    with pytest.raises(ValueError):
+        sur.set_params(np.zeros(3, dtype=np.float32))
+    assert sur.train(1, 1e-3) >= 0.0
