@@ -483,13 +483,27 @@ __global__ void k_sur_target(Geom g, const double* __restrict__ force, float* __
 
 // Sum of per-wave partial gradients (wave order) and one Adam step
 // (Kingma & Ba 2015, bias-corrected) on the FP32 master parameters.
-__global__ void k_sur_adam(const float* __restrict__ gpart, int nwaves, float* __restrict__ prm, float* __restrict__ m,
+// Gradient sum, first stage: chunk c (blockIdx.y) of the per-wave partials,
+// waves in order, one thread per parameter.
+constexpr int kGradChunks = 32;
+__global__ void k_sur_gsum(const float* __restrict__ gpart, int nwaves, float* __restrict__ gpart2) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NPAR) return;
+    const int per = (nwaves + kGradChunks - 1) / kGradChunks;
+    const int w0 = blockIdx.y * per, w1 = min(nwaves, w0 + per);
+    float g = 0.f;
+    for (int w = w0; w < w1; ++w) g += gpart[(size_t)w * NPAR + k];
+    gpart2[(size_t)blockIdx.y * NPAR + k] = g;
+}
+
+// Second stage (chunks in order) and one Adam step.
+__global__ void k_sur_adam(const float* __restrict__ gpart2, float* __restrict__ prm, float* __restrict__ m,
                            float* __restrict__ v, float* __restrict__ grad_out, float lr, float b1, float b2, float eps,
                            float c1, float c2, int step) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= NPAR) return;
     float gsum = 0.f;
-    for (int w = 0; w < nwaves; ++w) gsum += gpart[(size_t)w * NPAR + k];
+    for (int c = 0; c < kGradChunks; ++c) gsum += gpart2[(size_t)c * NPAR + k];
     if (grad_out) grad_out[k] = gsum;
     if (!step) return;
     const float mk = b1 * m[k] + (1.f - b1) * gsum;
@@ -499,14 +513,18 @@ __global__ void k_sur_adam(const float* __restrict__ gpart, int nwaves, float* _
     prm[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
-// out[0] = sum of the n partials; out[1] += the same sum (epoch accumulator),
-// or out[1] = 0 first when reset is set
-__global__ void k_sum_double(const double* __restrict__ p, int n, double* __restrict__ out, int reset) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += p[i];
-    out[0] = s;
-    out[1] = (reset ? 0.0 : out[1]) + s;
+// out[0] = sum of the n partials (one block, fixed order); out[1] += the same
+// sum (epoch accumulator), or out[1] = 0 first when reset is set
+__global__ __launch_bounds__(kBlock) void k_sum_double(const double* __restrict__ p, int n, double* __restrict__ out,
+                                                       int reset) {
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += kBlock) v[0] += p[i];
+    __shared__ double lds[4];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) {
+        out[0] = v[0];
+        out[1] = (reset ? 0.0 : out[1]) + v[0];
+    }
 }
 
 }  // namespace
@@ -525,6 +543,7 @@ struct stag_surrogate {
     float* m = nullptr;
     float* v = nullptr;
     float* gpart = nullptr;            // [nwaves][NPAR]
+    float* gpart2 = nullptr;           // [kGradChunks][NPAR]
     const double* aux = nullptr;       // auxiliary force field (internal momentum layout) or NULL
     float* grad = nullptr;             // [NPAR]
     double* lpart = nullptr;
@@ -577,10 +596,12 @@ void train_pass(stag_surrogate* s, int k, long long rows, bool grad, int adam_st
         const float b1 = 0.9f, b2 = 0.999f;
         const float c1 = adam_step ? 1.f - powf(b1, (float)adam_step) : 1.f;
         const float c2 = adam_step ? 1.f - powf(b2, (float)adam_step) : 1.f;
-        k_sur_adam<<<(NPAR + 255) / 256, 256, 0, c->s>>>(s->gpart, s->nblocks * kWavesSur, s->prm, s->m, s->v, s->grad,
-                                                         lr, b1, b2, 1e-8f, c1, c2, adam_step);
+        k_sur_gsum<<<dim3((NPAR + 255) / 256, kGradChunks), 256, 0, c->s>>>(s->gpart, s->nblocks * kWavesSur,
+                                                                             s->gpart2);
+        k_sur_adam<<<(NPAR + 255) / 256, 256, 0, c->s>>>(s->gpart2, s->prm, s->m, s->v, s->grad, lr, b1, b2, 1e-8f, c1,
+                                                         c2, adam_step);
     }
-    k_sum_double<<<1, 64, 0, c->s>>>(s->lpart, s->nblocks * kWavesSur, s->lsum, reset ? 1 : 0);
+    k_sum_double<<<1, kBlock, 0, c->s>>>(s->lpart, s->nblocks * kWavesSur, s->lsum, reset ? 1 : 0);
 }
 
 }  // namespace
@@ -600,7 +621,8 @@ stag_status stag_surrogate_create(stag_surrogate_handle* out, stag_handle lat, i
     if ((e = salloc(s, &s->f, slots * s->links * FI * 2)) || (e = salloc(s, &s->B, slots * s->links * NCH * 8 * 4)) ||
         (e = salloc(s, &s->tgt, slots * s->links * 8 * 4)) || (e = salloc(s, &s->prm, NPAR * 4)) ||
         (e = salloc(s, &s->m, NPAR * 4)) || (e = salloc(s, &s->v, NPAR * 4)) ||
-        (e = salloc(s, &s->gpart, (size_t)s->nblocks * kWavesSur * NPAR * 4)) || (e = salloc(s, &s->grad, NPAR * 4)) ||
+        (e = salloc(s, &s->gpart, (size_t)s->nblocks * kWavesSur * NPAR * 4)) ||
+        (e = salloc(s, &s->gpart2, (size_t)kGradChunks * NPAR * 4)) || (e = salloc(s, &s->grad, NPAR * 4)) ||
         (e = salloc(s, &s->lpart, (size_t)s->nblocks * kWavesSur * 8)) || (e = salloc(s, &s->lsum, 16))) {
         lat->err = s->err;
         stag_surrogate_destroy(s);
@@ -633,7 +655,7 @@ stag_status stag_surrogate_create(stag_surrogate_handle* out, stag_handle lat, i
 stag_status stag_surrogate_destroy(stag_surrogate_handle s) {
     if (!s) return STAG_OK;
     if (s->lat && s->lat->s) hipStreamSynchronize(s->lat->s);
-    void* bufs[] = {s->f, s->B, s->tgt, s->prm, s->m, s->v, s->gpart, s->grad, s->lpart, s->lsum};
+    void* bufs[] = {s->f, s->B, s->tgt, s->prm, s->m, s->v, s->gpart, s->gpart2, s->grad, s->lpart, s->lsum};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (s->lsum_host) hipHostFree(s->lsum_host);
