@@ -107,9 +107,25 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     const MsIter& s = st->it[par];
     const int iter = s.iter;
     const int slot = iter % L;
-    // The base system's streams do not depend on this iteration's scalars:
-    // issue their loads before the scalar prologue so that their latency
-    // overlaps it.
+    // Partial sums of the previous launches (<r,r> of the step or init, and
+    // the three dots of the operator): each thread issues its first loads all
+    // together, then the loads of the base system's streams, which do not
+    // depend on this iteration's scalars, so that one memory round trip
+    // covers all of them; the partials are still added in index order.
+    constexpr int kUq = 4, kUd = 8;
+    const int nbq = gridDim.x;  // init and step kernels use the same grid
+    double tq[kUq], t1[kUd], t2[kUd], t3[kUd];
+    // (unconditional loads from clamped indices, masked afterwards, so that
+    // none of them sits behind a branch)
+#pragma unroll
+    for (int j = 0; j < kUq; ++j) tq[j] = qin[min((int)threadIdx.x + j * kBlock, nbq - 1)];
+#pragma unroll
+    for (int j = 0; j < kUd; ++j) {
+        const int b = min((int)threadIdx.x + j * kBlock, nb2 - 1);
+        t1[j] = dpart[b];
+        t2[j] = dpart[nb2 + b];
+        t3[j] = dpart[2 * nb2 + b];
+    }
     double2 pre_r[kEPT], pre_a[kEPT], pre_p[kEPT], pre_x[kEPT];
     {
         const V* rc = ring + (size_t)slot * n3;
@@ -126,9 +142,18 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
         }
     }
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const int nbq = gridDim.x;  // init and step kernels use the same grid
-    for (int b = threadIdx.x; b < nbq; b += kBlock) v[0] += qin[b];
-    for (int b = threadIdx.x; b < nb2; b += kBlock) {
+#pragma unroll
+    for (int j = 0; j < kUq; ++j)
+        if ((int)threadIdx.x + j * kBlock < nbq) v[0] += tq[j];
+#pragma unroll
+    for (int j = 0; j < kUd; ++j)
+        if ((int)threadIdx.x + j * kBlock < nb2) {
+            v[1] += t1[j];
+            v[2] += t2[j];
+            v[3] += t3[j];
+        }
+    for (int b = threadIdx.x + kUq * kBlock; b < nbq; b += kBlock) v[0] += qin[b];
+    for (int b = threadIdx.x + kUd * kBlock; b < nb2; b += kBlock) {
         v[1] += dpart[b];
         v[2] += dpart[nb2 + b];
         v[3] += dpart[2 * nb2 + b];
