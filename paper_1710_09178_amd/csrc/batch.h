@@ -23,6 +23,16 @@ struct BTile {
     int cb0;
 };
 
+// Window tables of one system: [lag][n] entries at stride n.
+constexpr int kWinTab = kLagMax * kMaxPoles;
+
+// Scalars of one system for the step kernel.
+struct BScal {
+    double alpha, beta;
+    int stop, flush, npend, nact, base_on, slot;
+    int list[kMaxPoles];  // shifts to update in a flush, increasing
+};
+
 // Per-system state (system s = instance * nrhs + rhs), double-buffered by parity.
 struct BState {
     int n_inst, nrhs, n, base, maxiter;
@@ -34,13 +44,16 @@ struct BState {
     // [2][n_sys] by iteration parity like inst_done: 1 once the system has stopped
     int* sys_done;
     // [2][n_inst] by iteration parity: flag [j & 1] is read by the launches of
-    // iteration j; the step of iteration j writes [(j + 1) & 1]
+    // iteration j; the scalar kernel of iteration j writes [(j + 1) & 1]
     int* inst_done;
     unsigned long long* t_done;  // [n_sys] device wall clock at the stop
     double* sigma0_term;  // [n_inst] 4 m_i^2 + sigma_0
     int lag;              // shift-update window (1..kLagMax); residual ring of `lag` vectors
     MsHist* hist;         // [n_sys][kLagMax] scalars of the pending iterations
     size_t ring_stride;   // entries between ring slots (one batched vector)
+    BScal* scal;          // [n_sys] this iteration's scalars (written by the scalar kernel)
+    double* w_tab;        // [n_sys][3][kWinTab] alpha_s, beta_s, zeta_s of the window's iterations
+    int* w_act;           // [n_sys][kWinTab] shift active in the window's iterations
 };
 
 // Internal batched vector: instance i's block starts at 3*R*off_i and holds
@@ -73,6 +86,10 @@ void launch_bdslash_resid(const BatchDev& bd, int tps, const double2* links, con
 template <class V>
 void launch_bms_init(const BatchDev& bd, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, BState st,
                      double* qout, hipStream_t s);
+// One block per instance: sums the instance's partials and evaluates the
+// scalars of its systems into st.scal / st.w_tab / st.w_act.
+void launch_bms_scalars(const BatchDev& bd, BState st, const double* dpart, const double* qin, int par,
+                        hipStream_t s);
 // r: the residual ring (st.lag slots of st.ring_stride entries)
 template <class V>
 void launch_bms_step(const BatchDev& bd, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, BState st,

@@ -257,15 +257,10 @@ __global__ __launch_bounds__(kBlock) void k_bms_init(BatchDev bd, const double2*
 // The shifted updates are deferred over windows of st.lag iterations as in
 // the single-lattice solver: the scalars of each iteration go to the
 // system's history, and the window's last iteration (or the stopping one)
-// applies them in order.  w_*: this system's [lag][n] tables in LDS.
-struct BScal {
-    double alpha, beta;
-    int stop, flush, npend, nact, base_on, slot;
-    int list[kMaxPoles];
-};
-
+// applies them in order.  w_*: this system's [lag][n] window tables.  Also
+// writes the system's state for the next iteration (or the final one).
 __device__ void bsystem_scalars(BState& st, int s, int par, double rr, double pAp, double rAp, double ApAp,
-                                bool writer, BScal& o, double* w_as, double* w_bs, double* w_zn, int* w_act) {
+                                BScal& o, double* w_as, double* w_bs, double* w_zn, int* w_act) {
     const int n = st.n, base = st.base, L = st.lag;
     const MsIter& S = st.it[par][s];
     const int iter = S.iter;
@@ -333,7 +328,7 @@ __device__ void bsystem_scalars(BState& st, int s, int par, double rr, double pA
         for (int k = 0; k < n; ++k)
             if (k != base && w_act[k]) o.list[m++] = k;  // active at the window's first iteration
     o.nact = m;
-    if (writer) {
+    {
         MsIter& N = stop ? st.fin[s] : st.it[par ^ 1][s];
         for (int k = 0; k < n; ++k) {
             const int a = stop ? 0 : w_act[slot * n + k];
@@ -362,29 +357,23 @@ __device__ void bsystem_scalars(BState& st, int s, int par, double rr, double pA
     }
 }
 
-template <class V>
-__global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict__ ring, const V* __restrict__ Ap,
-                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps, BState st,
-                                                     const double* __restrict__ dpart, const double* __restrict__ qin,
-                                                     double* __restrict__ qout, int par) {
-    const BTile tl = bd.tiles[blockIdx.x];
+// One block per instance: the sums over the instance's tiles (in tile
+// order) and the scalars of its systems, evaluated once per iteration instead
+// of in every tile of the step.  Reads the stop flags of parity par and
+// writes those of par ^ 1.
+__global__ __launch_bounds__(kBlock) void k_bms_scalars(BatchDev bd, BState st, const double* __restrict__ dpart,
+                                                        const double* __restrict__ qin, int par) {
+    const int inst = blockIdx.x;
     const int* done_in = st.inst_done + par * st.n_inst;
     int* done_out = st.inst_done + (par ^ 1) * st.n_inst;
-    if (done_in[tl.inst]) {
-        if (blockIdx.x == bd.inst[tl.inst].tile0 && threadIdx.x == 0) done_out[tl.inst] = 1;
+    if (done_in[inst]) {
+        if (threadIdx.x == 0) done_out[inst] = 1;
         return;
     }
-    const BInst I = bd.inst[tl.inst];
-    const int R = bd.nrhs, SB = bd.tile_sites, n = st.n, L = st.lag;
-    __shared__ BScal sc[kMaxRhs];
+    const BInst I = bd.inst[inst];
+    const int R = bd.nrhs;
     __shared__ double lds[4 * 4 * kMaxRhs];
-    // window tables [rhs][lag][n]: as, bs, zn (double) then act (int)
-    extern __shared__ double wdyn[];
-    const int wsz = L * n;
-    double* w_as = wdyn;
-    double* w_bs = w_as + kMaxRhs * wsz;
-    double* w_zn = w_bs + kMaxRhs * wsz;
-    int* w_act = (int*)(w_zn + kMaxRhs * wsz);
+    __shared__ int sh_stop[kMaxRhs];
     // sums over the lattice's tiles: [rhs] rr, [rhs][3] dots
     double v[4 * kMaxRhs];
 #pragma unroll
@@ -404,29 +393,72 @@ __global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict_
         for (int k = 0; k < 4 * kMaxRhs; ++k) lds[k] = v[k];
     }
     __syncthreads();
-    const bool writer = (blockIdx.x == I.tile0);
     // stopped before this launch; a stop in this launch is written to the other parity
     const int* sys_in = st.sys_done + (size_t)par * st.n_inst * R;
     int* sys_out = st.sys_done + (size_t)(par ^ 1) * st.n_inst * R;
     if (threadIdx.x < R) {
         const int q = threadIdx.x;
-        const int s = tl.inst * R + q;
+        const int s = inst * R + q;
+        BScal& o = st.scal[s];
         if (sys_in[s]) {
-            if (writer) sys_out[s] = 1;
-            sc[q].stop = 1;
-            sc[q].flush = 0;
-            sc[q].nact = 0;
-            sc[q].base_on = 0;
+            sys_out[s] = 1;
+            o.stop = 1;
+            o.flush = 0;
+            o.nact = 0;
+            o.base_on = 0;
+            sh_stop[q] = 1;
         } else {
-            bsystem_scalars(st, s, par, lds[4 * q], lds[4 * q + 1], lds[4 * q + 2], lds[4 * q + 3], writer, sc[q],
-                            w_as + q * wsz, w_bs + q * wsz, w_zn + q * wsz, w_act + q * wsz);
+            double* wt = st.w_tab + (size_t)s * 3 * kWinTab;
+            bsystem_scalars(st, s, par, lds[4 * q], lds[4 * q + 1], lds[4 * q + 2], lds[4 * q + 3], o, wt,
+                            wt + kWinTab, wt + 2 * kWinTab, st.w_act + (size_t)s * kWinTab);
+            sh_stop[q] = o.stop;
         }
     }
     __syncthreads();
-    if (writer && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
         int all = 1;
-        for (int q = 0; q < R; ++q) all &= (sys_in[tl.inst * R + q] | sc[q].stop);
-        if (all) done_out[tl.inst] = 1;
+        for (int q = 0; q < R; ++q) all &= sh_stop[q];
+        if (all) done_out[inst] = 1;
+    }
+}
+
+template <class V>
+__global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict__ ring, const V* __restrict__ Ap,
+                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps, BState st,
+                                                     double* __restrict__ qout, int par) {
+    const BTile tl = bd.tiles[blockIdx.x];
+    if (st.inst_done[par * st.n_inst + tl.inst]) return;
+    const BInst I = bd.inst[tl.inst];
+    const int R = bd.nrhs, SB = bd.tile_sites, n = st.n, L = st.lag;
+    __shared__ BScal sc[kMaxRhs];
+    __shared__ double lds[4 * kMaxRhs];
+    // window tables [rhs][lag][n]: as, bs, zn (double) then act (int)
+    extern __shared__ double wdyn[];
+    const int wsz = L * n;
+    double* w_as = wdyn;
+    double* w_bs = w_as + kMaxRhs * wsz;
+    double* w_zn = w_bs + kMaxRhs * wsz;
+    int* w_act = (int*)(w_zn + kMaxRhs * wsz);
+    {
+        constexpr int words = (int)(sizeof(BScal) / sizeof(int));
+        const int* src = (const int*)(st.scal + (size_t)tl.inst * R);
+        int* dst = (int*)sc;
+        for (int w = threadIdx.x; w < R * words; w += kBlock) dst[w] = src[w];
+    }
+    __syncthreads();
+    int anyflush = 0;
+    for (int q = 0; q < R; ++q) anyflush |= sc[q].flush;
+    if (anyflush) {
+        for (int e = threadIdx.x; e < R * wsz; e += kBlock) {
+            const int q = e / wsz, j = e % wsz;
+            const size_t sy = (size_t)tl.inst * R + q;
+            const double* wt = st.w_tab + sy * 3 * kWinTab;
+            w_as[e] = wt[j];
+            w_bs[e] = wt[kWinTab + j];
+            w_zn[e] = wt[2 * kWinTab + j];
+            w_act[e] = st.w_act[sy * kWinTab + j];
+        }
+        __syncthreads();
     }
     double acc[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
     const int base = st.base;
@@ -638,13 +670,20 @@ template void launch_bms_init<float2>(const BatchDev&, const double2*, float2*, 
 template <class V>
 void launch_bms_step(const BatchDev& bd, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, BState st,
                      const double* dpart, const double* qin, double* qout, int par, hipStream_t s) {
+    (void)dpart;
+    (void)qin;
     const size_t lds = (size_t)kMaxRhs * st.lag * st.n * (3 * sizeof(double) + sizeof(int));
-    k_bms_step<V><<<bd.ntiles, kBlock, lds, s>>>(bd, r, Ap, p, x, ps, st, dpart, qin, qout, par);
+    k_bms_step<V><<<bd.ntiles, kBlock, lds, s>>>(bd, r, Ap, p, x, ps, st, qout, par);
 }
 template void launch_bms_step<double2>(const BatchDev&, double2*, const double2*, double2*, VecPtrs, VecPtrs, BState,
                                        const double*, const double*, double*, int, hipStream_t);
 template void launch_bms_step<float2>(const BatchDev&, float2*, const float2*, float2*, VecPtrs, VecPtrs, BState,
                                       const double*, const double*, double*, int, hipStream_t);
+
+void launch_bms_scalars(const BatchDev& bd, BState st, const double* dpart, const double* qin, int par,
+                        hipStream_t s) {
+    k_bms_scalars<<<st.n_inst, kBlock, 0, s>>>(bd, st, dpart, qin, par);
+}
 
 void launch_bsys_sum(const BatchDev& bd, int n_inst, const double* part, double* out, hipStream_t s) {
     const int n = n_inst * bd.nrhs;

@@ -188,6 +188,7 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
             const int* gate = st.inst_done + par * c->n_inst;
             launch_bdslash<V>(bd, c->tps, links, p, w, 1, gate, c->s);
             launch_bdslash_cg<V>(bd, c->tps, links, w, p, rj, Ap, st, gate, c->dpart, c->s);
+            launch_bms_scalars(bd, st, c->dpart, c->qpart[par], par, c->s);
             launch_bms_step<V>(bd, r, Ap, p, X, P, st, c->dpart, c->qpart[par], c->qpart[par ^ 1], par, c->s);
         }
     };
@@ -318,7 +319,10 @@ stag_status stag_batch_create(stag_batch_handle* out, int n_inst, const int* dim
         (s = balloc(c, &st.inst_done, 2 * n_inst * sizeof(int))) ||
         (s = balloc(c, &st.t_done, (c->n_sys + 1) * sizeof(unsigned long long))) ||
         (s = balloc(c, &st.sigma0_term, n_inst * sizeof(double))) ||
-        (s = balloc(c, &st.hist, (size_t)c->n_sys * kLagMax * sizeof(MsHist))) || (s = balloc(c, &c->sums, c->n_sys * sizeof(double))))
+        (s = balloc(c, &st.hist, (size_t)c->n_sys * kLagMax * sizeof(MsHist))) ||
+        (s = balloc(c, &st.scal, c->n_sys * sizeof(BScal))) ||
+        (s = balloc(c, &st.w_tab, (size_t)c->n_sys * 3 * kWinTab * sizeof(double))) ||
+        (s = balloc(c, &st.w_act, (size_t)c->n_sys * kWinTab * sizeof(int))) || (s = balloc(c, &c->sums, c->n_sys * sizeof(double))))
         return bail(s);
     if (hipHostMalloc((void**)&c->done_host, 2 * n_inst * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->sums_host, c->n_sys * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -341,7 +345,7 @@ stag_status stag_batch_destroy(stag_batch_handle c) {
     if (c->s) hipStreamSynchronize(c->s);
     void* bufs[] = {c->inst_d, c->tiles_d, c->links64, c->links32, c->b, c->r, c->p, c->Ap, c->w, c->e, c->res,
                     c->pool_x, c->pool_p, c->st.it[0], c->st.it[1], c->st.fin, c->st.sys_done, c->st.inst_done,
-                    c->st.t_done, c->st.sigma0_term, c->st.hist, c->dpart, c->qpart[0], c->qpart[1], c->gpart, c->sums};
+                    c->st.t_done, c->st.sigma0_term, c->st.hist, c->st.scal, c->st.w_tab, c->st.w_act, c->dpart, c->qpart[0], c->qpart[1], c->gpart, c->sums};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (c->done_host) hipHostFree(c->done_host);
