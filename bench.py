@@ -401,7 +401,7 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     out = {"workload": f"{len(dims)} lattices (16 each of 8^4, 12^3x6, 16^3x8, 24^3x6) x {nrhs} right-hand "
                        f"sides x 12 poles of x^(-1/4), masses U[0.005, 0.05], tol 1e-10",
            "systems": len(dims) * nrhs, "sites": int(sum(np.prod(d) for d in dims)),
-           "tune_us_tps_1_2_4": [round(u, 2) for u in tuned]}
+           "tune_us_tps_1_2_4_8": [round(u, 2) for u in tuned]}
     for name, prec in (("fp64", 0), ("mixed_fp32_fp64", 1)):
         B.solve(masses, rat, b, precision=prec, true_resid=False)
         torch.cuda.synchronize()

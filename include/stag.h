@@ -353,9 +353,13 @@ stag_status stag_batch_solve(stag_batch_handle b, const double* masses, const st
  * iterations (default 8); results do not depend on it.  Tuning. */
 stag_status stag_batch_set_shift_window(stag_batch_handle b, int lag);
 /* Autotune the Dslash work split for this batch: times the batched operator
- * for 1, 2 and 4 threads per site (precision 0 or 1) and keeps the fastest.
- * us_out: NULL or host [3] microseconds per application. */
+ * for 1, 2, 4 and 8 threads per site (precision 0 or 1) and keeps the
+ * fastest.  us_out: NULL or host [4] microseconds per application. */
 stag_status stag_batch_tune(stag_batch_handle b, int precision, double* us_out);
+/* Set the Dslash work split directly: 1, 2 or 4 threads per site share the
+ * four directions of a site through LDS; 8 lanes per site take one hop each
+ * and combine by lane exchanges.  Results agree to rounding.  Tuning. */
+stag_status stag_batch_set_tps(stag_batch_handle b, int tps);
 
 /* ---- measurement and tuning (not part of the method) ---------------------- */
 

@@ -210,12 +210,90 @@ __global__ __launch_bounds__(kBlock) void k_bdslash(BatchDev bd, const V* __rest
     epi.finish(blockIdx.x, racc);
 }
 
+// Eight lanes per output site, one hop each: lane h takes direction h / 2,
+// the forward hop U_mu(x) p(x+mu) for even h and the backward hop
+// U_mu(x-mu)^dag p(x-mu) for odd h (its matrix is loaded transposed and
+// conjugated, so both kinds run the same arithmetic).  Each lane holds one
+// link matrix, the eight partial colour vectors of a site meet by lane
+// exchanges (no LDS), and every right-hand side is finished right after its
+// exchange: its three (rhs, colour) outputs go to lanes (3 rhs + colour) mod 8.
+template <class V, class Epi>
+__global__ __launch_bounds__(kBlock) void k_bdslash8(BatchDev bd, const V* __restrict__ links,
+                                                     const V* __restrict__ in, int out_par, Epi epi,
+                                                     const int* __restrict__ inst_done) {
+    using Rl = typename BPrec<V>::R;
+    const BTile tl = bd.tiles[blockIdx.x];
+    if (inst_done && inst_done[tl.inst]) return;
+    const BInst I = bd.inst[tl.inst];
+    const Geom& g = I.g;
+    const int R = bd.nrhs;
+    const int h = threadIdx.x & 7, mu = h >> 1;
+    const bool bwd = h & 1;
+    const int cb = tl.cb0 + (int)(threadIdx.x >> 3);
+    const bool on = cb < g.vh;
+    V U[9];
+    int nbr = 0;
+    Rl sg = 0;
+    if (on) {
+        int x, y, z, t;
+        cb_coords(g, out_par, cb, x, y, z, t);
+        int cbf, cbb;
+        bool nf, nb;
+        bhop_geometry(g, mu, x, y, z, t, cbf, cbb, nf, nb);
+        const V* lk = links + blink_base(I);
+        const V* u = bwd ? lk + link_off(g, 1 - out_par, mu, 0) + cbb : lk + link_off(g, out_par, mu, 0) + cb;
+        const Rl cj = bwd ? Rl(-1) : Rl(1);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            const int src = bwd ? 3 * (e % 3) + e / 3 : e;
+            const V v = u[(size_t)src * g.vh];
+            U[e] = V{v.x, cj * v.y};
+        }
+        nbr = bwd ? cbb : cbf;
+        sg = bwd ? (nb ? Rl(1) : Rl(-1)) : (nf ? Rl(-1) : Rl(1));
+    } else {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) U[e] = V{0, 0};
+    }
+    double racc[Epi::K];
+#pragma unroll
+    for (int k = 0; k < Epi::K; ++k) racc[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < kMaxRhs; ++r) {
+        if (r >= R) break;
+        V pv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pv[c] = on ? in[bvec_off(I, R, r, c) + nbr] : V{0, 0};
+        V a[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            V f = cmul(U[3 * c], pv[0]);
+            f = cadd(f, cmul(U[3 * c + 1], pv[1]));
+            f = cadd(f, cmul(U[3 * c + 2], pv[2]));
+            a[c] = V{sg * f.x, sg * f.y};
+        }
+#pragma unroll
+        for (int m = 1; m < 8; m <<= 1)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                a[c].x += __shfl_xor(a[c].x, m, 64);
+                a[c].y += __shfl_xor(a[c].y, m, 64);
+            }
+        if (on)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((3 * r + c) % 8 == h) epi.item(I, tl.inst, R, r, cb, c, a[c], racc);
+    }
+    epi.finish(blockIdx.x, racc);
+}
+
 template <class V, class Epi>
 void bdslash_tps(const BatchDev& bd, int tps, const V* links, const V* in, int out_par, const Epi& epi,
                  const int* inst_done, hipStream_t s) {
     switch (tps) {
         case 1: k_bdslash<1, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
         case 2: k_bdslash<2, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+        case 8: k_bdslash8<V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
         default: k_bdslash<4, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
     }
 }

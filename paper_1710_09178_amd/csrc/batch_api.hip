@@ -502,6 +502,14 @@ stag_status stag_batch_set_shift_window(stag_batch_handle c, int lag) {
     return STAG_OK;
 }
 
+stag_status stag_batch_set_tps(stag_batch_handle c, int tps) {
+    if (!c) return bfail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
+    if (tps != 1 && tps != 2 && tps != 4 && tps != 8)
+        return bfail(c, STAG_ERR_INVALID_ARG, "threads per site must be 1, 2, 4 or 8");
+    c->tps = tps;
+    return build_tiles(c);
+}
+
 stag_status stag_batch_tune(stag_batch_handle c, int precision, double* us_out) {
     if (!c) return bfail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
     if (precision != 0 && precision != 1) return bfail(c, STAG_ERR_INVALID_ARG, "precision must be 0 or 1");
@@ -512,8 +520,8 @@ stag_status stag_batch_tune(stag_batch_handle c, int precision, double* us_out) 
     BHIP(c, hipEventCreate(&b));
     double best = 1e300;
     int best_tps = c->tps;
-    const int cand[3] = {1, 2, 4};
-    for (int q = 0; q < 3; ++q) {
+    const int cand[4] = {1, 2, 4, 8};
+    for (int q = 0; q < 4; ++q) {
         c->tps = cand[q];
         if ((e = build_tiles(c))) return e;
         const BatchDev bd = bdev(c);

@@ -150,6 +150,7 @@ def load_library() -> ctypes.CDLL:
         "stag_set_shift_window": (S, [H, I]),
         "stag_set_graphs": (S, [H, I]),
         "stag_batch_set_shift_window": (S, [H, I]),
+        "stag_batch_set_tps": (S, [H, I]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
         "stag_tune": (S, [H, I, I]),
@@ -452,8 +453,11 @@ class Batch:
     def set_shift_window(self, lag: int):
         self._check(self.lib.stag_batch_set_shift_window(self.h, int(lag)))
 
+    def set_tps(self, tps: int):
+        self._check(self.lib.stag_batch_set_tps(self.h, int(tps)))
+
     def tune(self, precision=0):
-        us = (ctypes.c_double * 3)()
+        us = (ctypes.c_double * 4)()
         self._check(self.lib.stag_batch_tune(self.h, int(precision), us))
         return list(us)
 

@@ -42,8 +42,21 @@ def _unpack(x_pole, nrhs):
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("nrhs", [1, 3, 4])
 def test_batch_matches_oracle(precision, nrhs):
-    log(f"batched solve precision={precision} nrhs={nrhs}")
+    _check_against_oracle(precision, nrhs, None)
+
+
+@pytest.mark.parametrize("precision,nrhs", [(0, 1), (0, 4), (1, 3)])
+def test_eight_lanes_per_site_matches_oracle(precision, nrhs):
+    """The hop-per-lane Dslash (8 lanes per site, lane exchanges instead of
+    LDS), including the 2^4 lattice whose single tile is mostly off-lattice."""
+    _check_against_oracle(precision, nrhs, 8)
+
+
+def _check_against_oracle(precision, nrhs, tps):
+    log(f"batched solve precision={precision} nrhs={nrhs} tps={tps}")
     B, Us, masses, bs, bdev_ = _setup(nrhs)
+    if tps:
+        B.set_tps(tps)
     rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
     x, info = B.solve(masses, rat, bdev_, precision=precision, tol=1e-10)
     xh = host(x)
@@ -75,7 +88,9 @@ def test_graph_and_stream_paths_agree_bitwise():
 def test_tune_and_errors():
     B, Us, masses, bs, bd = _setup(2, seed=2)
     us = B.tune(0)
-    assert len(us) == 3 and all(u > 0 for u in us)
+    assert len(us) == 4 and all(u > 0 for u in us)
+    with pytest.raises(stag.StagError):
+        B.set_tps(3)
     rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
     x, info = B.solve(masses, rat, bd)   # still correct after retiling
     assert info["true_resid"].max() < 1e-10
