@@ -195,6 +195,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--chain-traj", type=int, default=24, help="trajectories per learned-force comparison chain")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-mode", action="store_true", help="one solve + a 512 MiB copy, for counter runs")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
@@ -276,7 +277,7 @@ def main():
     rh = None
     if not args.no_trajectory:
         log("RHMC at 16^3x8" + ("" if args.no_surrogate else " with and without the learned force model"))
-        rh = rhmc(with_model=not args.no_surrogate)
+        rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj)
 
     out = {
         "metric": "multishift-CG Dslash GB/s (% HBM peak) at 32^3x8; sec/RHMC trajectory",
@@ -496,6 +497,7 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     if not with_model:
         return out
 
+    log(f"recording {n_pairs} training pairs")
     sur = Surrogate(lat, n_pairs, seed=1)
     rec = []
     t0 = time.perf_counter()
@@ -540,6 +542,7 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     err_model, err_trunc = force_errors()
 
     def chain(**extra):
+        log(f"chain of {n_traj} trajectories: " + ", ".join(f"{k}={v}" for k, v in extra.items() if k != "surrogate"))
         lat.set_gauge(U_start)
         torch.cuda.synchronize()
         res = []
