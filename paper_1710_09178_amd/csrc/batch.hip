@@ -627,15 +627,18 @@ __global__ __launch_bounds__(kBlock) void k_bms_step(BatchDev bd, V* __restrict_
         for (int q = 0; q < kMaxRhs; ++q) qout[(size_t)blockIdx.x * kMaxRhs + q] = acc[q];
 }
 
-__global__ void k_bsys_sum(BatchDev bd, int n_inst, const double* __restrict__ part, double* __restrict__ out) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// one block per system: its (tile, rhs) partials over the instance's tiles
+__global__ __launch_bounds__(kBlock) void k_bsys_sum(BatchDev bd, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+    const int s = blockIdx.x;
     const int R = bd.nrhs;
-    if (s >= n_inst * R) return;
     const BInst I = bd.inst[s / R];
     const int q = s % R;
-    double t = 0.0;
-    for (int k = 0; k < I.ntiles; ++k) t += part[(size_t)(I.tile0 + k) * kMaxRhs + q];
-    out[s] = t;
+    double t[1] = {0.0};
+    for (int k = threadIdx.x; k < I.ntiles; k += kBlock) t[0] += part[(size_t)(I.tile0 + k) * kMaxRhs + q];
+    __shared__ double lds[4];
+    block_sum<1>(t, lds);
+    if (threadIdx.x == 0) out[s] = t[0];
 }
 
 // canonical packed [inst][rhs][site][colour] <-> internal [inst][rhs][colour][site]
@@ -765,7 +768,7 @@ void launch_bms_scalars(const BatchDev& bd, BState st, const double* dpart, cons
 
 void launch_bsys_sum(const BatchDev& bd, int n_inst, const double* part, double* out, hipStream_t s) {
     const int n = n_inst * bd.nrhs;
-    k_bsys_sum<<<(n + 255) / 256, 256, 0, s>>>(bd, n_inst, part, out);
+    k_bsys_sum<<<n, kBlock, 0, s>>>(bd, part, out);
 }
 
 void launch_bvec_import(const BatchDev& bd, const double2* canon, double2* vec, hipStream_t s) {
