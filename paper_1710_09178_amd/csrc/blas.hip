@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
                                                     int nb2, const double* __restrict__ qin, double* __restrict__ qout,
                                                     int par) {
     if (st->done[par]) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->done[par ^ 1] = 1;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st->done[par ^ 1] = 1;
         return;
     }
     __shared__ double lds[16];
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
                     w_act[slot][k] = act;
                 }
             }
-            if (blockIdx.x == 0) {
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
                 // the state of the next iteration (or the final one)
                 MsIter& o = stop ? st->fin : st->it[par ^ 1];
                 o.active[k] = act;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
             sh_stop = stop;
             sh_nact = __popcll(lmask);
             sh_base_on = base_act;
-            if (blockIdx.x == 0) {
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
                 MsIter& o = stop ? st->fin : st->it[par ^ 1];
                 o.alpha_old = stop ? s.alpha_old : alpha;
                 o.beta_old = stop ? s.beta_old : beta;
@@ -263,6 +263,14 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     const bool base_on = sh_base_on;
     const int nact = sh_nact;
     V* r_next = ring + (size_t)((slot + 1) % L) * n3;
+    // Launches at the end of a window of L >= 2 may carry gridDim.y > 1: row 0
+    // updates the base system and every row takes the shift groups y,
+    // y + gridDim.y, ... of the flush, so the flush of one element runs on
+    // several blocks (each recomputes r_{j+1} from the same inputs, bitwise
+    // alike).  Rows other than 0 read only what no block writes in this
+    // launch: r_j (slot j % L, while r_{j+1} goes to another slot), Ap, the
+    // older ring slots and their own shifts' x_s, p_s.
+    const bool row0 = blockIdx.y == 0;
     double acc[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < kEPT; ++e) {
@@ -278,14 +286,16 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
             rv.x -= alpha * a.x;
             rv.y -= alpha * a.y;
             const V rl = from_d2<V>(rv);
-            r_next[i] = rl;
             rv = to_d2(rl);
-            acc[0] += rv.x * rv.x + rv.y * rv.y;
-            if (base_on) {
-                const double2 xbv = pre_x[e];
-                nt_store(xb + i, make_double2(xbv.x + alpha * pv.x, xbv.y + alpha * pv.y));
+            if (row0) {
+                r_next[i] = rl;
+                acc[0] += rv.x * rv.x + rv.y * rv.y;
+                if (base_on) {
+                    const double2 xbv = pre_x[e];
+                    nt_store(xb + i, make_double2(xbv.x + alpha * pv.x, xbv.y + alpha * pv.y));
+                }
+                p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
             }
-            p[i] = from_d2<V>(make_double2(rv.x + beta * pv.x, rv.y + beta * pv.y));
         }
         if (!flush) continue;
         // residuals r_{i+1} of the pending iterations i = iter - slot + t
@@ -303,8 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
         }
         // shifted poles in groups: all loads of a group are issued before its
         // stores (the pointers may not be proven distinct by the compiler)
-        constexpr int G = 4;
-        for (int g0 = 0; g0 < nact; g0 += G) {
+        constexpr int G = kFlushGroup;
+        for (int g0 = blockIdx.y * G; g0 < nact; g0 += gridDim.y * G) {
             double2 pk[G], xk[G];
 #pragma unroll
             for (int j = 0; j < G; ++j) {
@@ -341,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
             }
         }
     }
-    block_partial<1>(acc, qout);
+    if (row0) block_partial<1>(acc, qout);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rational_sum(int n3, const double2* __restrict__ b, VecPtrs x,
@@ -410,14 +420,14 @@ template void launch_ms_init<float2>(const Geom&, const double2*, float2*, float
 
 template <class V>
 void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
-                    int nb2, const double* qin, double* qout, int par, hipStream_t s) {
-    timed_launch(k_ms_step<V>, dim3(gridq(g)), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin, qout,
-                 par);
+                    int nb2, const double* qin, double* qout, int par, int rows, hipStream_t s) {
+    timed_launch(k_ms_step<V>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin,
+                 qout, par);
 }
 template void launch_ms_step<double2>(const Geom&, double2*, const double2*, double2*, VecPtrs, VecPtrs, MsState*,
-                                      const double*, int, const double*, double*, int, hipStream_t);
+                                      const double*, int, const double*, double*, int, int, hipStream_t);
 template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2*, VecPtrs, VecPtrs, MsState*,
-                                     const double*, int, const double*, double*, int, hipStream_t);
+                                     const double*, int, const double*, double*, int, int, hipStream_t);
 
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
     k_cg_restart<<<gridq(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);

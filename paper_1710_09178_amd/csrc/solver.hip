@@ -153,7 +153,7 @@ struct ChunkKey {
     const void* dpart;
     const void* qpart[2];
     double mt;
-    int tps, lag, chunk, nb2, v64;
+    int tps, lag, chunk, nb2, v64, n;
 };
 
 hipGraphExec_t cached_graph(stag_ctx* c, const ChunkKey& key) {
@@ -212,8 +212,18 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             Krylov<V>::deo_cg(g, ls, K.w, K.p, rj, K.Ap, gate, c->dpart, c->tps, c->s, mt);
             prof_end(c, a, 1, rec);
             prof_begin(c, &a);
+            // the last iteration of a window flushes the shifted updates; on
+            // lattices whose step grid is small the flush is latency-bound,
+            // and up to one block row per group of shifts spreads it (up to
+            // ~512 blocks in all).  Not with a window of 1, where r_{j+1}
+            // overwrites r_j in place (only the thread that read r_j may
+            // write it).
+            const int nsh = c->st_host->n - 1;
+            const int rows = (L > 1 && it_issued % L == L - 1 && nsh > 0)
+                                 ? std::max(1, std::min((nsh + kFlushGroup - 1) / kFlushGroup, 512 / ms_update_grid(g)))
+                                 : 1;
             launch_ms_step<V>(g, K.r, K.Ap, K.p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
-                              c->s);
+                              rows, c->s);
             prof_end(c, a, 2, rec);
         }
     };
@@ -236,6 +246,7 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
         key.mt = mt;
         key.tps = c->tps;
         key.lag = L;
+        key.n = c->st_host->n;
         key.chunk = chunk;
         key.nb2 = nb2;
         key.v64 = sizeof(V) == sizeof(double2);
