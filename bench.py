@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--chain-traj", type=int, default=24, help="trajectories per learned-force comparison chain")
+    ap.add_argument("--inner-iters", type=int, default=200,
+                    help="iterations of the truncated solve that feeds the learned model's auxiliary channel")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-mode", action="store_true", help="one solve + a 512 MiB copy, for counter runs")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
@@ -277,7 +279,7 @@ def main():
     rh = None
     if not args.no_trajectory:
         log("RHMC at 16^3x8" + ("" if args.no_surrogate else " with and without the learned force model"))
-        rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj)
+        rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj, inner_iters=args.inner_iters)
 
     out = {
         "metric": "multishift-CG Dslash GB/s (% HBM peak) at 32^3x8; sec/RHMC trajectory",
