@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     MsState* __restrict__ st, const double* __restrict__ dpart,
                                                     int nb2, const double* __restrict__ qin, double* __restrict__ qout,
-                                                    int par) {
+                                                    int par, MsStepConst sc) {
     if (st->done[par]) {
         if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st->done[par ^ 1] = 1;
         return;
@@ -103,10 +103,11 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     __shared__ int w_act[kLagMax][kMaxPoles];
     __shared__ double sh_alpha, sh_beta;
     __shared__ int sh_stop, sh_nact, sh_base_on;
-    const int n = st->n, base = st->base, L = st->lag;
+    // n, base, lag and the ring slot come with the launch, so the stream
+    // addresses below do not wait for the state
+    const int n = sc.n, base = sc.base, L = sc.lag, slot = sc.slot;
     const MsIter& s = st->it[par];
     const int iter = s.iter;
-    const int slot = iter % L;
     // Partial sums of the previous launches (<r,r> of the step or init, and
     // the three dots of the operator): each thread issues its first loads all
     // together, then the loads of the base system's streams, which do not
@@ -420,14 +421,16 @@ template void launch_ms_init<float2>(const Geom&, const double2*, float2*, float
 
 template <class V>
 void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
-                    int nb2, const double* qin, double* qout, int par, int rows, hipStream_t s) {
+                    int nb2, const double* qin, double* qout, int par, int rows, MsStepConst sc, hipStream_t s) {
     timed_launch(k_ms_step<V>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin,
-                 qout, par);
+                 qout, par, sc);
 }
 template void launch_ms_step<double2>(const Geom&, double2*, const double2*, double2*, VecPtrs, VecPtrs, MsState*,
-                                      const double*, int, const double*, double*, int, int, hipStream_t);
+                                      const double*, int, const double*, double*, int, int, MsStepConst,
+                                      hipStream_t);
 template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2*, VecPtrs, VecPtrs, MsState*,
-                                     const double*, int, const double*, double*, int, int, hipStream_t);
+                                     const double*, int, const double*, double*, int, int, MsStepConst,
+                                     hipStream_t);
 
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
     k_cg_restart<<<gridq(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);

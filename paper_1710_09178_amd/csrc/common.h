@@ -318,13 +318,18 @@ void launch_ms_init(const Geom& g, const double2* b, V* r, V* p, VecPtrs x, VecP
                     double* qout, hipStream_t s);
 // Shifted systems updated together per thread in a window flush.
 constexpr int kFlushGroup = 4;
+// Constants of one step launch: MsState's n, base and lag, and the ring slot
+// j % lag of its iteration j.
+struct MsStepConst {
+    int n, base, lag, slot;
+};
 // one iteration's scalars (from the partials of the previous kernels) and the
 // fused r, p, x_k, p_k update; par = iteration parity.  x_k stay FP64.
 // rows > 1 spreads a window flush's shift groups over that many block rows
 // (any rows >= 1 gives the same results).
 template <class V>
 void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
-                    int nb2, const double* qin, double* qout, int par, int rows, hipStream_t s);
+                    int nb2, const double* qin, double* qout, int par, int rows, MsStepConst sc, hipStream_t s);
 // p = r and partials of |r|^2 (restart of a CG from a given residual)
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s);
 // out = c0 b + sum_k coef_k x_k with c0, coef, n read from st

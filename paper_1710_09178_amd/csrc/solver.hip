@@ -153,7 +153,7 @@ struct ChunkKey {
     const void* dpart;
     const void* qpart[2];
     double mt;
-    int tps, lag, chunk, nb2, v64, n;
+    int tps, lag, chunk, nb2, v64, n, base;
 };
 
 hipGraphExec_t cached_graph(stag_ctx* c, const ChunkKey& key) {
@@ -222,8 +222,12 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             const int rows = (L > 1 && it_issued % L == L - 1 && nsh > 0)
                                  ? std::max(1, std::min((nsh + kFlushGroup - 1) / kFlushGroup, 512 / ms_update_grid(g)))
                                  : 1;
+            // every launch that runs has device iteration it_issued (a
+            // stopped solve's later launches exit at the flag), and a
+            // replayed chunk starts at a multiple of its length, hence of L
+            const MsStepConst sc{c->st_host->n, c->st_host->base, L, it_issued % L};
             launch_ms_step<V>(g, K.r, K.Ap, K.p, X, P, c->st, c->dpart, nb2, c->qpart[par], c->qpart[par ^ 1], par,
-                              rows, c->s);
+                              rows, sc, c->s);
             prof_end(c, a, 2, rec);
         }
     };
@@ -247,6 +251,7 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
         key.tps = c->tps;
         key.lag = L;
         key.n = c->st_host->n;
+        key.base = c->st_host->base;
         key.chunk = chunk;
         key.nb2 = nb2;
         key.v64 = sizeof(V) == sizeof(double2);
