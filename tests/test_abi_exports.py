@@ -88,3 +88,25 @@ def test_binding_signatures_match_the_header():
                 assert at in scalar, (name, decl, at)
         checked += 1
     assert checked >= 25
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback: without the built library every entry raises."""
+    from paper_1710_09178_amd import stag as S
+    monkeypatch.setattr(S, "_lib", None)
+    monkeypatch.setattr(S, "LIB_PATH", os.path.join(ROOT, "paper_1710_09178_amd", "no_such_libstag.so"))
+    with pytest.raises(RuntimeError):
+        S.load_library()
+    with pytest.raises(RuntimeError):
+        S.Lattice((4, 4, 4, 4))
+
+
+def test_product_package_does_not_use_the_oracle():
+    """The HIP path and the oracle share nothing: no module of the package
+    imports or names the oracle."""
+    pkg = os.path.join(ROOT, "paper_1710_09178_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
