@@ -125,6 +125,28 @@ def test_shift_window_does_not_change_results(precision):
         B.set_shift_window(3)
 
 
+def test_eight_lanes_per_site_window_invariance_and_agreement():
+    """With the hop-per-lane operator (32-site tiles) windows 1 and 8 agree
+    bitwise, and the solutions agree with the 4-threads-per-site split (the
+    two sum a site's hops in different orders; both reach the FP64 true
+    residual, so they differ by at most tol times the condition number)."""
+    B, Us, masses, bs, bd = _setup(4, seed=4)
+    rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
+    out = {}
+    for tps in (4, 8):
+        B.set_tps(tps)
+        for lag in (1, 8):
+            log(f"batched tps={tps} window {lag}")
+            B.set_shift_window(lag)
+            x, info = B.solve(masses, rat, bd)
+            out[tps, lag] = host(x)
+            assert info["true_resid"].max() < 1e-10
+    assert np.array_equal(out[8, 1], out[8, 8])
+    assert np.array_equal(out[4, 1], out[4, 8])
+    ref = out[4, 8]
+    assert np.abs(out[8, 8] - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
 def test_large_instances_window_and_residuals():
     """Many more tiles than the GPU runs at once (6 x 24^3x6 + 2 x 16^3x8 +
     8^4, 4 right-hand sides: 2216 tiles of 128 sites) and the 12-pole table:
