@@ -15,16 +15,18 @@ namespace stag {
 
 namespace {
 
-constexpr int kEPTi = 2;  // must equal kEPT of the step kernel (same grid)
-
-template <class V>
+// The init, restart and step kernels share one grid: EPT complex elements
+// per thread (2, or 1 on small lattices, where more blocks shorten the
+// latency-bound steps); the step sums the partials of init or of the previous
+// step, one per block of that grid.
+template <class V, int EPT>
 __global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __restrict__ b, V* __restrict__ r,
                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     const MsState* __restrict__ st, double* __restrict__ qout) {
     const int n = st->n, base = st->base;
     double acc[1] = {0.0};
-    for (int e = 0; e < kEPTi; ++e) {
-        const int i = (blockIdx.x * kEPTi + e) * kBlock + threadIdx.x;
+    for (int e = 0; e < EPT; ++e) {
+        const int i = (blockIdx.x * EPT + e) * kBlock + threadIdx.x;
         if (i >= n3) continue;
         const double2 bv = b[i];
         const V bl = from_d2<V>(bv);
@@ -39,11 +41,12 @@ __global__ __launch_bounds__(kBlock) void k_ms_init(int n3, const double2* __res
     block_partial<1>(acc, qout);
 }
 
+template <int EPT>
 __global__ __launch_bounds__(kBlock) void k_cg_restart(int n3, const float2* __restrict__ r, float2* __restrict__ p,
                                                        double* __restrict__ qout) {
     double acc[1] = {0.0};
-    for (int e = 0; e < kEPTi; ++e) {
-        const int i = (blockIdx.x * kEPTi + e) * kBlock + threadIdx.x;
+    for (int e = 0; e < EPT; ++e) {
+        const int i = (blockIdx.x * EPT + e) * kBlock + threadIdx.x;
         if (i >= n3) continue;
         const float2 rv = r[i];
         p[i] = rv;
@@ -69,7 +72,6 @@ __device__ __forceinline__ float2 nt_load(const float2* p) {
 __device__ __forceinline__ void nt_store(double2* p, double2 v) { __builtin_nontemporal_store(d2v{v.x, v.y}, (d2v*)p); }
 __device__ __forceinline__ void nt_store(float2* p, float2 v) { __builtin_nontemporal_store(f2v{v.x, v.y}, (f2v*)p); }
 
-constexpr int kEPT = 2;  // complex elements per thread in the vector kernels of the solve
 
 // Iteration j (parity par):
 //   rr_j   = sum of the <r,r> partials of the previous step (or of init)
@@ -87,7 +89,7 @@ constexpr int kEPT = 2;  // complex elements per thread in the vector kernels of
 // the window's updates to x_s and p_s in order, reading and writing each once
 // instead of L times.  The arithmetic and its order are unchanged, so the
 // results do not depend on L.
-template <class V>
+template <class V, int EPT>
 __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring, const V* __restrict__ Ap,
                                                     V* __restrict__ p, VecPtrs x, VecPtrs ps,
                                                     MsState* __restrict__ st, const double* __restrict__ dpart,
@@ -127,13 +129,13 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
         t2[j] = dpart[nb2 + b];
         t3[j] = dpart[2 * nb2 + b];
     }
-    double2 pre_r[kEPT], pre_a[kEPT], pre_p[kEPT], pre_x[kEPT];
+    double2 pre_r[EPT], pre_a[EPT], pre_p[EPT], pre_x[EPT];
     {
         const V* rc = ring + (size_t)slot * n3;
         const double2* xb = x.at<double2>(base);
 #pragma unroll
-        for (int e = 0; e < kEPT; ++e) {
-            const int i = (blockIdx.x * kEPT + e) * kBlock + threadIdx.x;
+        for (int e = 0; e < EPT; ++e) {
+            const int i = (blockIdx.x * EPT + e) * kBlock + threadIdx.x;
             if (i < n3) {
                 pre_r[e] = to_d2(rc[i]);
                 pre_a[e] = to_d2(Ap[i]);
@@ -274,8 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     const bool row0 = blockIdx.y == 0;
     double acc[1] = {0.0};
 #pragma unroll
-    for (int e = 0; e < kEPT; ++e) {
-        const int i = (blockIdx.x * kEPT + e) * kBlock + threadIdx.x;
+    for (int e = 0; e < EPT; ++e) {
+        const int i = (blockIdx.x * EPT + e) * kBlock + threadIdx.x;
         if (i >= n3) continue;
         // r and p in the Krylov precision V, solutions accumulated in FP64
         const double2 r0 = pre_r[e];
@@ -401,8 +403,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 }
 
 inline int grid3(const Geom& g) { return (3 * g.vh + kBlock - 1) / kBlock; }
-// grid of the init / step / restart kernels (kEPT elements per thread)
-inline int gridq(const Geom& g) { return (3 * g.vh + kBlock * kEPT - 1) / (kBlock * kEPT); }
+// elements per thread of the init / step / restart kernels: 1 when two per
+// thread would leave fewer than 512 blocks
+inline int ms_ept(const Geom& g) { return (3 * g.vh + 2 * kBlock - 1) / (2 * kBlock) < 512 ? 1 : 2; }
+inline int gridq(const Geom& g) {
+    const int ept = ms_ept(g);
+    return (3 * g.vh + kBlock * ept - 1) / (kBlock * ept);
+}
 
 }  // namespace
 
@@ -412,7 +419,10 @@ int dot_grid(const Geom& g) { return grid3(g); }
 template <class V>
 void launch_ms_init(const Geom& g, const double2* b, V* r, V* p, VecPtrs x, VecPtrs ps, const MsState* st,
                     double* qout, hipStream_t s) {
-    k_ms_init<V><<<gridq(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
+    if (ms_ept(g) == 1)
+        k_ms_init<V, 1><<<gridq(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
+    else
+        k_ms_init<V, 2><<<gridq(g), kBlock, 0, s>>>(3 * g.vh, b, r, p, x, ps, st, qout);
 }
 template void launch_ms_init<double2>(const Geom&, const double2*, double2*, double2*, VecPtrs, VecPtrs,
                                       const MsState*, double*, hipStream_t);
@@ -422,8 +432,12 @@ template void launch_ms_init<float2>(const Geom&, const double2*, float2*, float
 template <class V>
 void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs ps, MsState* st, const double* dpart,
                     int nb2, const double* qin, double* qout, int par, int rows, MsStepConst sc, hipStream_t s) {
-    timed_launch(k_ms_step<V>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2, qin,
-                 qout, par, sc);
+    if (ms_ept(g) == 1)
+        timed_launch(k_ms_step<V, 1>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2,
+                     qin, qout, par, sc);
+    else
+        timed_launch(k_ms_step<V, 2>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, r, Ap, p, x, ps, st, dpart, nb2,
+                     qin, qout, par, sc);
 }
 template void launch_ms_step<double2>(const Geom&, double2*, const double2*, double2*, VecPtrs, VecPtrs, MsState*,
                                       const double*, int, const double*, double*, int, int, MsStepConst,
@@ -433,7 +447,10 @@ template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2
                                      hipStream_t);
 
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
-    k_cg_restart<<<gridq(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);
+    if (ms_ept(g) == 1)
+        k_cg_restart<1><<<gridq(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);
+    else
+        k_cg_restart<2><<<gridq(g), kBlock, 0, s>>>(3 * g.vh, r, p, qout);
 }
 
 void launch_rational_sum(const Geom& g, const double2* b, VecPtrs x, const MsState* st, double2* out,
