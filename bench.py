@@ -133,9 +133,21 @@ def summarize_trace(path):
     import csv
     from collections import defaultdict
     d = defaultdict(list)
+    spans = []
     for row in csv.DictReader(open(path)):
-        d[_short(row["Kernel_Name"])].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
-    lines = [f"{'kernel':70s} {'launches':>8s} {'worked':>7s} {'avg_us(all)':>11s} {'avg_us(worked)':>14s} "
+        s0, s1 = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+        d[_short(row["Kernel_Name"])].append((s1 - s0) / 1e3)
+        spans.append((s0, s1))
+    # share of the traced span with a kernel running, and the mean idle gap
+    spans.sort()
+    busy, end = 0, spans[0][0] if spans else 0
+    for s0, s1 in spans:
+        busy += max(0, s1 - max(s0, end))
+        end = max(end, s1)
+    wall = (end - spans[0][0]) if spans else 0
+    lines = [f"traced span {wall / 1e6:.2f} ms, kernels running {100.0 * busy / max(wall, 1):.1f}% of it, "
+             f"{len(spans)} launches, mean gap {(wall - busy) / max(len(spans), 1) / 1e3:.2f} us",
+             f"{'kernel':70s} {'launches':>8s} {'worked':>7s} {'avg_us(all)':>11s} {'avg_us(worked)':>14s} "
              f"{'min_us':>8s} {'max_us':>8s}"]
     for k, v in sorted(d.items(), key=lambda kv: -sum(kv[1])):
         top = sorted(v)[len(v) // 2:]
@@ -183,6 +195,32 @@ def pmc_mode():
     print(json.dumps({"pmc_mode": True, "iters": info["iters"], "copy_bytes": 512 * 2 ** 20}), flush=True)
 
 
+def trajectory_trace_mode(n_traj=3):
+    """A few RHMC trajectories at 16^3x8 (beta 5.4, m 0.02, 12-pole tables,
+    tau 1, 20 steps) from a near-identity start, after one untimed one: a
+    short program for a kernel trace of the trajectory's launches."""
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice
+    torch.cuda.set_device(0)
+    dims = (16, 16, 16, 8)
+    lat = Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.random_su3_near_identity(dims, 0.5, synth.make_rng(5, 0))).cuda())
+    r_f = synth.load_rational("xm050_n12_m0.02")
+    r_h = synth.load_rational("xp025_n12_m0.02")
+    kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
+    lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, inject_u=0.0, traj_index=0, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, inject_u=0.0, traj_index=1 + i, **kw)
+           for i in range(n_traj)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n_traj
+    print(json.dumps({"trajectory_trace_mode": True, "sec_per_traj": round(dt, 4),
+                      "cg_iters": [r["cg_iters_total"] for r in res]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,11 +238,16 @@ def main():
                     help="iterations of the truncated solve that feeds the learned model's auxiliary channel")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--pmc-mode", action="store_true", help="one solve + a 512 MiB copy, for counter runs")
+    ap.add_argument("--trajectory-trace-mode", action="store_true",
+                    help="a few 16^3x8 RHMC trajectories, for a kernel trace")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
     args = ap.parse_args()
     if args.summarize_trace:
         text, _ = summarize_trace(args.summarize_trace)
         print(text)
+        return
+    if args.trajectory_trace_mode:
+        trajectory_trace_mode()
         return
     if args.pmc_mode:
         pmc_mode()
