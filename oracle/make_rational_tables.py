@@ -28,6 +28,11 @@ TABLES = {
     # heavier mass for small-lattice trajectory tests (m = 0.1)
     "xm050_n8_m0.1": (-0.5, 0.1 ** 2, 64.0, 8, "small trajectory tests, action/force"),
     "xp025_n8_m0.1": (0.25, 0.1 ** 2, 64.0, 8, "small trajectory tests, heat bath"),
+    # higher-accuracy action and heat-bath tables beside the 8-pole MD set
+    # (m = 0.1): the accurate tables decide the Metropolis step, the cheaper
+    # one drives the molecular dynamics
+    "xm050_n16_m0.1": (-0.5, 0.1 ** 2, 64.0, 16, "small trajectory tests, accurate action"),
+    "xp025_n16_m0.1": (0.25, 0.1 ** 2, 64.0, 16, "small trajectory tests, accurate heat bath"),
     # the paper's Appendix example: degree 24/24 for x^(1/4) on [5e-5, 34]
     "xp025_n24_paper": (0.25, 5e-5, 34.0, 24, "paper Appendix example (error < 1e-12)"),
 }

@@ -45,6 +45,37 @@ def test_trajectory_matches_oracle(dims):
     assert abs(out["plaquette"] - ref["plaquette"]) < 1e-12
 
 
+def test_accurate_action_tables_with_a_cheaper_md_set():
+    """16-pole action and heat-bath tables (relative error ~2e-12) decide the
+    Metropolis step while the 8-pole table (~2e-6) drives the molecular
+    dynamics; the trajectory matches the oracle's with the same tables."""
+    dims = (4, 4, 2, 4)
+    log("trajectory with 16-pole action / heat bath and 8-pole MD tables")
+    rng = synth.make_rng(300, 5)
+    U0 = synth.random_su3_near_identity(dims, 0.4, rng)
+    seed, traj = 2024, 7
+    prm = hmc.HMCParams(beta=5.4, mass=0.1, tau=0.5, n_steps=6,
+                        r_md=synth.load_rational("xm050_n8_m0.1"),
+                        r_action=synth.load_rational("xm050_n16_m0.1"),
+                        r_heatbath=synth.load_rational("xp025_n16_m0.1"),
+                        tol_md=1e-12, tol_action=1e-12)
+    P0 = philox.momentum(dims, seed, traj)
+    xi = philox.source(dims, seed, traj)
+    u = philox.uniform(seed, traj)
+    ref = hmc.trajectory(U0, dims, prm, P0, xi, u)
+    lat = lattice(dims, U0)
+    out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                         tol_md=1e-12, tol_action=1e-12, seed=seed, traj_index=traj)
+    K0, Sg0, Sf0 = ref["H0"]
+    K1, Sg1, Sf1 = ref["H1"]
+    for a, b in [(out["K_old"], K0), (out["Sg_old"], Sg0), (out["Sf_old"], Sf0),
+                 (out["K_new"], K1), (out["Sg_new"], Sg1), (out["Sf_new"], Sf1)]:
+        assert abs(a - b) <= 1e-10 * abs(b)
+    assert abs(out["dH"] - ref["dH"]) < 1e-8
+    assert out["accepted"] == int(ref["accepted"])
+    assert np.abs(host(lat.get_gauge()) - ref["U"]).max() < 1e-10
+
+
 def test_injected_fields_and_rejection_restores():
     dims = (4, 4, 2, 4)
     rng = synth.make_rng(301, 0)
