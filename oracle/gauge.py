@@ -42,6 +42,19 @@ def mean_plaquette(U, dims) -> float:
     return acc / (6 * L.volume(dims))
 
 
+def polyakov_loop(U, dims) -> complex:
+    """Spatial average of (1/3) tr of the ordered product of the time links
+    U_t(x,0) U_t(x,1) ... U_t(x,N_t-1) at every spatial site x: the Wilson line
+    that closes around the periodic time direction, a gauge-invariant
+    observable of the sampled configurations (expectation values of Sec. 2)."""
+    nt = dims[3]
+    ut = U[..., 3, :, :]  # (t, z, y, x, 3, 3)
+    P = ut[0]
+    for t in range(1, nt):
+        P = _mm(P, ut[t])
+    return complex(np.trace(P, axis1=-2, axis2=-1).mean() / 3)
+
+
 def gauge_action(U, dims, beta: float) -> float:
     acc = 0.0
     for mu in range(4):
