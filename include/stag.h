@@ -190,6 +190,13 @@ stag_status stag_fermion_force(stag_handle h, double mass, const stag_rational* 
 stag_status stag_gauge_force(stag_handle h, double beta, void* mom, double dt);
 /* S_g of the handle's links and the mean plaquette <Re tr P / 3> (host outs, may be NULL). */
 stag_status stag_gauge_action(stag_handle h, double beta, double* S_out, double* plaq_out);
+/* Polyakov loop of the handle's links: (1 / (3 Nx Ny Nz)) times the sum over
+ * spatial sites x of tr [U_t(x,0) U_t(x,1) ... U_t(x,Nt-1)], the ordered
+ * product of the time links closing around the periodic time direction; a
+ * gauge-invariant observable of the sampled configurations (expectation
+ * values, Sec. 2).  Host outs re and im, either may be NULL.  Errors: no
+ * gauge field set (STAG_ERR_NO_GAUGE), HIP failures. */
+stag_status stag_polyakov_loop(stag_handle h, double* re_out, double* im_out);
 /* K = (1/2) sum over links and a of mom_a^2 (host out). */
 stag_status stag_kinetic_energy(stag_handle h, const void* mom, double* K_out);
 /* U <- exp(i dt p) U for every link, then projection back to SU(3)

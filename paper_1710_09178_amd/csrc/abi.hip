@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "observables.h"
 
 using namespace stag;
 
@@ -481,6 +482,20 @@ stag_status stag_gauge_action(stag_handle c, double beta, double* S, double* pla
     if (e) return e;
     if ((e = enter(c))) return e;
     if ((e = gauge_action_impl(c, beta, S, plaq))) return e;
+    return leave(c);
+}
+
+stag_status stag_polyakov_loop(stag_handle c, double* re, double* im) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if ((e = enter(c))) return e;
+    const int nb = launch_polyakov(c->g, c->links, c->gpart, c->s);
+    launch_finalize(c->gpart, nb, 2, c->scal, c->s);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->scal_host, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    const double ns = 3.0 * c->g.nx * c->g.ny * c->g.nz;
+    if (re) *re = c->scal_host[0] / ns;
+    if (im) *im = c->scal_host[1] / ns;
     return leave(c);
 }
 

@@ -120,6 +120,7 @@ def load_library() -> ctypes.CDLL:
         "stag_fermion_force": (S, [H, D, ctypes.POINTER(CRational), D, I, P, P, D, ctypes.POINTER(CSolveInfo)]),
         "stag_gauge_force": (S, [H, D, P, D]),
         "stag_gauge_action": (S, [H, D, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "stag_polyakov_loop": (S, [H, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "stag_kinetic_energy": (S, [H, P, ctypes.POINTER(D)]),
         "stag_link_update": (S, [H, P, D]),
         "stag_random_momentum": (S, [H, ctypes.c_uint64, ctypes.c_uint64, P]),
@@ -329,6 +330,11 @@ class Lattice:
         S, plaq = ctypes.c_double(), ctypes.c_double()
         self._check(self.lib.stag_gauge_action(self.h, float(beta), ctypes.byref(S), ctypes.byref(plaq)))
         return S.value, plaq.value
+
+    def polyakov_loop(self) -> complex:
+        re, im = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.stag_polyakov_loop(self.h, ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
 
     def kinetic_energy(self, mom) -> float:
         K = ctypes.c_double()
