@@ -76,6 +76,30 @@ def test_accurate_action_tables_with_a_cheaper_md_set():
     assert np.abs(host(lat.get_gauge()) - ref["U"]).max() < 1e-10
 
 
+def test_checkpoint_resume_is_bitwise(tmp_path):
+    """A checkpoint is the canonical FP64 gauge field plus the (seed,
+    trajectory index) of the counter-based random numbers: a fresh handle
+    loaded from the file reproduces the next trajectory bit for bit."""
+    dims = (4, 4, 2, 4)
+    rng = synth.make_rng(300, 9)
+    U0 = synth.random_su3_near_identity(dims, 0.4, rng)
+    prm = _params(4, 0.5)
+    args = (prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath)
+    kw = dict(tol_md=1e-12, tol_action=1e-12, seed=77)
+    lat = lattice(dims, U0)
+    lat.trajectory(*args, traj_index=0, **kw)
+    path = tmp_path / "ckpt.npz"
+    np.savez(path, U=host(lat.get_gauge()), seed=77, next_traj=1)
+    cont = lat.trajectory(*args, traj_index=1, **kw)
+    U_cont = host(lat.get_gauge())
+    ck = np.load(path)
+    fresh = lattice(dims, ck["U"])
+    res = fresh.trajectory(*args, traj_index=int(ck["next_traj"]), tol_md=1e-12, tol_action=1e-12,
+                           seed=int(ck["seed"]))
+    assert res["dH"] == cont["dH"] and res["accepted"] == cont["accepted"]
+    assert np.array_equal(host(fresh.get_gauge()), U_cont)
+
+
 def test_injected_fields_and_rejection_restores():
     dims = (4, 4, 2, 4)
     rng = synth.make_rng(301, 0)
