@@ -519,6 +519,7 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
                 "plaquette_end": round(res[-1]["plaquette"], 5), "trajectories": len(res)}
 
     U_therm = lat.get_gauge()
+    pl = lat.polyakov_loop()
     t_first = t
 
     def timed_chain(**extra):
@@ -530,7 +531,7 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
         torch.cuda.synchronize()
         return summary(res, (time.perf_counter() - t1) / n_exact)
 
-    out = {"sec_per_trajectory": dict(timed_chain(),
+    out = {"sec_per_trajectory": dict(timed_chain(), polyakov_loop_thermalised=[round(pl.real, 6), round(pl.imag, 6)],
                                       workload="RHMC 16^3x8, beta 5.4, m 0.02, 12-pole x^(-1/2) and x^(1/4) "
                                                "tables, tau 1, 20 leapfrog steps, thermalised from a hot start")}
     # precision form in the trajectory: MD force solves with FP32 Krylov vectors
