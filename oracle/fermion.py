@@ -44,6 +44,25 @@ def rational_apply(U, dims, mass, b, rat, tol, maxiter=100000):
     return out
 
 
+def chiral_condensate(U, dims, mass, etas, tol) -> tuple[float, float]:
+    """Stochastic estimate of (1/V) Tr M^{-1}, M = 2m + D (one staggered field).
+
+    M^{-1} = (2m - D)(4m^2 - D^2)^{-1}; D changes parity while (4m^2 - D^2)^{-1}
+    keeps it, so only 2m (4m^2 - D^2)^{-1} contributes to the trace, and its
+    even and odd blocks (4m^2 - D_eo D_oe and 4m^2 - D_oe D_eo) have the same
+    spectrum: Tr M^{-1} = 4m Tr_e A^{-1}.  With noise eta on the even sites,
+    E[eta eta^dag] = 1, Tr_e A^{-1} = E[Re eta^dag A^{-1} eta].  Returns the
+    mean over the given noise vectors and its standard error."""
+    V = L.volume(dims)
+    vals = []
+    for eta in etas:
+        x = multishift_cg(lambda v: dirac.apply_A(U, v, dims, mass), eta, [0.0], tol)["x"][0]
+        vals.append(4.0 * mass * float(vdot(eta, x).real) / V)
+    vals = np.array(vals)
+    err = float(vals.std(ddof=1) / np.sqrt(len(vals))) if len(vals) > 1 else 0.0
+    return float(vals.mean()), err
+
+
 def fermion_action(U, dims, mass, phi, rat, tol) -> float:
     return float(vdot(phi, rational_apply(U, dims, mass, phi, rat, tol)).real)
 

@@ -1,10 +1,12 @@
-"""Pins for the oracle's Polyakov loop: unit links, a closed form for
-constant diagonal time links, gauge invariance (which fails for the reversed
-product) and the centre transformation (which tells tr P from its conjugate)."""
+"""Pins for the oracle's observables.  Polyakov loop: unit links, a closed
+form for constant diagonal time links, gauge invariance (which fails for the
+reversed product) and the centre transformation (which tells tr P from its
+conjugate).  Chiral condensate: the even-site reduction against the dense
+full-lattice inverse, and the noise estimator against the exact trace."""
 import numpy as np
 
 import synth
-from oracle import gauge, lattice as L
+from oracle import dirac, fermion, gauge, lattice as L, philox
 
 DIMS = (4, 2, 4, 6)
 
@@ -51,3 +53,36 @@ def test_centre_transformation_multiplies_by_z():
     Uz[0, ..., 3, :, :] *= z  # every time link leaving the t = 0 slice
     assert abs(gauge.polyakov_loop(Uz, DIMS) - z * gauge.polyakov_loop(U, DIMS)) < 1e-14
     assert abs(gauge.polyakov_loop(U, DIMS)) > 1e-3
+
+
+def _dense_A(U, dims, mass):
+    vh = L.volume(dims) // 2
+    cols = []
+    for j in range(3 * vh):
+        e = np.zeros(3 * vh, dtype=complex)
+        e[j] = 1.0
+        cols.append(dirac.apply_A(U, e.reshape(vh, 3), dims, mass).reshape(-1))
+    return np.array(cols).T
+
+
+def test_condensate_reduction_to_the_even_sites():
+    """(1/V) Tr (2m + D)^{-1} from the dense full-lattice matrix (built from
+    the defining formula entry by entry) equals (4m/V) Tr_e A^{-1}."""
+    dims, mass = (2, 2, 2, 4), 0.15
+    U = synth.random_su3_near_identity(dims, 0.8, synth.make_rng(720, 0))
+    V = L.volume(dims)
+    M = 2 * mass * np.eye(3 * V) + dirac.dense_dslash(U, dims)
+    full = np.trace(np.linalg.inv(M)).real / V
+    even = 4 * mass * np.trace(np.linalg.inv(_dense_A(U, dims, mass))).real / V
+    assert abs(full - even) < 1e-12 * abs(full)
+    assert abs(np.trace(np.linalg.inv(M)).imag) < 1e-10
+
+
+def test_condensate_estimator_converges_to_the_trace():
+    dims, mass = (2, 2, 2, 2), 0.2
+    U = synth.random_su3_near_identity(dims, 0.8, synth.make_rng(721, 0))
+    exact = 4 * mass * np.trace(np.linalg.inv(_dense_A(U, dims, mass))).real / L.volume(dims)
+    etas = [philox.source(dims, 5, k) for k in range(400)]
+    est, err = fermion.chiral_condensate(U, dims, mass, etas, 1e-13)
+    assert 0 < err < 0.05 * abs(exact)
+    assert abs(est - exact) < 4 * err
