@@ -197,6 +197,17 @@ stag_status stag_gauge_action(stag_handle h, double beta, double* S_out, double*
  * values, Sec. 2).  Host outs re and im, either may be NULL.  Errors: no
  * gauge field set (STAG_ERR_NO_GAUGE), HIP failures. */
 stag_status stag_polyakov_loop(stag_handle h, double* re_out, double* im_out);
+/* Chiral condensate of one staggered field, (1/V) Tr M^{-1} for M = 2m + D,
+ * estimated with n_noise Gaussian sources on the even sites (the sources of
+ * stag_random_source with counters (seed, k), k < n_noise): since only the
+ * parity-preserving part of M^{-1} = (2m - D)(4m^2 - D^2)^{-1} has a trace
+ * and both parity blocks have the same spectrum, Tr M^{-1} = 4m Tr_e A^{-1},
+ * estimated by (4m/V) Re <eta, A^{-1} eta> (an observable of the sampled
+ * configurations, Sec. 2).  Host outs: the mean and, if err_out is not NULL,
+ * its standard error (0 for one source).  Each source is solved to tol.
+ * Errors: no gauge field, invalid arguments, NOT_CONVERGED, NONFINITE. */
+stag_status stag_chiral_condensate(stag_handle h, double mass, double tol, int maxiter, int n_noise,
+                                   uint64_t seed, double* mean_out, double* err_out);
 /* K = (1/2) sum over links and a of mom_a^2 (host out). */
 stag_status stag_kinetic_energy(stag_handle h, const void* mom, double* K_out);
 /* U <- exp(i dt p) U for every link, then projection back to SU(3)

@@ -499,6 +499,40 @@ stag_status stag_polyakov_loop(stag_handle c, double* re, double* im) {
     return leave(c);
 }
 
+stag_status stag_chiral_condensate(stag_handle c, double mass, double tol, int maxiter, int n_noise, uint64_t seed,
+                                   double* mean_out, double* err_out) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!(mass > 0.0) || !std::isfinite(mass) || !(tol > 0.0) || maxiter < 1 || n_noise < 1 || !mean_out)
+        return fail(c, STAG_ERR_INVALID_ARG, "need mass > 0, tol > 0, maxiter >= 1, n_noise >= 1 and mean_out");
+    const double residue = 1.0, pole = 0.0;
+    const stag_rational r{1, 0.0, &residue, &pole};
+    if ((e = enter(c))) return e;
+    const double V = 2.0 * c->g.vh;
+    double sum = 0.0, sum2 = 0.0;
+    for (int k = 0; k < n_noise; ++k) {
+        // noise k: the Gaussian source of the counter (seed, k), E[eta eta^dag] = 1
+        launch_random_source(c->g, seed, (uint64_t)k, c->xi, c->s);
+        SolveResult res;
+        double S = 0.0;  // Re <eta, A^-1 eta>
+        if ((e = fermion_action_impl(c, mass, &r, tol, maxiter, c->xi, &S, res))) return e;
+        if (res.nonfinite || !res.converged) {
+            if ((e = leave(c))) return e;
+            return finish_solve_status(c, res);
+        }
+        const double v = 4.0 * mass * S / V;
+        sum += v;
+        sum2 += v * v;
+    }
+    if ((e = leave(c))) return e;
+    const double mean = sum / n_noise;
+    *mean_out = mean;
+    if (err_out)
+        *err_out = n_noise > 1 ? std::sqrt(std::max(0.0, (sum2 - n_noise * mean * mean) / (n_noise - 1)) / n_noise)
+                               : 0.0;
+    return STAG_OK;
+}
+
 stag_status stag_kinetic_energy(stag_handle c, const void* mom, double* K) {
     stag_status e = check_common(c, false);
     if (e) return e;

@@ -121,6 +121,7 @@ def load_library() -> ctypes.CDLL:
         "stag_gauge_force": (S, [H, D, P, D]),
         "stag_gauge_action": (S, [H, D, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "stag_polyakov_loop": (S, [H, ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "stag_chiral_condensate": (S, [H, D, D, I, I, ctypes.c_uint64, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "stag_kinetic_energy": (S, [H, P, ctypes.POINTER(D)]),
         "stag_link_update": (S, [H, P, D]),
         "stag_random_momentum": (S, [H, ctypes.c_uint64, ctypes.c_uint64, P]),
@@ -335,6 +336,12 @@ class Lattice:
         re, im = ctypes.c_double(), ctypes.c_double()
         self._check(self.lib.stag_polyakov_loop(self.h, ctypes.byref(re), ctypes.byref(im)))
         return complex(re.value, im.value)
+
+    def chiral_condensate(self, mass, tol, maxiter, n_noise, seed):
+        mean, err = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.stag_chiral_condensate(self.h, float(mass), float(tol), int(maxiter), int(n_noise),
+                                                    int(seed), ctypes.byref(mean), ctypes.byref(err)))
+        return mean.value, err.value
 
     def kinetic_energy(self, mom) -> float:
         K = ctypes.c_double()

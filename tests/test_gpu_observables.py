@@ -1,11 +1,12 @@
-"""GPU Polyakov loop against the oracle on random fields (several tiles of
-spatial sites, odd extents along x in blocks, 16^3x8) and the centre
-transformation on the GPU."""
+"""GPU observables against the oracle: the Polyakov loop on random fields
+(several blocks of spatial sites, 16^3x8) and under the centre
+transformation; the stochastic chiral condensate with the same sources."""
 import numpy as np
 import pytest
 
 import synth
-from oracle import gauge
+from oracle import fermion, gauge, philox
+from paper_1710_09178_amd import stag
 from tests.gpu_util import lattice, log
 
 pytestmark = pytest.mark.gpu
@@ -26,3 +27,19 @@ def test_polyakov_loop_matches_oracle(dims, eps):
     Uz[0, ..., 3, :, :] *= z
     lz = lattice(dims, Uz)
     assert abs(lz.polyakov_loop() - z * got) < 1e-13
+
+
+def test_chiral_condensate_matches_oracle():
+    """Same sources (counters (seed, k)), same estimator: the GPU mean and
+    standard error agree with the oracle's to the solver tolerance."""
+    dims, mass, seed, n = (4, 4, 2, 4), 0.1, 5, 8
+    log("chiral condensate")
+    U = synth.random_su3_near_identity(dims, 0.6, synth.make_rng(711, 0))
+    lat = lattice(dims, U)
+    mean, err = lat.chiral_condensate(mass, 1e-12, 100000, n, seed)
+    etas = [philox.source(dims, seed, k) for k in range(n)]
+    ref, ref_err = fermion.chiral_condensate(U, dims, mass, etas, 1e-12)
+    assert abs(mean - ref) < 1e-9 * abs(ref), (mean, ref)
+    assert abs(err - ref_err) < 1e-6 * ref_err, (err, ref_err)
+    with pytest.raises(stag.StagError):
+        lat.chiral_condensate(mass, 1e-12, 100000, 0, seed)
