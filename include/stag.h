@@ -61,6 +61,7 @@ typedef enum {
     STAG_ERR_NO_GAUGE = -2,      /* a compute call before stag_set_gauge */
     STAG_ERR_NOT_CONVERGED = -3, /* solver hit maxiter; info is filled */
     STAG_ERR_NONFINITE = -4,     /* NaN/Inf met in a reduction */
+    STAG_ERR_SPECTRUM = -5,      /* a rational table's interval does not cover the spectrum of A */
     STAG_ERR_HIP = -6,           /* a HIP runtime call failed */
     STAG_ERR_OOM = -7            /* device allocation failed */
 } stag_status;
@@ -140,6 +141,24 @@ stag_status stag_multishift_solve(stag_handle h, double mass, const stag_rationa
                                   int maxiter, const void* b_even, void* const* x_even,
                                   void* sum_even, stag_solve_info* info);
 
+/* ---- spectral range (Appendix) ------------------------------------------ */
+
+/* Power iteration of A = 4m^2 - D_eo D_oe on the handle's links: starting
+ * from the estimator-noise vector (seed, 0) of stag_chiral_condensate, A is
+ * applied iters times (normalising on the way) and lam_out receives the
+ * Rayleigh quotient <v, A v> / <v, v>: a lower estimate of the largest
+ * eigenvalue that rises to it with iters.  Host out. */
+stag_status stag_power_estimate(stag_handle h, double mass, int iters, uint64_t seed, double* lam_out);
+/* Does the interval [xmin, xmax] of a rational table cover the spectrum of A?
+ * The Appendix needs the approximation interval to reach below the smallest
+ * eigenvalue (2m)^2 and above the largest.  A = 4m^2 + D_oe^dag D_oe, so 4m^2
+ * is a lower bound and 4m^2 + 64 an upper one (|D_oe| <= 8).  Returns
+ * STAG_ERR_SPECTRUM (message in stag_last_error) when xmin > 4m^2, or when
+ * xmax < 4m^2 + 64 and 1.1 times the power estimate after 100 iterations
+ * exceeds xmax; STAG_OK otherwise.  lam_out (may be NULL): the estimate, or 0
+ * when the certain bound made it unnecessary. */
+stag_status stag_check_spectrum(stag_handle h, double mass, double xmin, double xmax, double* lam_out);
+
 /* ---- precision form ------------------------------------------------------ */
 
 /* Storage of the links read by the Dirac operator.  The 12-real formats keep
@@ -155,6 +174,18 @@ typedef enum {
  * forces): STAG_LINKS_F64_18 or STAG_LINKS_F64_12.  The compressed copy is
  * derived from the handle's links whenever they change. */
 stag_status stag_set_link_format(stag_handle h, int format);
+
+/* The sloppy operator of the precision form, applied to FP64 internal vectors
+ * so that its error against the FP64 operator can be measured: in is rounded
+ * to FP32, D (stag_dslash_sloppy: out_parity 1 = D_oe, 0 = D_eo) or
+ * A = 4m^2 - D_eo D_oe (stag_mdagm_sloppy) is applied in FP32 arithmetic with
+ * the links stored in `format` (STAG_LINKS_F32_18 or STAG_LINKS_F16_12, row 2
+ * rebuilt as conj(row0 x row1) in FP32), exactly as inside the FP32 Krylov
+ * solves, and the result is widened to FP64 in out (Sec. 3.2 operator; the
+ * paper's remarks on FP32 and link compression).  in and out must not
+ * overlap.  The first call allocates the link copy and the FP32 vectors. */
+stag_status stag_dslash_sloppy(stag_handle h, void* out, const void* in, int out_parity, int format);
+stag_status stag_mdagm_sloppy(stag_handle h, void* out_even, const void* in_even, double mass, int format);
 
 typedef struct {
     int sloppy;              /* STAG_LINKS_F32_18 or STAG_LINKS_F16_12 (FP32 vectors in both) */
@@ -198,8 +229,10 @@ stag_status stag_gauge_action(stag_handle h, double beta, double* S_out, double*
  * gauge field set (STAG_ERR_NO_GAUGE), HIP failures. */
 stag_status stag_polyakov_loop(stag_handle h, double* re_out, double* im_out);
 /* Chiral condensate of one staggered field, (1/V) Tr M^{-1} for M = 2m + D,
- * estimated with n_noise Gaussian sources on the even sites (the sources of
- * stag_random_source with counters (seed, k), k < n_noise): since only the
+ * estimated with n_noise Gaussian noise vectors on the even sites (the
+ * distribution of stag_random_source, drawn from a separate estimator-noise
+ * field of the counter (seed, k), k < n_noise, so never equal to a heat-bath
+ * source of a chain with the same seed): since only the
  * parity-preserving part of M^{-1} = (2m - D)(4m^2 - D^2)^{-1} has a trace
  * and both parity blocks have the same spectrum, Tr M^{-1} = 4m Tr_e A^{-1},
  * estimated by (4m/V) Re <eta, A^{-1} eta> (an observable of the sampled
@@ -303,6 +336,11 @@ typedef struct {
                                      residual, no refinement.  The force stays a deterministic
                                      function of the links, so the algorithm stays exact; heat bath
                                      and actions are always FP64. */
+    double spectrum_lo, spectrum_hi; /* both 0: no check.  Otherwise the interval the rational tables
+                                     were made for: the trajectory first checks it against the
+                                     spectrum of A on its starting links (stag_check_spectrum) and
+                                     returns STAG_ERR_SPECTRUM, with nothing changed, if it does not
+                                     cover it */
 } stag_hmc_params;
 
 typedef struct {
@@ -317,7 +355,11 @@ typedef struct {
 } stag_traj_info;
 
 /* Heat bath, leapfrog integration and Metropolis test on the handle's gauge
- * field; on rejection the field is restored.  info may be NULL. */
+ * field; on rejection the field is restored.  info may be NULL.  Errors:
+ * invalid parameters (nothing done), NOT_CONVERGED / NONFINITE from a solve,
+ * model failures: on every error after the heat bath the gauge field is
+ * restored to its state at the call and the model's auxiliary field is
+ * detached, so the handle still holds the chain's configuration. */
 stag_status stag_md_trajectory(stag_handle h, const stag_hmc_params* p, stag_traj_info* info);
 
 /* ---- batched form: many lattices x right-hand sides x poles ---------------- */

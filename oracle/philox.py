@@ -11,6 +11,8 @@ M0 = 0xD2511F53, M1 = 0xCD9E8D57; the key is advanced by the Weyl constants
 Counter layout of this project (both sides use it):
     c0 = low 32 bits of the draw index,  c1 = field | (high bits of index) << 8,
     c2, c3 = low / high 32 bits of the trajectory number,  key = seed (lo, hi).
+Fields: 0 momenta, 1 heat-bath source, 2 Metropolis uniform, 3 estimator
+noise (c2, c3 then hold the noise vector's number).
 Each draw gives two 53-bit uniforms u = ((w0 << 32 | w1) >> 11 + 1/2) 2^-53
 in (0,1) and, by Box-Muller, two Gaussians
     g0 = sqrt(-2 ln u1) cos(2 pi u2),   g1 = sqrt(-2 ln u1) sin(2 pi u2).
@@ -26,6 +28,7 @@ MASK = 0xFFFFFFFF
 FIELD_MOMENTUM = 0
 FIELD_SOURCE = 1
 FIELD_UNIFORM = 2
+FIELD_NOISE = 3
 
 
 def philox4x32_10(ctr: np.ndarray, key) -> np.ndarray:
@@ -87,6 +90,15 @@ def source(dims, seed: int, traj: int) -> np.ndarray:
     uses draw 3k+q, real and imaginary parts N(0, 1/2)."""
     vh = nx_ny_nz_nt(dims) // 2
     g = gaussians(np.arange(3 * vh, dtype=np.uint64), FIELD_SOURCE, seed, traj)
+    return (g[:, 0] + 1j * g[:, 1]).reshape(vh, 3) * np.sqrt(0.5)
+
+
+def noise(dims, seed: int, k: int) -> np.ndarray:
+    """Noise vector number k of the stochastic estimators: the same
+    distribution as `source`, from its own field of the counter, so that it is
+    independent of every heat-bath source of a chain with the same seed."""
+    vh = nx_ny_nz_nt(dims) // 2
+    g = gaussians(np.arange(3 * vh, dtype=np.uint64), FIELD_NOISE, seed, k)
     return (g[:, 0] + 1j * g[:, 1]).reshape(vh, 3) * np.sqrt(0.5)
 
 

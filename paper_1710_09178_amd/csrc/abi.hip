@@ -132,6 +132,70 @@ stag_status fermion_force_impl(stag_ctx* c, double mass, const stag_rational* r,
     return STAG_OK;
 }
 
+// Rayleigh quotient <v, A v> / <v, v> after `iters` power iterations from the
+// estimator-noise vector (seed, 0); v is normalised every 8 applications (the
+// quotient does not depend on the scale).  Uses p, Ap and tmp_o.
+stag_status power_rayleigh_impl(stag_ctx* c, double mass, int iters, uint64_t seed, double* lam) {
+    const Geom& g = c->g;
+    LinkSet ls;
+    stag_status e = get_links(c, -1, ls);
+    if (e) return e;
+    const double m2 = 4.0 * mass * mass;
+    double2 *v = c->p, *t = c->Ap;
+    launch_random_source(g, seed, 0, v, c->s, kFieldNoise);
+    for (int k = 0; k < iters; ++k) {
+        launch_dslash(g, ls, v, c->tmp_o, 1, c->tps, nullptr, c->s);
+        launch_dslash_axpy(g, ls, c->tmp_o, v, m2, t, c->tps, c->s);
+        if (k % 8 == 7 || k == iters - 1) {
+            launch_dot_re(g, t, t, c->gpart, c->s);
+            launch_finalize(c->gpart, dot_grid(g), 1, c->scal, c->s);
+            launch_scale_rsqrt(g, t, c->scal, c->s);
+        }
+        std::swap(v, t);
+    }
+    launch_dslash(g, ls, v, c->tmp_o, 1, c->tps, nullptr, c->s);
+    launch_dslash_axpy(g, ls, c->tmp_o, v, m2, t, c->tps, c->s);
+    launch_dot_re(g, v, t, c->gpart, c->s);
+    launch_finalize(c->gpart, dot_grid(g), 1, c->scal, c->s);
+    launch_dot_re(g, v, v, c->gpart, c->s);
+    launch_finalize(c->gpart, dot_grid(g), 1, c->scal + 1, c->s);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->scal_host, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+    *lam = c->scal_host[0] / c->scal_host[1];
+    if (!std::isfinite(*lam)) return fail(c, STAG_ERR_NONFINITE, "non-finite value in the power iteration");
+    return STAG_OK;
+}
+
+// Interval [xmin, xmax] of a rational table against the spectrum of A: the
+// table must reach below 4m^2 (the exact lower bound) and above lambda_max,
+// either for certain (xmax >= 4m^2 + 64, since |D_oe| <= 8) or with a margin
+// of 10% over the power estimate after 100 iterations (which lies below
+// lambda_max).
+constexpr int kSpectrumIters = 100;
+constexpr double kSpectrumMargin = 0.1;
+stag_status spectrum_check_impl(stag_ctx* c, double mass, double xmin, double xmax, double* lam_out) {
+    const double lo = 4.0 * mass * mass;
+    if (lam_out) *lam_out = 0.0;
+    if (xmin > lo) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "rational interval starts at %.6g, above the lower spectral bound 4m^2 = %.6g", xmin,
+                 lo);
+        return fail(c, STAG_ERR_SPECTRUM, buf);
+    }
+    if (xmax >= lo + 64.0) return STAG_OK;
+    double lam = 0.0;
+    stag_status e = power_rayleigh_impl(c, mass, kSpectrumIters, 0, &lam);
+    if (e) return e;
+    if (lam_out) *lam_out = lam;
+    if ((1.0 + kSpectrumMargin) * lam > xmax) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "rational interval ends at %.6g, below 1.1 x the estimated largest eigenvalue %.6g of A", xmax, lam);
+        return fail(c, STAG_ERR_SPECTRUM, buf);
+    }
+    return STAG_OK;
+}
+
 stag_status gauge_action_impl(stag_ctx* c, double beta, double* S, double* plaq) {
     const int nb = launch_plaquette(c->g, c->links, c->gpart, c->s);
     launch_finalize(c->gpart, nb, 1, c->scal, c->s);
@@ -353,6 +417,64 @@ stag_status stag_mdagm(stag_handle c, void* out, const void* in, double mass) {
     return leave(c);
 }
 
+stag_status stag_power_estimate(stag_handle c, double mass, int iters, uint64_t seed, double* lam_out) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!std::isfinite(mass) || iters < 0 || !lam_out)
+        return fail(c, STAG_ERR_INVALID_ARG, "need a finite mass, iters >= 0 and lam_out");
+    if ((e = enter(c))) return e;
+    if ((e = power_rayleigh_impl(c, mass, iters, seed, lam_out))) return e;
+    return leave(c);
+}
+
+stag_status stag_check_spectrum(stag_handle c, double mass, double xmin, double xmax, double* lam_out) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!std::isfinite(mass) || !std::isfinite(xmin) || !std::isfinite(xmax) || !(xmin < xmax))
+        return fail(c, STAG_ERR_INVALID_ARG, "need a finite mass and xmin < xmax");
+    if ((e = enter(c))) return e;
+    const stag_status chk = spectrum_check_impl(c, mass, xmin, xmax, lam_out);
+    if ((e = leave(c))) return e;
+    return chk;
+}
+
+// The precision form's sloppy operator applied to FP64 vectors (input
+// rounded to FP32, output widened): what the FP32 Krylov solves apply.
+stag_status stag_dslash_sloppy(stag_handle c, void* out, const void* in, int out_parity, int format) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in) || out == in)
+        return fail(c, STAG_ERR_INVALID_ARG, "vector pointers NULL, misaligned or equal");
+    if (out_parity != 0 && out_parity != 1) return fail(c, STAG_ERR_INVALID_ARG, "parity must be 0 or 1");
+    if (format != STAG_LINKS_F32_18 && format != STAG_LINKS_F16_12)
+        return fail(c, STAG_ERR_INVALID_ARG, "sloppy format must be STAG_LINKS_F32_18 or STAG_LINKS_F16_12");
+    if ((e = enter(c))) return e;
+    LinkSet ls;
+    if ((e = get_links(c, format, ls)) || (e = ensure_fp32_workspace(c))) return e;
+    launch_vec_narrow(c->g, (const double2*)in, c->p32, c->s);
+    launch_dslash32(c->g, ls, c->p32, c->w32, out_parity, c->tps, nullptr, c->s);
+    launch_vec_widen(c->g, c->w32, (double2*)out, c->s);
+    return leave(c);
+}
+
+stag_status stag_mdagm_sloppy(stag_handle c, void* out, const void* in, double mass, int format) {
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!aligned16(out) || !aligned16(in) || out == in)
+        return fail(c, STAG_ERR_INVALID_ARG, "vector pointers NULL, misaligned or equal");
+    if (!std::isfinite(mass)) return fail(c, STAG_ERR_INVALID_ARG, "mass must be finite");
+    if (format != STAG_LINKS_F32_18 && format != STAG_LINKS_F16_12)
+        return fail(c, STAG_ERR_INVALID_ARG, "sloppy format must be STAG_LINKS_F32_18 or STAG_LINKS_F16_12");
+    if ((e = enter(c))) return e;
+    LinkSet ls;
+    if ((e = get_links(c, format, ls)) || (e = ensure_fp32_workspace(c))) return e;
+    launch_vec_narrow(c->g, (const double2*)in, c->p32, c->s);
+    launch_dslash32(c->g, ls, c->p32, c->w32, 1, c->tps, nullptr, c->s);
+    launch_dslash32_axpy(c->g, ls, c->w32, c->p32, 4.0 * mass * mass, c->Ap32, c->tps, c->s);
+    launch_vec_widen(c->g, c->Ap32, (double2*)out, c->s);
+    return leave(c);
+}
+
 namespace {
 stag_status solve_entry(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter, const void* b,
                         void* const* x, void* sum, const stag_mixed_opts* mixed, stag_solve_info* info) {
@@ -511,8 +633,9 @@ stag_status stag_chiral_condensate(stag_handle c, double mass, double tol, int m
     const double V = 2.0 * c->g.vh;
     double sum = 0.0, sum2 = 0.0;
     for (int k = 0; k < n_noise; ++k) {
-        // noise k: the Gaussian source of the counter (seed, k), E[eta eta^dag] = 1
-        launch_random_source(c->g, seed, (uint64_t)k, c->xi, c->s);
+        // noise k: Gaussian, E[eta eta^dag] = 1, from the estimator-noise
+        // stream (seed, k), independent of the heat-bath sources
+        launch_random_source(c->g, seed, (uint64_t)k, c->xi, c->s, kFieldNoise);
         SolveResult res;
         double S = 0.0;  // Re <eta, A^-1 eta>
         if ((e = fermion_action_impl(c, mass, &r, tol, maxiter, c->xi, &S, res))) return e;
@@ -614,10 +737,21 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         stag_status e2 = dmalloc(c, &c->mom_aux, (size_t)64 * c->g.vh * sizeof(double));
         if (e2) return e2;
     }
+    if (ferm && (p->spectrum_lo != 0.0 || p->spectrum_hi != 0.0) &&
+        !(std::isfinite(p->spectrum_lo) && std::isfinite(p->spectrum_hi) && p->spectrum_lo < p->spectrum_hi))
+        return fail(c, STAG_ERR_INVALID_ARG, "spectrum interval must be finite with lo < hi (or both 0)");
     if ((e = enter(c))) return e;
     const Geom& g = c->g;
     const size_t mb = (size_t)64 * g.vh * sizeof(double);
     const size_t lb = (size_t)72 * g.vh * sizeof(double2);
+    // the tables' interval against the spectrum of A on the starting links
+    if (ferm && p->spectrum_hi != 0.0) {
+        stag_status chk = spectrum_check_impl(c, p->mass, p->spectrum_lo, p->spectrum_hi, nullptr);
+        if (chk) {
+            leave(c);
+            return chk;
+        }
+    }
     stag_traj_info I{};
     SolveResult res;
     int iters = 0, nsolve = 0;
@@ -648,6 +782,17 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         launch_rational_sum(g, c->xi, X, c->st, c->phi, c->s);
     }
     launch_copy(c->links_backup, c->links, lb, c->s);
+    // From here on the links change: every error return restores the links of
+    // the trajectory's start (and detaches the model's auxiliary field), so a
+    // caller that catches the error still holds a configuration of the chain.
+    auto restore_after_error = [&](stag_status err) -> stag_status {
+        launch_copy(c->links, c->links_backup, lb, c->s);
+        links_changed(c);
+        if (p->surrogate && p->inner_iters > 0) stag_surrogate_set_aux(p->surrogate, nullptr);
+        leave(c);
+        return err;
+    };
+    e = [&]() -> stag_status {
     // H at the start
     if ((e = kinetic_impl(c, c->mom, &I.K_old))) return e;
     if ((e = gauge_action_impl(c, p->beta, &I.Sg_old, nullptr))) return e;
@@ -735,6 +880,9 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         if ((e = reduce_to_host(c, &u))) return e;
     }
     I.accepted = (u < std::exp(-I.dH)) ? 1 : 0;
+    return STAG_OK;
+    }();
+    if (e) return restore_after_error(e);
     if (!I.accepted) {
         launch_copy(c->links, c->links_backup, lb, c->s);
         links_changed(c);

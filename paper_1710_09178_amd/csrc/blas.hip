@@ -385,6 +385,15 @@ __global__ __launch_bounds__(kBlock) void k_dot_re(int n3, const double2* __rest
     block_partial<1>(acc, part);
 }
 
+// v *= 1 / sqrt(s2[0]) (normalisation inside the power iteration)
+__global__ __launch_bounds__(kBlock) void k_scale_rsqrt(int n3, double2* __restrict__ v, const double* __restrict__ s2) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n3) return;
+    const double f = 1.0 / sqrt(s2[0]);
+    const double2 a = v[i];
+    v[i] = make_double2(f * a.x, f * a.y);
+}
+
 __global__ __launch_bounds__(kBlock) void k_finalize_pad(const double* __restrict__ part, int nb,
                                                          double* __restrict__ out, int npad) {
     __shared__ double lds[4];
@@ -460,6 +469,10 @@ void launch_rational_sum(const Geom& g, const double2* b, VecPtrs x, const MsSta
 
 void launch_dot_re(const Geom& g, const double2* a, const double2* b, double* part, hipStream_t s) {
     k_dot_re<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, a, b, part);
+}
+
+void launch_scale_rsqrt(const Geom& g, double2* v, const double* s2, hipStream_t s) {
+    k_scale_rsqrt<<<grid3(g), kBlock, 0, s>>>(3 * g.vh, v, s2);
 }
 
 void launch_finalize_pad(const double* part, int nb, double* out, int npad, hipStream_t s) {

@@ -305,6 +305,8 @@ void launch_vec_to_internal(const Geom& g, const double2* canon, double2* vec, h
 void launch_vec_to_canon(const Geom& g, const double2* vec, double2* canon, hipStream_t s);
 void launch_mom_to_internal(const Geom& g, const double* canon, double* mom, int par_offset, hipStream_t s);
 void launch_mom_to_canon(const Geom& g, const double* mom, double* canon, hipStream_t s);
+void launch_vec_narrow(const Geom& g, const double2* in, float2* out, hipStream_t s);
+void launch_vec_widen(const Geom& g, const float2* in, double2* out, hipStream_t s);
 void launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 // y += a x over n doubles
@@ -342,6 +344,8 @@ int dot_grid(const Geom& g);
 void launch_finalize(const double* part, int nb, int K, double* out, hipStream_t s);
 // out[0] = sum of nb partials, out[1..npad) = 0 (a partial array of another grid)
 void launch_finalize_pad(const double* part, int nb, double* out, int npad, hipStream_t s);
+// v *= 1 / sqrt(s2[0]), s2 a device scalar
+void launch_scale_rsqrt(const Geom& g, double2* v, const double* s2, hipStream_t s);
 
 // Forces and MD
 void launch_fermion_force(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef,
@@ -355,7 +359,9 @@ int launch_kinetic(const Geom& g, const double* mom, double* part, hipStream_t s
 
 // Random fields
 void launch_random_momentum(const Geom& g, uint64_t seed, uint64_t traj, double* mom, hipStream_t s);
-void launch_random_source(const Geom& g, uint64_t seed, uint64_t traj, double2* xi, hipStream_t s);
+constexpr uint32_t kFieldSource = 1, kFieldNoise = 3;
+void launch_random_source(const Geom& g, uint64_t seed, uint64_t traj, double2* xi, hipStream_t s,
+                          uint32_t field = kFieldSource);
 void launch_philox(const uint32_t ctr[4], const uint32_t key[2], size_t n, uint32_t* out, hipStream_t s);
 void launch_uniform(uint64_t seed, uint64_t traj, double* out, hipStream_t s);
 

@@ -125,6 +125,17 @@ __global__ void k_axpy_real(size_t n, double a, const double* __restrict__ x, do
         y[i] += a * x[i];
 }
 
+// FP64 <-> FP32 copies of internal half vectors (the sloppy operator's input
+// rounding and output widening)
+__global__ void k_vec_narrow(size_t n, const double2* __restrict__ in, float2* __restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+__global__ void k_vec_widen(size_t n, const float2* __restrict__ in, double2* __restrict__ out) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+
 inline int blocks_for(size_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -177,6 +188,19 @@ void launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
     int nb = blocks_for(n16);
     if (nb > 8192) nb = 8192;
     k_copy<<<nb, 256, 0, s>>>((uint4*)dst, (const uint4*)src, n16);
+}
+
+void launch_vec_narrow(const Geom& g, const double2* in, float2* out, hipStream_t s) {
+    const size_t n = (size_t)3 * g.vh;
+    int nb = blocks_for(n);
+    if (nb > 8192) nb = 8192;
+    k_vec_narrow<<<nb, 256, 0, s>>>(n, in, out);
+}
+void launch_vec_widen(const Geom& g, const float2* in, double2* out, hipStream_t s) {
+    const size_t n = (size_t)3 * g.vh;
+    int nb = blocks_for(n);
+    if (nb > 8192) nb = 8192;
+    k_vec_widen<<<nb, 256, 0, s>>>(n, in, out);
 }
 
 void launch_axpy_real(size_t n, double a, const double* x, double* y, hipStream_t s) {

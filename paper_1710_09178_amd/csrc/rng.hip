@@ -1,7 +1,8 @@
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) and Box-Muller
 // Gaussians for the random fields of a trajectory (Sec. 3.1 step 1).
 // Counter words: (draw index low, field | draw index high << 8, traj low,
-// traj high); key = (seed low, seed high).
+// traj high); key = (seed low, seed high).  Fields: 0 momenta, 1 heat-bath
+// source, 2 Metropolis uniform, 3 estimator noise.
 #include "common.h"
 
 namespace stag {
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_random_momentum(Geom g, uint64_t see
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_random_source(Geom g, uint64_t seed, uint64_t traj,
+__global__ __launch_bounds__(kBlock) void k_random_source(Geom g, uint64_t seed, uint64_t traj, uint32_t field,
                                                           double2* __restrict__ xi) {
     const int cb = blockIdx.x * kBlock + threadIdx.x;
     if (cb >= g.vh) return;
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_random_source(Geom g, uint64_t seed,
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         double g0, g1;
-        gauss_pair(3 * (uint64_t)cb + q, 1u, seed, traj, g0, g1);
+        gauss_pair(3 * (uint64_t)cb + q, field, seed, traj, g0, g1);
         xi[(size_t)q * g.vh + cb] = make_double2(s * g0, s * g1);
     }
 }
@@ -119,9 +120,12 @@ void launch_random_momentum(const Geom& g, uint64_t seed, uint64_t traj, double*
     k_random_momentum<<<grid, kBlock, 0, s>>>(g, seed, traj, mom);
 }
 
-void launch_random_source(const Geom& g, uint64_t seed, uint64_t traj, double2* xi, hipStream_t s) {
+// field 1: the heat-bath source of trajectory traj; field 3: noise vector
+// number traj of the stochastic estimators (an independent stream, so that a
+// measurement with the chain's seed never reuses a heat-bath source)
+void launch_random_source(const Geom& g, uint64_t seed, uint64_t traj, double2* xi, hipStream_t s, uint32_t field) {
     const int grid = (g.vh + kBlock - 1) / kBlock;
-    k_random_source<<<grid, kBlock, 0, s>>>(g, seed, traj, xi);
+    k_random_source<<<grid, kBlock, 0, s>>>(g, seed, traj, field, xi);
 }
 
 void launch_philox(const uint32_t ctr[4], const uint32_t key[2], size_t n, uint32_t* out, hipStream_t s) {

@@ -419,7 +419,6 @@ stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double to
     return STAG_OK;
 }
 
-namespace {
 stag_status ensure_fp32_workspace(stag_ctx* c) {
     const Geom& g = c->g;
     stag_status e;
@@ -430,7 +429,6 @@ stag_status ensure_fp32_workspace(stag_ctx* c) {
     }
     return STAG_OK;
 }
-}  // namespace
 
 stag_status ms_solve_sloppy(stag_ctx* c, int sloppy, double mass, const stag_rational* r, double tol, int maxiter,
                             const double2* b, double2* const* x, SolveResult& res) {

@@ -22,6 +22,7 @@ STAG_ERR_INVALID_ARG = -1
 STAG_ERR_NO_GAUGE = -2
 STAG_ERR_NOT_CONVERGED = -3
 STAG_ERR_NONFINITE = -4
+STAG_ERR_SPECTRUM = -5
 STAG_ERR_HIP = -6
 STAG_ERR_OOM = -7
 
@@ -60,7 +61,8 @@ class CHMCParams(ctypes.Structure):
                 ("inject_u", ctypes.c_double), ("no_fermions", ctypes.c_int),
                 ("surrogate", ctypes.c_void_p), ("exact_every", ctypes.c_int),
                 ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int), ("inner_iters", ctypes.c_int),
-                ("md_link_format", ctypes.c_int)]
+                ("md_link_format", ctypes.c_int), ("spectrum_lo", ctypes.c_double),
+                ("spectrum_hi", ctypes.c_double)]
 
 
 class CTrajInfo(ctypes.Structure):
@@ -110,6 +112,10 @@ def load_library() -> ctypes.CDLL:
         "stag_mom_export": (S, [H, P, P]),
         "stag_dslash": (S, [H, P, P, I]),
         "stag_mdagm": (S, [H, P, P, D]),
+        "stag_dslash_sloppy": (S, [H, P, P, I, I]),
+        "stag_power_estimate": (S, [H, D, I, ctypes.c_uint64, ctypes.POINTER(D)]),
+        "stag_check_spectrum": (S, [H, D, D, D, ctypes.POINTER(D)]),
+        "stag_mdagm_sloppy": (S, [H, P, P, D, I]),
         "stag_multishift_solve": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(P), P,
                                       ctypes.POINTER(CSolveInfo)]),
         "stag_multishift_solve_mixed": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(P), P,
@@ -165,6 +171,9 @@ def load_library() -> ctypes.CDLL:
     return lib
 
 
+_DOUBLE_TYPES = (torch.float64, torch.complex128)
+
+
 def _ptr(t) -> int | None:
     if t is None:
         return None
@@ -175,6 +184,26 @@ def _ptr(t) -> int | None:
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
     return t.data_ptr()
+
+
+def _buf(t, nbytes: int, what: str, optional: bool = False) -> int | None:
+    """Device pointer of a double-precision buffer of exactly nbytes bytes.
+
+    The C ABI takes raw pointers, so a wrongly sized or typed tensor would make
+    a kernel read or write outside it: every wrapper checks here first.
+    """
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{what}: a tensor is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if t.dtype not in _DOUBLE_TYPES:
+        raise TypeError(f"{what}: expected float64 or complex128, got {t.dtype}")
+    got = t.numel() * t.element_size()
+    if got != nbytes:
+        raise ValueError(f"{what}: expected {nbytes} bytes, got {got}")
+    return _ptr(t)
 
 
 class RationalArg:
@@ -208,6 +237,8 @@ class Lattice:
         nx, ny, nz, nt = self.dims
         self.V = nx * ny * nz * nt
         self.Vh = self.V // 2
+        # byte sizes of every field kind, checked before each call
+        self._nb = {k: int(self.lib.stag_field_bytes(h, k)) for k in range(5)}
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -219,6 +250,20 @@ class Lattice:
         if code not in allow:
             raise StagError(code, self.lib.stag_last_error(self.h).decode())
         return code
+
+    def _vec(self, t, what, optional=False):
+        return _buf(t, self._nb[FIELD_HALF_VEC], what, optional)
+
+    def _mom(self, t, what, optional=False):
+        return _buf(t, self._nb[FIELD_MOM], what, optional)
+
+    def _xs(self, xs, n):
+        if xs is None:
+            return None
+        xs = list(xs)
+        if len(xs) != n:
+            raise ValueError(f"xs: expected {n} solution vectors (one per pole), got {len(xs)}")
+        return (ctypes.c_void_p * n)(*[self._vec(x, f"xs[{k}]") for k, x in enumerate(xs)])
 
     # ---- allocation helpers (torch device memory)
     def field_bytes(self, kind: int) -> int:
@@ -232,7 +277,7 @@ class Lattice:
 
     # ---- fields
     def set_gauge(self, U: torch.Tensor):
-        self._check(self.lib.stag_set_gauge(self.h, _ptr(U)))
+        self._check(self.lib.stag_set_gauge(self.h, _buf(U, self._nb[FIELD_CANON_GAUGE], "U")))
 
     def get_gauge(self) -> torch.Tensor:
         nx, ny, nz, nt = self.dims
@@ -242,31 +287,54 @@ class Lattice:
 
     def vec_import(self, canon: torch.Tensor, parity: int = 0) -> torch.Tensor:
         out = self.new_vec()
-        self._check(self.lib.stag_vec_import(self.h, _ptr(out), _ptr(canon), parity))
+        self._check(self.lib.stag_vec_import(self.h, _ptr(out), _buf(canon, self._nb[FIELD_CANON_HALF_VEC], "canon"),
+                                             parity))
         return out
 
     def vec_export(self, internal: torch.Tensor, parity: int = 0) -> torch.Tensor:
         out = torch.empty((self.Vh, 3), dtype=torch.complex128, device="cuda")
-        self._check(self.lib.stag_vec_export(self.h, _ptr(out), _ptr(internal), parity))
+        self._check(self.lib.stag_vec_export(self.h, _ptr(out), _buf(internal, self._nb[FIELD_HALF_VEC], "internal"),
+                                             parity))
         return out
 
     def mom_import(self, canon: torch.Tensor) -> torch.Tensor:
         out = self.new_mom()
-        self._check(self.lib.stag_mom_import(self.h, _ptr(out), _ptr(canon)))
+        self._check(self.lib.stag_mom_import(self.h, _ptr(out), _buf(canon, self._nb[FIELD_CANON_MOM], "canon")))
         return out
 
     def mom_export(self, internal: torch.Tensor) -> torch.Tensor:
         nx, ny, nz, nt = self.dims
         out = torch.empty((nt, nz, ny, nx, 4, 8), dtype=torch.float64, device="cuda")
-        self._check(self.lib.stag_mom_export(self.h, _ptr(out), _ptr(internal)))
+        self._check(self.lib.stag_mom_export(self.h, _ptr(out), _buf(internal, self._nb[FIELD_MOM], "internal")))
         return out
 
     # ---- operators
     def dslash(self, out: torch.Tensor, inp: torch.Tensor, out_parity: int):
-        self._check(self.lib.stag_dslash(self.h, _ptr(out), _ptr(inp), out_parity))
+        self._check(self.lib.stag_dslash(self.h, self._vec(out, "out"), self._vec(inp, "inp"), out_parity))
 
     def mdagm(self, out: torch.Tensor, inp: torch.Tensor, mass: float):
-        self._check(self.lib.stag_mdagm(self.h, _ptr(out), _ptr(inp), float(mass)))
+        self._check(self.lib.stag_mdagm(self.h, self._vec(out, "out"), self._vec(inp, "inp"), float(mass)))
+
+    def dslash_sloppy(self, out: torch.Tensor, inp: torch.Tensor, out_parity: int, fmt: int):
+        """The precision form's FP32 operator (links in fmt) on FP64 vectors."""
+        self._check(self.lib.stag_dslash_sloppy(self.h, self._vec(out, "out"), self._vec(inp, "inp"), out_parity,
+                                                int(fmt)))
+
+    def mdagm_sloppy(self, out: torch.Tensor, inp: torch.Tensor, mass: float, fmt: int):
+        self._check(self.lib.stag_mdagm_sloppy(self.h, self._vec(out, "out"), self._vec(inp, "inp"), float(mass),
+                                               int(fmt)))
+
+    def power_estimate(self, mass: float, iters: int, seed: int = 0) -> float:
+        lam = ctypes.c_double()
+        self._check(self.lib.stag_power_estimate(self.h, float(mass), int(iters), int(seed), ctypes.byref(lam)))
+        return lam.value
+
+    def check_spectrum(self, mass: float, xmin: float, xmax: float) -> float:
+        """Raises StagError(STAG_ERR_SPECTRUM) if [xmin, xmax] misses the spectrum of A;
+        returns the power estimate of its top (0 when the certain bound sufficed)."""
+        lam = ctypes.c_double()
+        self._check(self.lib.stag_check_spectrum(self.h, float(mass), float(xmin), float(xmax), ctypes.byref(lam)))
+        return lam.value
 
     # ---- solver
     def multishift_solve(self, mass, rat, tol, maxiter, b, xs=None, sum_out=None, true_resid=True,
@@ -276,11 +344,10 @@ class Lattice:
         resid = (ctypes.c_double * n)()
         ipp = (ctypes.c_int * n)()
         info = CSolveInfo(0, 0, resid if true_resid else None, ipp, 0.0)
-        xarr = None
-        if xs is not None:
-            xarr = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+        xarr = self._xs(xs, n)
         code = self.lib.stag_multishift_solve(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
-                                              _ptr(b), xarr, _ptr(sum_out), ctypes.byref(info))
+                                              self._vec(b, "b"), xarr, self._vec(sum_out, "sum_out", True),
+                                              ctypes.byref(info))
         allow = (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,)
         self._check(code, allow)
         return {"code": code, "iters": info.iters, "seconds": info.seconds,
@@ -293,13 +360,11 @@ class Lattice:
         resid = (ctypes.c_double * n)()
         ipp = (ctypes.c_int * n)()
         info = CSolveInfo(0, 0, resid if true_resid else None, ipp, 0.0)
-        xarr = None
-        if xs is not None:
-            xarr = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+        xarr = self._xs(xs, n)
         opts = CMixedOpts(int(sloppy), float(tol_sloppy), int(reliable_every))
         code = self.lib.stag_multishift_solve_mixed(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
-                                                    _ptr(b), xarr, _ptr(sum_out), ctypes.byref(opts),
-                                                    ctypes.byref(info))
+                                                    self._vec(b, "b"), xarr, self._vec(sum_out, "sum_out", True),
+                                                    ctypes.byref(opts), ctypes.byref(info))
         allow = (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,)
         self._check(code, allow)
         return {"code": code, "iters": info.iters, "seconds": info.seconds,
@@ -313,19 +378,20 @@ class Lattice:
         S = ctypes.c_double()
         info = CSolveInfo()
         self._check(self.lib.stag_fermion_action(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
-                                                 _ptr(phi), ctypes.byref(S), ctypes.byref(info)))
+                                                 self._vec(phi, "phi"), ctypes.byref(S), ctypes.byref(info)))
         return S.value
 
     def fermion_force(self, mass, rat, tol, maxiter, phi, mom, dt=0.0, allow_not_converged=False) -> dict:
         r = RationalArg(rat)
         info = CSolveInfo()
         code = self.lib.stag_fermion_force(self.h, float(mass), ctypes.byref(r.c), float(tol), int(maxiter),
-                                           _ptr(phi), _ptr(mom), float(dt), ctypes.byref(info))
+                                           self._vec(phi, "phi"), self._mom(mom, "mom"), float(dt),
+                                           ctypes.byref(info))
         self._check(code, (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,))
         return {"code": code, "iters": info.iters, "seconds": info.seconds}
 
     def gauge_force(self, beta, mom, dt=0.0):
-        self._check(self.lib.stag_gauge_force(self.h, float(beta), _ptr(mom), float(dt)))
+        self._check(self.lib.stag_gauge_force(self.h, float(beta), self._mom(mom, "mom"), float(dt)))
 
     def gauge_action(self, beta):
         S, plaq = ctypes.c_double(), ctypes.c_double()
@@ -345,11 +411,11 @@ class Lattice:
 
     def kinetic_energy(self, mom) -> float:
         K = ctypes.c_double()
-        self._check(self.lib.stag_kinetic_energy(self.h, _ptr(mom), ctypes.byref(K)))
+        self._check(self.lib.stag_kinetic_energy(self.h, self._mom(mom, "mom"), ctypes.byref(K)))
         return K.value
 
     def link_update(self, mom, dt):
-        self._check(self.lib.stag_link_update(self.h, _ptr(mom), float(dt)))
+        self._check(self.lib.stag_link_update(self.h, self._mom(mom, "mom"), float(dt)))
 
     def random_momentum(self, seed, traj) -> torch.Tensor:
         out = self.new_mom()
@@ -364,12 +430,14 @@ class Lattice:
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
                    no_fermions=False, surrogate=None, exact_every=1, coarse_force=False,
-                   record_pairs=False, inner_iters=0, md_link_format=0) -> dict:
+                   record_pairs=False, inner_iters=0, md_link_format=0, spectrum=None) -> dict:
         a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
         prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
-                         _ptr(inject_mom), _ptr(inject_xi), inject_u, int(no_fermions),
+                         self._mom(inject_mom, "inject_mom", True), self._vec(inject_xi, "inject_xi", True),
+                         inject_u, int(no_fermions),
                          surrogate.h if surrogate is not None else None, int(exact_every),
-                         int(coarse_force), int(record_pairs), int(inner_iters), int(md_link_format))
+                         int(coarse_force), int(record_pairs), int(inner_iters), int(md_link_format),
+                         *(map(float, spectrum) if spectrum is not None else (0.0, 0.0)))
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
         return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
@@ -439,14 +507,20 @@ class Batch:
         return int(self.lib.stag_batch_vec_bytes(self.h)) // 16
 
     def set_gauge(self, inst: int, U: torch.Tensor):
-        self._check(self.lib.stag_batch_set_gauge(self.h, int(inst), _ptr(U)))
+        if not 0 <= int(inst) < len(self.dims):
+            raise ValueError(f"inst: expected 0..{len(self.dims) - 1}, got {inst}")
+        nb = 2 * self.vh[int(inst)] * 4 * 9 * 16
+        self._check(self.lib.stag_batch_set_gauge(self.h, int(inst), _buf(U, nb, "U")))
 
     def solve(self, masses, rat, b: torch.Tensor, precision=0, tol=1e-10, tol_sloppy=1e-5, maxiter=100000,
               use_graph=True, true_resid=True, allow_not_converged=False):
         r = RationalArg(rat)
         n = r.c.n
         nsys = len(self.dims) * self.nrhs
-        m = (ctypes.c_double * len(self.dims))(*[float(v) for v in masses])
+        masses = [float(v) for v in masses]
+        if len(masses) != len(self.dims):
+            raise ValueError(f"masses: expected {len(self.dims)} values (one per lattice), got {len(masses)}")
+        m = (ctypes.c_double * len(self.dims))(*masses)
         x = torch.empty(n * self.vec_len(), dtype=torch.complex128, device="cuda")
         lat = (ctypes.c_double * nsys)()
         res = (ctypes.c_double * (nsys * n))()
@@ -454,7 +528,8 @@ class Batch:
         ipp = (ctypes.c_int * (nsys * n))()
         info = CBatchInfo(0, 0, 0.0, lat, res if true_resid else None, its, ipp)
         opts = CBatchOpts(int(precision), float(tol), float(tol_sloppy), int(maxiter), int(use_graph))
-        code = self.lib.stag_batch_solve(self.h, m, ctypes.byref(r.c), _ptr(b), _ptr(x), ctypes.byref(opts),
+        code = self.lib.stag_batch_solve(self.h, m, ctypes.byref(r.c), _buf(b, 16 * self.vec_len(), "b"), _ptr(x),
+                                         ctypes.byref(opts),
                                          ctypes.byref(info))
         allow = (STAG_OK, STAG_ERR_NOT_CONVERGED) if allow_not_converged else (STAG_OK,)
         self._check(code, allow)
@@ -518,10 +593,10 @@ class Surrogate:
         return int(self.lib.stag_surrogate_capacity(self.h))
 
     def set_aux(self, aux: torch.Tensor | None):
-        self._check(self.lib.stag_surrogate_set_aux(self.h, _ptr(aux) if aux is not None else None))
+        self._check(self.lib.stag_surrogate_set_aux(self.h, self.lat._mom(aux, "aux", True)))
 
     def add_pair(self, force: torch.Tensor):
-        self._check(self.lib.stag_surrogate_add_pair(self.h, _ptr(force)))
+        self._check(self.lib.stag_surrogate_add_pair(self.h, self.lat._mom(force, "force")))
 
     def train(self, epochs: int, lr: float) -> float:
         loss = ctypes.c_double()
@@ -532,11 +607,11 @@ class Surrogate:
         loss = ctypes.c_double()
         g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
         gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if want_grad else None
-        self._check(self.lib.stag_surrogate_eval(self.h, _ptr(force), ctypes.byref(loss), gp))
+        self._check(self.lib.stag_surrogate_eval(self.h, self.lat._mom(force, "force"), ctypes.byref(loss), gp))
         return loss.value, g
 
     def force(self, mom: torch.Tensor, dt: float = 0.0):
-        self._check(self.lib.stag_surrogate_force(self.h, _ptr(mom), float(dt)))
+        self._check(self.lib.stag_surrogate_force(self.h, self.lat._mom(mom, "mom"), float(dt)))
 
 
 def surrogate_params_to_flat(params: dict) -> np.ndarray:

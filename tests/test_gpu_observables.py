@@ -30,14 +30,15 @@ def test_polyakov_loop_matches_oracle(dims, eps):
 
 
 def test_chiral_condensate_matches_oracle():
-    """Same sources (counters (seed, k)), same estimator: the GPU mean and
-    standard error agree with the oracle's to the solver tolerance."""
+    """Same noise vectors (estimator-noise stream (seed, k)), same estimator:
+    the GPU mean and standard error agree with the oracle's to the solver
+    tolerance."""
     dims, mass, seed, n = (4, 4, 2, 4), 0.1, 5, 8
     log("chiral condensate")
     U = synth.random_su3_near_identity(dims, 0.6, synth.make_rng(711, 0))
     lat = lattice(dims, U)
     mean, err = lat.chiral_condensate(mass, 1e-12, 100000, n, seed)
-    etas = [philox.source(dims, seed, k) for k in range(n)]
+    etas = [philox.noise(dims, seed, k) for k in range(n)]
     ref, ref_err = fermion.chiral_condensate(U, dims, mass, etas, 1e-12)
     assert abs(mean - ref) < 1e-9 * abs(ref), (mean, ref)
     assert abs(err - ref_err) < 1e-6 * ref_err, (err, ref_err)

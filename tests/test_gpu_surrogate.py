@@ -149,7 +149,41 @@ def test_training_on_fermion_forces_lowers_the_loss():
     sur.train(30, 3e-3)
     l1, _ = sur.eval(mom)
     log(f"  fermion-force loss before {l0:.4e} after {l1:.4e}")
+    # Without the auxiliary channel the inputs are functions of U alone, while
+    # the force depends on the pseudofermion field drawn with it: the model
+    # can only learn the part common to the four pairs, so the bar is a
+    # decrease, not a factor.
     assert l1 < l0
+
+
+def test_training_with_the_truncated_force_channel():
+    """With the auxiliary channel set to the force of a solve stopped after 20
+    iterations (13% off the exact force on these fields, measured with the
+    oracle), c_6 = 1 alone already leaves (0.13)^2 = 1.8% of the loss of a
+    zero model: training on the exact forces must get below 10% of it."""
+    dims = (6, 4, 4, 8)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    lat = stag.Lattice(dims)
+    sur = stag.Surrogate(lat, 4, seed=5)
+    rng = synth.make_rng(702, 1)
+    keep = []
+    for k in range(4):
+        U = synth.random_su3_near_identity(dims, 0.5, rng)
+        lat.set_gauge(dev(U))
+        phi = lat.vec_import(dev(synth.gaussian_half_vector(dims, rng)), 0)
+        mom, aux = lat.new_mom(), lat.new_mom()
+        lat.fermion_force(0.1, rat, 1e-10, 100000, phi, mom, 0.0)
+        lat.fermion_force(0.1, rat, 1e-30, 20, phi, aux, 0.0, allow_not_converged=True)
+        sur.set_aux(aux)
+        sur.add_pair(mom)
+        keep.append(aux)
+    zero = stag.Surrogate(lat, 1)
+    zero.set_params(np.zeros(zero.n_params, dtype=np.float32))
+    l_zero, _ = zero.eval(mom)
+    sur.train(60, 1e-2)
+    l1, _ = sur.eval(mom)
+    log(f"  loss of a zero model {l_zero:.4e}, trained with the channel {l1:.4e}")
+    assert l1 < 0.1 * l_zero
 
 
 def test_trajectory_with_model_is_exact_when_every_kick_is_exact():
@@ -269,10 +303,155 @@ def test_model_error_paths():
     sur.add_pair(mom)
     with pytest.raises(stag.StagError):
         sur.add_pair(mom)                       # dataset full
-    with pytest.raises(stag.StagError):
-        sur.set_aux(mom[1:])                    # misaligned device pointer
+    with pytest.raises(ValueError):
+        sur.set_aux(mom[1:])                    # wrong size: refused by the binding
+    import ctypes                               # misaligned device pointer: refused by the library
+    assert sur.lib.stag_surrogate_set_aux(sur.h, ctypes.c_void_p(mom.data_ptr() + 8)) == stag.STAG_ERR_INVALID_ARG
     with pytest.raises(stag.StagError):
         sur.train(1, -1.0)                      # learning rate must be positive
     with pytest.raises(ValueError):
         sur.set_params(np.zeros(3, dtype=np.float32))
     assert sur.train(1, 1e-3) >= 0.0
+
+
+# ---- the learned model at the size of the 16^3x8 RHMC workload -------------
+# 131,072 links: every wave of the training and inference kernels walks 8
+# tiles of 16 links, accumulating across tiles and reusing its LDS, which the
+# small lattices above (at most one tile per wave) never do.
+
+C4 = (16, 16, 16, 8)
+U_BF16 = 2.0 ** -8          # unit roundoff of bfloat16 (8 significant bits)
+
+
+def _c4_setup(with_aux, seed=0):
+    U = synth.random_su3_near_identity(C4, 0.6, synth.make_rng(708, seed))
+    nx, ny, nz, nt = C4
+    rng = synth.make_rng(708, 100 + seed)
+    target = rng.standard_normal((nt, nz, ny, nx, 4, 8))
+    aux = rng.standard_normal((nt, nz, ny, nx, 4, 8)) if with_aux else None
+    return U, target, aux
+
+
+def _fp64_bounds(p, f, B, target):
+    """First-order bounds on |model_bf16 - model_fp64| for the force and the
+    gradient, from the bf16 unit roundoff u of the operands each matrix
+    product rounds (both operands: 2u), propagated through SiLU (|silu'| <=
+    1.1, |silu''| <= 0.5) and the backward products; 1e-5 of the absolute
+    terms covers the FP32 accumulations.  Returns (e_F, e_grad dict)."""
+    u = U_BF16
+    a = np.abs
+    W1, W2, W3 = p["W1"], p["W2"], p["W3"]
+    z1 = f @ W1.T + p["b1"]
+    h1 = S.silu(z1)
+    z2 = h1 @ W2.T + p["b2"]
+    h2 = S.silu(z2)
+    c = h2 @ W3.T + p["b3"]
+    F = np.einsum("nj,nja->na", c[:, :S.N_CH], B)
+    e_z1 = 2 * u * (a(f) @ a(W1).T)
+    e_h1 = 1.1 * e_z1
+    e_z2 = 2 * u * (a(h1) @ a(W2).T) + e_h1 @ a(W2).T
+    e_h2 = 1.1 * e_z2
+    e_c = 2 * u * (a(h2) @ a(W3).T) + e_h2 @ a(W3).T
+    absF = np.einsum("nj,nja->na", a(c[:, :S.N_CH]), a(B))
+    e_F = np.einsum("nj,nja->na", e_c[:, :S.N_CH], a(B)) + 1e-5 * absF
+    N = f.shape[0]
+    dF = 2.0 * (F - target) / N
+    e_dF = 2.0 * e_F / N
+    dc = np.zeros((N, S.N_OUT))
+    e_dc = np.zeros((N, S.N_OUT))
+    dc[:, :S.N_CH] = np.einsum("na,nja->nj", dF, B)
+    e_dc[:, :S.N_CH] = np.einsum("na,nja->nj", e_dF, a(B)) + 1e-5 * np.einsum("na,nja->nj", a(dF), a(B))
+    s2, s1 = S.dsilu(z2), S.dsilu(z1)
+    dh2 = dc @ W3
+    e_dh2 = 2 * u * (a(dc) @ a(W3)) + e_dc @ a(W3)
+    dz2 = dh2 * s2
+    e_dz2 = e_dh2 * a(s2) + a(dh2) * 0.5 * e_z2
+    dh1 = dz2 @ W2
+    e_dh1 = 2 * u * (a(dz2) @ a(W2)) + e_dz2 @ a(W2)
+    dz1 = dh1 * s1
+    e_dz1 = e_dh1 * a(s1) + a(dh1) * 0.5 * e_z1
+    acc = 1e-5
+    e = {"W3": (2 * u * a(dc) + e_dc).T @ a(h2) + a(dc).T @ e_h2 + acc * (a(dc).T @ a(h2)),
+         "b3": e_dc.sum(0) + acc * a(dc).sum(0),
+         "W2": (2 * u * a(dz2) + e_dz2).T @ a(h1) + a(dz2).T @ e_h1 + acc * (a(dz2).T @ a(h1)),
+         "b2": e_dz2.sum(0) + acc * a(dz2).sum(0),
+         "W1": (2 * u * a(dz1) + e_dz1).T @ a(f) + acc * (a(dz1).T @ a(f)),
+         "b1": e_dz1.sum(0) + acc * a(dz1).sum(0)}
+    return e_F, e
+
+
+@pytest.mark.parametrize("with_aux", [False, True])
+def test_c4_size_force_matches_oracle(with_aux):
+    """Model force at 16^3x8 against the oracle's bf16 mode (same rounding
+    points) and against its FP64 mode within the bf16 roundoff bound."""
+    log(f"surrogate force 16^3x8 aux={with_aux}")
+    U, _, aux = _c4_setup(with_aux)
+    lat = lattice(C4, U)
+    sur = stag.Surrogate(lat, 1)
+    p = _params(11)
+    sur.set_params(_flat(p))
+    if with_aux:
+        aux_dev = lat.mom_import(dev(aux))
+        sur.set_aux(aux_dev)
+    mom = lat.new_mom()
+    sur.force(mom, 0.0)
+    got = host(lat.mom_export(mom)).reshape(-1, 8)
+    f, loops = S.features(U, C4, aux)
+    B = S.basis(loops, aux)
+    exp_bf, _ = S.forward(p, f, B, mode="bf16")
+    scale = np.abs(exp_bf).max()
+    assert np.abs(got - exp_bf).max() < 3e-3 * scale
+    assert np.sqrt(np.mean((got - exp_bf) ** 2)) < 2e-4 * scale
+    exp64, _ = S.forward(p, f, B, mode="fp64")
+    e_F, _ = _fp64_bounds(p, f, B, np.zeros_like(exp64))
+    ratio = np.abs(got - exp64) / e_F
+    log(f"  max |F_gpu - F_fp64| / bound = {ratio.max():.3f}")
+    assert ratio.max() <= 1.0
+
+
+def test_c4_size_loss_gradient_and_adam_match_oracle():
+    """Loss and gradient at 16^3x8 (with the auxiliary channel) against the
+    oracle's bf16 mode and, within the bf16 roundoff bound, its FP64 mode;
+    then two Adam steps of the GPU trainer against the oracle's Adam applied
+    to the same gradients."""
+    log("surrogate loss / gradient / Adam 16^3x8")
+    U, target, aux = _c4_setup(True, seed=1)
+    lat = lattice(C4, U)
+    sur = stag.Surrogate(lat, 1)
+    p = _params(12)
+    sur.set_params(_flat(p))
+    aux_dev = lat.mom_import(dev(aux))
+    sur.set_aux(aux_dev)
+    tdev = lat.mom_import(dev(target))
+    loss, g = sur.eval(tdev, want_grad=True)
+    f, loops = S.features(U, C4, aux)
+    tf = target.reshape(-1, 8).astype(np.float32).astype(np.float64)
+    B = S.basis(loops, aux).astype(np.float32).astype(np.float64)
+    lref, gref = S.loss_and_grad(p, f, B, tf, mode="bf16")
+    assert abs(loss - lref) < 1e-4 * lref
+    gg = _unflat(g.astype(np.float64))
+    for k in KEYS:
+        err = np.abs(gg[k] - gref[k]).max() / max(np.abs(gref[k]).max(), 1e-30)
+        assert err < 2e-2, (k, err)
+    l64, g64 = S.loss_and_grad(p, f, B, tf, mode="fp64")
+    _, e_g = _fp64_bounds(p, f, B, tf)
+    for k in KEYS:
+        ratio = (np.abs(gg[k] - g64[k]) / e_g[k]).max()
+        log(f"  {k}: max |g_gpu - g_fp64| / bound = {ratio:.3f}")
+        assert ratio <= 1.0, k
+    # Adam: the trainer's step on its one pair uses the gradient eval returns
+    sur.add_pair(tdev)
+    state = {}
+    ref = {k: v.copy() for k, v in p.items()}
+    lr = 3e-3
+    for step in range(2):
+        _, gs = sur.eval(tdev, want_grad=True)
+        sur.train(1, lr)
+        S.adam_step(ref, _unflat(gs.astype(np.float64)), state, lr=lr)
+        got = _unflat(sur.get_params().astype(np.float64))
+        for k in KEYS:
+            d = np.abs(got[k] - ref[k])
+            tol = 1e-5 * lr + 2.0 ** -23 * np.abs(ref[k])
+            assert (d <= tol).all(), (step, k, d.max())
+        moved = np.abs(got["W2"] - p["W2"]).max()
+        assert 0.5 * lr * (step + 1) < moved <= 1.01 * lr * (step + 1)

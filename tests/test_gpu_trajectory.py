@@ -157,3 +157,28 @@ def test_fp32_md_forces(fmt):
     assert abs(outs[0]["Sf_old"] - ref["H0"][2]) <= 1e-10 * abs(ref["H0"][2])
     tol = 1e-4 if fmt == 2 else 5e-2
     assert abs(outs[0]["dH"] - ref["dH"]) < tol * max(1.0, abs(ref["dH"]))
+
+
+def test_failed_solve_restores_the_links():
+    """A momentum field with one NaN component passes the heat bath and the
+    first kick, moves one link to NaN in the first link update, and the next
+    force solve stops with NONFINITE: the handle's links are then those of the
+    call, bit for bit, and the next trajectory runs normally."""
+    from paper_1710_09178_amd import stag
+    dims = (4, 4, 2, 4)
+    log("trajectory error path restores the links")
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(300, 9))
+    prm = _params(4, 0.5)
+    lat = lattice(dims, U0)
+    before = host(lat.get_gauge())
+    P = philox.momentum(dims, 1, 0)
+    P[1, 0, 1, 2, 3, 5] = np.nan
+    bad = lat.mom_import(dev(P))
+    with pytest.raises(stag.StagError) as ei:
+        lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                       tol_md=1e-12, tol_action=1e-12, seed=1, traj_index=0, inject_mom=bad)
+    assert ei.value.code == stag.STAG_ERR_NONFINITE
+    assert np.array_equal(host(lat.get_gauge()), before)
+    out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                         tol_md=1e-12, tol_action=1e-12, seed=1, traj_index=0)
+    assert np.isfinite(out["dH"])

@@ -82,7 +82,21 @@ def test_condensate_estimator_converges_to_the_trace():
     dims, mass = (2, 2, 2, 2), 0.2
     U = synth.random_su3_near_identity(dims, 0.8, synth.make_rng(721, 0))
     exact = 4 * mass * np.trace(np.linalg.inv(_dense_A(U, dims, mass))).real / L.volume(dims)
-    etas = [philox.source(dims, 5, k) for k in range(400)]
+    etas = [philox.noise(dims, 5, k) for k in range(400)]
     est, err = fermion.chiral_condensate(U, dims, mass, etas, 1e-13)
     assert 0 < err < 0.05 * abs(exact)
     assert abs(est - exact) < 4 * err
+
+
+def test_estimator_noise_is_not_a_heat_bath_source():
+    """The noise stream has its own field of the counter: with the chain's seed
+    none of its vectors repeats the heat-bath source of any trajectory, and its
+    moments are those of the source distribution."""
+    dims = (4, 4, 2, 4)
+    for k in range(4):
+        eta = philox.noise(dims, 9, k)
+        for traj in range(4):
+            assert np.abs(eta - philox.source(dims, 9, traj)).max() > 0.1
+    big = np.concatenate([philox.noise((8, 8, 8, 8), 3, k).ravel() for k in range(4)])
+    assert abs(np.mean(np.abs(big) ** 2) - 1.0) < 0.02
+    assert abs(np.mean(big)) < 0.02

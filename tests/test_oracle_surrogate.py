@@ -102,6 +102,41 @@ def test_bf16_rounding():
     assert np.array_equal(S.bf16(vals), exp)
 
 
+def test_adam_first_step_closed_form():
+    """With bias correction the first Adam step moves every parameter by
+    -lr g / (|g| + eps) (m_1 / (1 - b1) = g, v_1 / (1 - b2) = g^2): about lr
+    against the gradient's sign for |g| >> eps, and g / (|g| + eps) of it for
+    tiny gradients (which places eps outside the square root)."""
+    lr, eps = 0.01, 1e-8
+    g = np.array([0.3, -2.0, 1e-9, -3e-9, 0.0, 5e3])
+    params = {"w": np.zeros_like(g)}
+    S.adam_step(params, {"w": g}, {}, lr=lr)
+    exp = -lr * g / (np.abs(g) + eps)
+    assert np.allclose(params["w"], exp, rtol=1e-12, atol=0.0)
+    # a step without bias correction would be (1-b1)/sqrt(1-b2) = 3.16 times longer
+    assert abs(params["w"][1] - lr) < 1e-9
+
+
+def test_adam_second_step_by_hand():
+    """Two steps with gradients g1 then g2, written out:
+    m_2 / (1 - b1^2) = (b1 g1 + g2) / (1 + b1),  v_2 / (1 - b2^2) = (b2 g1^2 + g2^2) / (1 + b2),
+    step_2 = -lr (b1 g1 + g2) / (1 + b1) / (sqrt((b2 g1^2 + g2^2) / (1 + b2)) + eps)."""
+    lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
+    g1 = np.array([1.0, 0.5, -2.0, 1.0])
+    g2 = np.array([0.0, 0.5, 3.0, -1.0])
+    params = {"w": np.array([0.1, 0.2, 0.3, 0.4])}
+    state = {}
+    S.adam_step(params, {"w": g1}, state, lr=lr)
+    w1 = params["w"].copy()
+    S.adam_step(params, {"w": g2}, state, lr=lr)
+    step2 = -lr * ((b1 * g1 + g2) / (1 + b1)) / (np.sqrt((b2 * g1 ** 2 + g2 ** 2) / (1 + b2)) + eps)
+    assert np.allclose(params["w"] - w1, step2, rtol=1e-12, atol=1e-15)
+    # first entry worked out by hand (g1 = 1, g2 = 0; eps changes it by 5e-10)
+    assert abs((params["w"][0] - w1[0]) - (-lr * (0.9 / 1.9) / np.sqrt(0.999 / 1.999))) < 1e-9
+    # an unchanged gradient keeps the step at lr (eps changes it by 1e-9)
+    assert abs((params["w"][1] - w1[1]) + lr) < 2e-9
+
+
 def test_adam_minimises_a_quadratic():
     params = {"w": np.array([3.0, -2.0])}
     state = {}
