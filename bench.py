@@ -233,6 +233,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-naik", action="store_true")
+    ap.add_argument("--no-memory-check", action="store_true")
     ap.add_argument("--chain-traj", type=int, default=24, help="trajectories per learned-force comparison chain")
     ap.add_argument("--inner-iters", type=int, default=200,
                     help="iterations of the truncated solve that feeds the learned model's auxiliary channel")
@@ -289,7 +291,11 @@ def main():
     torch.cuda.synchronize()
     log(f"timing {args.steps} solves")
     t0 = time.perf_counter()
-    infos = [step() for _ in range(args.steps)]
+    infos, step_ms = [], []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step())      # returns after the solve has finished (host-side info)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
@@ -301,6 +307,7 @@ def main():
     lat.profile_enable(3 * (infos[0]["iters"] + 64))
     chk = step(resid=True)
     ms, cnt = lat.profile_read()
+    doe_samples = lat.profile_samples(0)
     lat.profile_enable(0)
     avg_us = [1e3 * ms[i] / max(cnt[i], 1) for i in range(3)]
     doe_gbs = B_DOE * vh / (avg_us[0] * 1e-6) / 1e9
@@ -313,6 +320,16 @@ def main():
     if not args.no_forms:
         log("precision forms")
         forms = precision_forms(lat, rat, bd, xs, vh, base, ms_per_step)
+
+    memory = None
+    if not args.no_memory_check:
+        log("memory check: stream ceilings, isolated D_oe after a read sweep, 48^3x16 solve")
+        memory = memory_check(lat, bd, vh)
+
+    improved = None
+    if not args.no_naik:
+        log("Naik-improved operator")
+        improved = improved_operator(lat, rat, bd, xs, vh)
 
     batched = None
     if not args.no_batch:
@@ -347,6 +364,8 @@ def main():
         "kernels": {"dslash_oe": {"avg_us": round(avg_us[0], 3), "GB/s": round(doe_gbs, 1), "launches": cnt[0]},
                     "dslash_eo_cg": {"avg_us": round(avg_us[1], 3), "GB/s": round(deo_gbs, 1), "launches": cnt[1]},
                     "shift_update": {"avg_us": round(avg_us[2], 3), "GB/s": round(upd_gbs, 1), "launches": cnt[2]}},
+        "ms_per_step_pct": _pct(step_ms),
+        "dslash_oe_us_pct": _pct(doe_samples),
         "iterations": infos[0]["iters"],
         "true_resid_max": max(chk["true_resid"]),
         "dslash_gflops": round(570 * vh * 1e-9 / (avg_us[0] * 1e-6), 1),
@@ -357,6 +376,14 @@ def main():
         out["precision_forms"] = forms
     if batched:
         out["batched_form"] = batched
+    if improved:
+        out["naik_operator"] = improved
+    if memory:
+        out["memory_check"] = memory
+        out["roofline"]["beyond_cache"] = {
+            "dslash_oe_48c3x16_frac": memory["solve_48c3x16"]["dslash_oe_frac_at_p50"],
+            "dslash_oe_32c3x8_after_read_sweep_GB/s":
+                memory["dslash_oe_32c3x8_isolated_after_2GiB_read_sweep_us"]["GB/s_at_p50"]}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(U, b, rat, vh, args.lag, args.cpu_seconds)
@@ -394,6 +421,137 @@ def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
         out[name] = {"ms_per_solve": round(msm, 3), "speedup_vs_fp64_18": round(fp64_ms / msm, 3),
                      "iterations_total": im["iters"], "iterations_per_pole": im["iters_per_pole"],
                      "true_resid_max": max(chk["true_resid"]), "tol_sloppy": 1e-5, "reliable_every": 50}
+    return out
+
+
+def _pct(v):
+    import numpy as np
+    v = np.asarray(v, dtype=np.float64)
+    return {"p10": round(float(np.percentile(v, 10)), 3), "p50": round(float(np.percentile(v, 50)), 3),
+            "p90": round(float(np.percentile(v, 90)), 3), "n": int(v.size)}
+
+
+def memory_check(lat, bd, vh, reps=20):
+    """Which memory serves the D_oe kernel.  (1) STREAM-like ceilings of this
+    GPU: a read-only sum of 4 GiB and a 2 GiB copy (torch kernels, events on
+    torch's stream).  (2) The isolated 32^3x8 D_oe, back to back and each one
+    right after a read-only 2 GiB sweep (no dirty lines left to write back),
+    which evicts the 151 MB of links from the 256 MB Infinity Cache.  (3) The
+    12-pole solve at 48^3x16, whose 1.02 GB of links cannot stay in any cache:
+    its D_oe is served by HBM.  The 48^3x16 links are the 24^3x8 eps = 0.2
+    field repeated 2x2x2x2 (bandwidth does not depend on the values); the
+    source is drawn at full size."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice
+    out = {}
+    big = torch.ones(4 * 2 ** 30 // 8, dtype=torch.float64, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    big.sum()
+    sums, copies = [], []
+    half = big[: big.numel() // 2]
+    dst = torch.empty_like(half)
+    for _ in range(5):
+        e0.record()
+        big.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        sums.append(big.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        e0.record()
+        dst.copy_(half)
+        e1.record()
+        torch.cuda.synchronize()
+        copies.append(2 * half.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del dst
+    out["stream_ceiling_GB/s"] = {"read_sum_4GiB": round(max(sums), 1), "copy_2GiB": round(max(copies), 1)}
+    sweep = big[: 2 * 2 ** 30 // 8]
+    y = lat.new_vec()
+    for mode in ("back_to_back", "after_2GiB_read_sweep"):
+        lat.profile_enable(4)
+        for _ in range(reps):
+            if mode != "back_to_back":
+                sweep.sum()
+            lat.dslash(y, bd, 1)
+        us = lat.profile_samples(0)
+        lat.profile_enable(0)
+        pc = _pct(us)
+        pc["GB/s_at_p50"] = round(B_DOE * vh / (pc["p50"] * 1e-6) / 1e9, 1)
+        out[f"dslash_oe_32c3x8_isolated_{mode}_us"] = pc
+    del big, sweep
+    torch.cuda.empty_cache()
+    dims = (48, 48, 48, 16)
+    small = synth.random_su3_near_identity((24, 24, 24, 8), 0.2, synth.make_rng(1, 0))
+    U = np.tile(small, (2, 2, 2, 2, 1, 1, 1))
+    b = synth.gaussian_half_vector(dims, synth.make_rng(1, 2))
+    rat = synth.load_rational(TABLE)
+    big_lat = Lattice(dims)
+    big_lat.set_gauge(torch.from_numpy(U).cuda())
+    del U, small
+    bdev = big_lat.vec_import(torch.from_numpy(b).cuda(), 0)
+    xs = [big_lat.new_vec() for _ in rat["pole"]]
+    big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
+    ms = (time.perf_counter() - t0) * 1e3
+    big_lat.profile_enable(3 * (info["iters"] + 64))
+    chk = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=True)
+    vh48 = big_lat.Vh
+    doe = _pct(big_lat.profile_samples(0))
+    deo = _pct(big_lat.profile_samples(1))
+    big_lat.profile_enable(0)
+    base = int(np.argmin(rat["pole"]))
+    out["solve_48c3x16"] = {
+        "ms_per_solve": round(ms, 3), "iterations": info["iters"], "true_resid_max": max(chk["true_resid"]),
+        "value_GB/s": round(solve_bytes(vh48, info["iters"], info["iters_per_pole"], base, 8) / (ms * 1e-3) / 1e9, 1),
+        "links_GB": round(2 * 4 * 144 * vh48 / 1e9, 3),
+        "dslash_oe_us": doe, "dslash_oe_GB/s_at_p50": round(B_DOE * vh48 / (doe["p50"] * 1e-6) / 1e9, 1),
+        "dslash_oe_frac_at_p50": round(B_DOE * vh48 / (doe["p50"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+        "dslash_eo_cg_us": deo, "dslash_eo_cg_GB/s_at_p50": round(B_DEO_CG * vh48 / (deo["p50"] * 1e-6) / 1e9, 1)}
+    del big_lat, xs, bdev
+    torch.cuda.empty_cache()
+    return out
+
+
+# Naik-improved operator: 16 links per output site (8 one-hop, 8 long links)
+B_NAIK_DOE = {"f64_links18": 16 * 144 + 96, "f64_links12": 16 * 96 + 96}
+NAIK_FLOP = 16 * 66 + 15 * 6 + 2 * 6   # 16 SU(3) x vector, the sums, the two weights
+
+
+def improved_operator(lat, rat, bd, xs, vh, reps=3):
+    """The 32^3x8 12-pole solve with the Naik-improved operator (c1 = 9/8,
+    c3 = -1/24), FP64 18-real and 12-real links: solve time, iterations, true
+    residuals, and its D_oe kernel timed with events inside a profiled solve
+    (algorithmic bytes: 16 links + in + out per output site)."""
+    import torch
+    from paper_1710_09178_amd import stag
+    out = {}
+    lat.set_naik(9.0 / 8.0, -1.0 / 24.0)
+    for name, fmt in [("f64_links18", stag.LINKS_F64_18), ("f64_links12", stag.LINKS_F64_12)]:
+        lat.set_link_format(fmt)
+        lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            info = lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        lat.profile_enable(3 * (info["iters"] + 64))
+        chk = lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=True)
+        pms, cnt = lat.profile_read()
+        lat.profile_enable(0)
+        us = 1e3 * pms[0] / max(cnt[0], 1)
+        gbs = B_NAIK_DOE[name] * vh / (us * 1e-6) / 1e9
+        out[name] = {"ms_per_solve": round(ms, 3), "iterations": info["iters"],
+                     "true_resid_max": max(chk["true_resid"]),
+                     "dslash_oe_avg_us": round(us, 3), "dslash_oe_GB/s": round(gbs, 1),
+                     "dslash_oe_frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "dslash_oe_gflops": round(NAIK_FLOP * vh * 1e-9 / (us * 1e-6), 1),
+                     "algorithmic_bytes_per_site": B_NAIK_DOE[name]}
+    lat.set_link_format(stag.LINKS_F64_18)
+    lat.set_naik(1.0, 0.0)
     return out
 
 

@@ -175,6 +175,24 @@ typedef enum {
  * derived from the handle's links whenever they change. */
 stag_status stag_set_link_format(stag_handle h, int format);
 
+/* Operator improvement (Sec. 8 Summary: "improved" staggered quarks, whose
+ * stencil reaches past the nearest neighbours).  With (c1, c3) != (1, 0)
+ * every operator application of h -- stag_dslash, stag_mdagm, the sloppy
+ * operators and all solves -- uses the Naik-improved hopping term
+ *   c1 sum_mu s_mu(x) [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)]
+ * + c3 sum_mu s3_mu(x) [L_mu(x) psi(x+3mu) - L_mu(x-3mu)^dag psi(x-3mu)],
+ * L_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu), with the staggered phase of
+ * direction mu once per path and -1 per link of the path that leaves the last
+ * time slice.  Tree-level improvement is c1 = 9/8, c3 = -1/24; (1, 0) restores
+ * the one-hop operator.  The long links are derived from the links (in the
+ * format set by stag_set_link_format, and the sloppy formats on demand) at
+ * the first operator call after every change of the links; the first use
+ * allocates them (144 B per link in FP64).  The pseudofermion force and
+ * trajectories with fermions need the one-hop operator: with the improvement
+ * on they return STAG_ERR_INVALID_ARG.  Returns STAG_ERR_INVALID_ARG for
+ * non-finite weights. */
+stag_status stag_set_naik(stag_handle h, double c1, double c3);
+
 /* The sloppy operator of the precision form, applied to FP64 internal vectors
  * so that its error against the FP64 operator can be measured: in is rounded
  * to FP32, D (stag_dslash_sloppy: out_parity 1 = D_oe, 0 = D_eo) or
@@ -429,8 +447,15 @@ stag_status stag_batch_set_tps(stag_batch_handle b, int tps);
 stag_status stag_profile_enable(stag_handle h, int max_launches);
 /* Accumulated kernel milliseconds and launch counts since stag_profile_enable:
  * index 0 = D_oe (odd <- even), 1 = D_eo with the fused CG epilogue,
- * 2 = fused multi-shift vector update.  Host arrays of length 3, may be NULL. */
+ * 2 = fused multi-shift vector update.  Host arrays of length 3, may be NULL.
+ * While recording is on, stag_dslash also times its launch (waiting for it)
+ * and books it under 0 (D_oe) or 1 (plain D_eo). */
 stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
+/* The individual recorded launch durations of one kind (index as above), in
+ * microseconds and in launch order: *n_out receives the number recorded, the
+ * first min(cap, *n_out) go to us_out (host array).  STAG_ERR_INVALID_ARG for
+ * a kind outside [0, 2], cap < 0, n_out NULL, or us_out NULL with cap > 0. */
+stag_status stag_profile_samples(stag_handle h, int kind, float* us_out, int cap, int* n_out);
 /* Solvers replay each chunk of iterations from a hipGraph captured on first
  * use (kernel nodes only; up to 8 cached per handle, keyed by every launch
  * argument) unless profiling or reliable updates need per-launch work.  on = 0

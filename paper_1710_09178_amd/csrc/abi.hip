@@ -168,9 +168,9 @@ stag_status power_rayleigh_impl(stag_ctx* c, double mass, int iters, uint64_t se
 
 // Interval [xmin, xmax] of a rational table against the spectrum of A: the
 // table must reach below 4m^2 (the exact lower bound) and above lambda_max,
-// either for certain (xmax >= 4m^2 + 64, since |D_oe| <= 8) or with a margin
-// of 10% over the power estimate after 100 iterations (which lies below
-// lambda_max).
+// either for certain (xmax >= 4m^2 + dmax^2 with dmax = 8 >= |D_oe|, or
+// 8 (|c1| + |c3|) for the improved operator) or with a margin of 10% over the
+// power estimate after 100 iterations (which lies below lambda_max).
 constexpr int kSpectrumIters = 100;
 constexpr double kSpectrumMargin = 0.1;
 stag_status spectrum_check_impl(stag_ctx* c, double mass, double xmin, double xmax, double* lam_out) {
@@ -182,7 +182,8 @@ stag_status spectrum_check_impl(stag_ctx* c, double mass, double xmin, double xm
                  lo);
         return fail(c, STAG_ERR_SPECTRUM, buf);
     }
-    if (xmax >= lo + 64.0) return STAG_OK;
+    const double dmax = c->naik ? 8.0 * (std::fabs(c->naik_c1) + std::fabs(c->naik_c3)) : 8.0;
+    if (xmax >= lo + dmax * dmax) return STAG_OK;
     double lam = 0.0;
     stag_status e = power_rayleigh_impl(c, mass, kSpectrumIters, 0, &lam);
     if (e) return e;
@@ -294,7 +295,8 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
 stag_status stag_destroy(stag_handle c) {
     if (!c) return STAG_OK;
     if (c->s) hipStreamSynchronize(c->s);
-    void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->r32, c->p32, c->Ap32, c->w32,
+    void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->long_d18, c->long_d12, c->long_s18, c->long_h12,
+                    c->r32, c->p32, c->Ap32, c->w32,
                     c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
                     c->gpart, c->scal, c->mom_tmp, c->mom_aux};
@@ -399,7 +401,19 @@ stag_status stag_dslash(stag_handle c, void* out, const void* in, int out_parity
     if ((e = enter(c))) return e;
     LinkSet ls;
     if ((e = get_links(c, -1, ls))) return e;
+    const bool timed = c->prof_on && c->prof_ev.size() >= 2;
+    if (timed) next_launch_timing() = LaunchTiming{c->prof_ev[0], c->prof_ev[1]};
     launch_dslash(c->g, ls, (const double2*)in, (double2*)out, out_parity, c->tps, nullptr, c->s);
+    if (timed) {
+        // measurement mode: wait for the launch and book it as D_oe / D_eo
+        HIP_OR_FAIL(c, hipEventSynchronize(c->prof_ev[1]));
+        float ms = 0.f;
+        HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]));
+        const int kind = out_parity == 1 ? 0 : 1;
+        c->prof_ms[kind] += ms;
+        c->prof_cnt[kind] += 1;
+        c->prof_samples[kind].push_back(ms);
+    }
     return leave(c);
 }
 
@@ -539,13 +553,36 @@ stag_status stag_multishift_solve_mixed(stag_handle c, double mass, const stag_r
     return solve_entry(c, mass, r, tol, maxiter, b, x, sum, opts, info);
 }
 
+// Allocates the derived link copies the FP64 operator of c needs (filled by
+// get_links at the next operator call), so that operator calls themselves do
+// not allocate.
+stag_status alloc_link_copies(stag_ctx* c) {
+    const size_t l12 = (size_t)48 * c->g.vh * sizeof(double2), l18 = (size_t)72 * c->g.vh * sizeof(double2);
+    stag_status e;
+    if (c->fmt64 == STAG_LINKS_F64_12 && !c->links_d12 && (e = dmalloc(c, &c->links_d12, l12))) return e;
+    if (c->naik && !c->long_d18 && (e = dmalloc(c, &c->long_d18, l18))) return e;
+    if (c->naik && c->fmt64 == STAG_LINKS_F64_12 && !c->long_d12 && (e = dmalloc(c, &c->long_d12, l12))) return e;
+    return STAG_OK;
+}
+
 stag_status stag_set_link_format(stag_handle c, int format) {
     stag_status e = check_common(c, false);
     if (e) return e;
     if (format != STAG_LINKS_F64_18 && format != STAG_LINKS_F64_12)
         return fail(c, STAG_ERR_INVALID_ARG, "FP64 operator format must be STAG_LINKS_F64_18 or STAG_LINKS_F64_12");
     c->fmt64 = format;
-    return STAG_OK;
+    return alloc_link_copies(c);
+}
+
+stag_status stag_set_naik(stag_handle c, double c1, double c3) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (!std::isfinite(c1) || !std::isfinite(c3))
+        return fail(c, STAG_ERR_INVALID_ARG, "Naik weights must be finite");
+    c->naik = !(c1 == 1.0 && c3 == 0.0);
+    c->naik_c1 = c1;
+    c->naik_c3 = c3;
+    return alloc_link_copies(c);
 }
 
 stag_status stag_fermion_action(stag_handle c, double mass, const stag_rational* r, double tol, int maxiter,
@@ -577,6 +614,8 @@ stag_status stag_fermion_force(stag_handle c, double mass, const stag_rational* 
     if (!(tol > 0.0) || maxiter < 1) return fail(c, STAG_ERR_INVALID_ARG, "need tol > 0 and maxiter >= 1");
     if (!aligned16(phi) || !aligned16(mom)) return fail(c, STAG_ERR_INVALID_ARG, "phi/mom NULL or misaligned");
     if (!std::isfinite(dt)) return fail(c, STAG_ERR_INVALID_ARG, "dt must be finite");
+    if (c->naik)
+        return fail(c, STAG_ERR_INVALID_ARG, "the pseudofermion force is implemented for the one-hop operator only");
     if ((e = enter(c))) return e;
     SolveResult res;
     if ((e = fermion_force_impl(c, mass, r, tol, maxiter, (const double2*)phi, (double*)mom, dt, res))) return e;
@@ -712,6 +751,8 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         p->maxiter < 1)
         return fail(c, STAG_ERR_INVALID_ARG, "need n_steps >= 1, tau > 0, tolerances > 0, maxiter >= 1");
     const bool ferm = !p->no_fermions;
+    if (ferm && c->naik)
+        return fail(c, STAG_ERR_INVALID_ARG, "trajectories with fermions need the one-hop operator (no Naik force)");
     if (ferm) {
         if ((e = check_rational(c, &p->r_md, p->mass)) || (e = check_rational(c, &p->r_action, p->mass)) ||
             (e = check_rational(c, &p->r_heatbath, p->mass)))
@@ -907,7 +948,7 @@ stag_status stag_profile_enable(stag_handle c, int max_launches) {
     for (auto ev : c->prof_ev) hipEventDestroy(ev);
     c->prof_ev.clear();
     c->prof_on = max_launches > 0;
-    for (int i = 0; i < 3; ++i) c->prof_ms[i] = 0, c->prof_cnt[i] = 0;
+    for (int i = 0; i < 3; ++i) c->prof_ms[i] = 0, c->prof_cnt[i] = 0, c->prof_samples[i].clear();
     if (!c->prof_on) return STAG_OK;
     c->prof_ev.resize((size_t)2 * max_launches);
     for (auto& ev : c->prof_ev)
@@ -924,6 +965,18 @@ stag_status stag_profile_read(stag_handle c, double ms[3], long counts[3]) {
         if (ms) ms[i] = c->prof_ms[i];
         if (counts) counts[i] = c->prof_cnt[i];
     }
+    return STAG_OK;
+}
+
+// The recorded launch durations of one kind, in order (microseconds).
+stag_status stag_profile_samples(stag_handle c, int kind, float* us_out, int cap, int* n_out) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (kind < 0 || kind > 2 || cap < 0 || !n_out || (cap > 0 && !us_out))
+        return fail(c, STAG_ERR_INVALID_ARG, "need kind in [0, 2], cap >= 0, n_out and us_out when cap > 0");
+    const auto& v = c->prof_samples[kind];
+    *n_out = (int)v.size();
+    for (int i = 0; i < cap && i < (int)v.size(); ++i) us_out[i] = 1e3f * v[i];
     return STAG_OK;
 }
 

@@ -24,6 +24,14 @@ struct stag_ctx {
     void* links_h12 = nullptr;
     bool d12_ok = false, s18_ok = false, h12_ok = false;
     int fmt64 = STAG_LINKS_F64_18;  // storage used by the FP64 operator
+    // Naik-improved operator: weights and long links (derived like the copies above)
+    int naik = 0;
+    double naik_c1 = 1.0, naik_c3 = 0.0;
+    double2* long_d18 = nullptr;
+    double2* long_d12 = nullptr;
+    float2* long_s18 = nullptr;
+    void* long_h12 = nullptr;
+    bool long_ok = false, long_d12_ok = false, long_s18_ok = false, long_h12_ok = false;
     double* mom = nullptr;
     double* mom_tmp = nullptr;   // force staging when a trajectory records training pairs
     double* mom_aux = nullptr;   // truncated-solve force fed to a learned model
@@ -63,6 +71,7 @@ struct stag_ctx {
     size_t prof_used = 0;
     double prof_ms[3] = {0, 0, 0};       // D_oe, D_eo + CG epilogue, multi-shift step
     long prof_cnt[3] = {0, 0, 0};
+    std::vector<float> prof_samples[3];  // every recorded launch's milliseconds
     std::string err;
     int last_iters = 0;
 };
@@ -96,7 +105,10 @@ stag_status ensure_pool(stag_ctx* c, int n);
 stag_status ensure_fp32_workspace(stag_ctx* c);
 // the link copies needed by the FP64 operator and (fmt32 >= 0) the FP32 one, refreshed if stale
 stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls);
-inline void links_changed(stag_ctx* c) { c->d12_ok = c->s18_ok = c->h12_ok = false; }
+inline void links_changed(stag_ctx* c) {
+    c->d12_ok = c->s18_ok = c->h12_ok = false;
+    c->long_ok = c->long_d12_ok = c->long_s18_ok = c->long_h12_ok = false;
+}
 
 struct SolveResult {
     int iters = 0;

@@ -6,7 +6,10 @@
 namespace stag {
 
 // The operator's link copies.  d18 is the master FP64 field; the others are
-// derived from it (rows 0-1 only for the 12-real formats).
+// derived from it (rows 0-1 only for the 12-real formats).  With naik set the
+// operator is the improved one: weights c1 (one hop) and c3 (three hops), and
+// the long links L_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu) in the same formats
+// and layouts (ld18 ... lh12).
 struct LinkSet {
     int fmt64;               // STAG_LINKS_F64_18 or STAG_LINKS_F64_12
     int fmt32;               // STAG_LINKS_F32_18 or STAG_LINKS_F16_12
@@ -14,6 +17,13 @@ struct LinkSet {
     const double2* d12;
     const float2* s18;
     const void* h12;         // __half2 [2][4][6][Vh]
+    int naik;
+    int pad_;                // keeps the struct free of implicit padding (graph keys compare bytes)
+    double c1, c3;
+    const double2* ld18;
+    const double2* ld12;
+    const float2* ls18;
+    const void* lh12;
 };
 
 int dslash_grid(const Geom& g, int tps);
@@ -39,7 +49,10 @@ void launch_dslash32_cg(const Geom& g, const LinkSet& ls, const float2* w_o, con
 void launch_dslash32_axpy(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* in, double c,
                           float2* out, int tps, hipStream_t s);
 
-// link copies derived from the FP64 master field
+// long links L_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu) (plain SU(3) products,
+// no staggered signs) in the layout of the FP64 18-real links
+void launch_long_links(const Geom& g, const double2* d18, double2* long18, hipStream_t s);
+// link copies derived from an FP64 18-real field (the links or the long links)
 void launch_links_to_d12(const Geom& g, const double2* d18, double2* d12, hipStream_t s);
 void launch_links_to_s18(const Geom& g, const double2* d18, float2* s18, hipStream_t s);
 void launch_links_to_h12(const Geom& g, const double2* d18, void* h12, hipStream_t s);

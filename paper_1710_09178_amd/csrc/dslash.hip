@@ -1,6 +1,10 @@
 // Even-odd staggered hopping operator (Sec. 3.2):
 //   (D psi)(x) = sum_mu s_mu(x) U_mu(x) psi(x+mu) - s_mu(x-mu) U_mu(x-mu)^dag psi(x-mu)
 // for output sites of one parity, with fused epilogues for the solvers.
+// The Naik-improved operator (the "improved" quarks of the Summary, Sec. 8)
+// weights that sum by c1 and adds c3 times the same stencil at distance 3,
+// with the three-link products L_mu(x) = U_mu(x) U_mu(x+mu) U_mu(x+2mu)
+// ("long links", built once per gauge field) in place of U.
 //
 // Work decomposition: a 256-thread block owns SB = 256/TPS consecutive output
 // sites (after the XCD-aware tile remap).  Each 64-lane wave takes one "slice"
@@ -111,6 +115,84 @@ __device__ __forceinline__ void hop_geometry(const Geom& g, int mu, int x, int y
     }
 }
 
+// Neighbours at distance 3 and the signs of the three-link paths to them.
+// eta_mu does not depend on x_mu, so a path carries eta_mu(x) once; each of
+// its links that leaves the last time slice adds a factor -1: the forward
+// path from t crosses floor((t+3)/Nt) times, the backward path (from t-3 to
+// t) 3 - floor((t-3+3Nt)/Nt) times, for any even Nt >= 2.
+__device__ __forceinline__ int wrap_p3(int v, int n) {
+    v += 3;
+    v -= (v >= n) ? n : 0;
+    v -= (v >= n) ? n : 0;
+    return v;
+}
+__device__ __forceinline__ int wrap_m3(int v, int n) {
+    v -= 3;
+    v += (v < 0) ? n : 0;
+    v += (v < 0) ? n : 0;
+    return v;
+}
+__device__ __forceinline__ void hop3_geometry(const Geom& g, int mu, int x, int y, int z, int t, int& cbf,
+                                              int& cbb, bool& nf, bool& nb) {
+    if (mu == 0) {
+        cbf = cb_index(g, wrap_p3(x, g.nx), y, z, t);
+        cbb = cb_index(g, wrap_m3(x, g.nx), y, z, t);
+        nf = nb = false;
+    } else if (mu == 1) {
+        cbf = cb_index(g, x, wrap_p3(y, g.ny), z, t);
+        cbb = cb_index(g, x, wrap_m3(y, g.ny), z, t);
+        nf = nb = (x & 1);
+    } else if (mu == 2) {
+        cbf = cb_index(g, x, y, wrap_p3(z, g.nz), t);
+        cbb = cb_index(g, x, y, wrap_m3(z, g.nz), t);
+        nf = nb = ((x + y) & 1);
+    } else {
+        cbf = cb_index(g, x, y, z, wrap_p3(t, g.nt));
+        cbb = cb_index(g, x, y, z, wrap_m3(t, g.nt));
+        const bool eta = ((x + y + z) & 1);
+        nf = eta ^ (((t + 3) / g.nt) & 1);
+        nb = eta ^ ((3 - (t - 3 + 3 * g.nt) / g.nt) & 1);
+    }
+}
+
+// acc += wf * U psi_f - wb * U'^dag psi_b for one direction: U is the link
+// (or long link) leaving the output site (parity out_par, index cb), U' the
+// one arriving from the backward neighbour cbb (which also indexes psi_b).
+template <class Link>
+__device__ __forceinline__ void hop_w(const Geom& g, const Link& L, const typename Link::C* __restrict__ in,
+                                      int out_par, int mu, int cb, int cbf, int cbb, typename Link::R wf,
+                                      typename Link::R wb, typename Link::C (&acc)[3]) {
+    using C = typename Link::C;
+    C U[9], W[9], pf[3], pb[3];
+    L.load(g, out_par, mu, cb, U);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pf[c] = in[(size_t)c * g.vh + cbf];
+    L.load(g, 1 - out_par, mu, cbb, W);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pb[c] = in[(size_t)c * g.vh + cbb];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        C f = cmul(U[3 * a], pf[0]);
+        f = cadd(f, cmul(U[3 * a + 1], pf[1]));
+        f = cadd(f, cmul(U[3 * a + 2], pf[2]));
+        C b = cmulc(W[a], pb[0]);
+        b = cadd(b, cmulc(W[3 + a], pb[1]));
+        b = cadd(b, cmulc(W[6 + a], pb[2]));
+        acc[a].x += wf * f.x - wb * b.x;
+        acc[a].y += wf * f.y - wb * b.y;
+    }
+}
+
+// The improved operator: one-hop links and long links in the same storage
+// format, and the weights of the two stencils.
+template <class Link>
+struct NaikOp {
+    using C = typename Link::C;
+    using R = typename Link::R;
+    Link one, three;
+    double c1, c3;
+};
+
 // acc += sf * U psi_f - sb * U'^dag psi_b for one direction
 template <class Link>
 __device__ __forceinline__ void hop(const Geom& g, const Link& L, const typename Link::C* __restrict__ in, int out_par,
@@ -140,6 +222,20 @@ __device__ __forceinline__ void hop(const Geom& g, const Link& L, const typename
         acc[a].x += sf * f.x - sb * b.x;
         acc[a].y += sf * f.y - sb * b.y;
     }
+}
+
+template <class Link>
+__device__ __forceinline__ void hop(const Geom& g, const NaikOp<Link>& op, const typename Link::C* __restrict__ in,
+                                    int out_par, int mu, int cb, int x, int y, int z, int t,
+                                    typename Link::C (&acc)[3]) {
+    using R = typename Link::R;
+    int cbf, cbb;
+    bool nf, nb;
+    hop_geometry(g, mu, x, y, z, t, cbf, cbb, nf, nb);
+    const R c1 = (R)op.c1, c3 = (R)op.c3;
+    hop_w(g, op.one, in, out_par, mu, cb, cbf, cbb, nf ? -c1 : c1, nb ? -c1 : c1, acc);
+    hop3_geometry(g, mu, x, y, z, t, cbf, cbb, nf, nb);
+    hop_w(g, op.three, in, out_par, mu, cb, cbf, cbb, nf ? -c3 : c3, nb ? -c3 : c3, acc);
 }
 
 // ---- epilogues: called once per (colour, site) item with the hopping sum v
@@ -272,20 +368,32 @@ void launch_tps(const Geom& g, const Link& L, const typename Link::C* in, int ou
     }
 }
 
-// dispatch on the storage format of the operator
+// dispatch on the storage format of the operator and on the improvement
 template <class Fn>
 void with_link64(const LinkSet& ls, Fn fn) {
-    if (ls.fmt64 == STAG_LINKS_F64_12)
+    if (ls.naik) {
+        if (ls.fmt64 == STAG_LINKS_F64_12)
+            fn(NaikOp<LinkD12>{LinkD12{ls.d12}, LinkD12{ls.ld12}, ls.c1, ls.c3});
+        else
+            fn(NaikOp<LinkD18>{LinkD18{ls.d18}, LinkD18{ls.ld18}, ls.c1, ls.c3});
+    } else if (ls.fmt64 == STAG_LINKS_F64_12) {
         fn(LinkD12{ls.d12});
-    else
+    } else {
         fn(LinkD18{ls.d18});
+    }
 }
 template <class Fn>
 void with_link32(const LinkSet& ls, Fn fn) {
-    if (ls.fmt32 == STAG_LINKS_F16_12)
+    if (ls.naik) {
+        if (ls.fmt32 == STAG_LINKS_F16_12)
+            fn(NaikOp<LinkH12>{LinkH12{(const __half2*)ls.h12}, LinkH12{(const __half2*)ls.lh12}, ls.c1, ls.c3});
+        else
+            fn(NaikOp<LinkS18>{LinkS18{ls.s18}, LinkS18{ls.ls18}, ls.c1, ls.c3});
+    } else if (ls.fmt32 == STAG_LINKS_F16_12) {
         fn(LinkH12{(const __half2*)ls.h12});
-    else
+    } else {
         fn(LinkS18{ls.s18});
+    }
 }
 
 }  // namespace

@@ -120,6 +120,32 @@ __global__ void k_links_to_h12(Geom g, const double2* __restrict__ d18, __half2*
     }
 }
 
+// Long links: one thread per (parity, mu, site); the three factors sit on
+// parities par, 1 - par, par.
+__global__ void k_long_links(Geom g, const double2* __restrict__ d18, double2* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 8 * g.vh) return;
+    const int pm = i / g.vh, cb = i % g.vh;
+    const int par = pm >> 2, mu = pm & 3;
+    int c[4];
+    cb_coords(g, par, cb, c[0], c[1], c[2], c[3]);
+    const int n[4] = {g.nx, g.ny, g.nz, g.nt};
+    M3 acc, u;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) acc.e[e] = d18[link_off(g, par, mu, e) + cb];
+#pragma unroll
+    for (int k = 1; k <= 2; ++k) {
+        c[mu] = (c[mu] + 1 == n[mu]) ? 0 : c[mu] + 1;
+        const int cbk = cb_index(g, c[0], c[1], c[2], c[3]);
+        const int pk = par ^ (k & 1);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u.e[e] = d18[link_off(g, pk, mu, e) + cbk];
+        acc = m3_mul(acc, u);
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) out[link_off(g, par, mu, e) + cb] = acc.e[e];
+}
+
 __global__ void k_axpy_real(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         y[i] += a * x[i];
@@ -161,6 +187,9 @@ void launch_mom_to_internal(const Geom& g, const double* canon, double* mom, int
 void launch_mom_to_canon(const Geom& g, const double* mom, double* canon, hipStream_t s) {
     const size_t n = (size_t)8 * g.vh;
     k_mom_to_canon<<<blocks_for(n), 256, 0, s>>>(g, mom, canon);
+}
+void launch_long_links(const Geom& g, const double2* d18, double2* long18, hipStream_t s) {
+    k_long_links<<<blocks_for((size_t)8 * g.vh), 256, 0, s>>>(g, d18, long18);
 }
 void launch_links_to_d12(const Geom& g, const double2* d18, double2* d12, hipStream_t s) {
     k_links_to_d12<<<blocks_for((size_t)8 * g.vh), 256, 0, s>>>(g, d18, d12);

@@ -31,7 +31,10 @@ stag_status ensure_pool(stag_ctx* c, int n) {
 stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls) {
     const Geom& g = c->g;
     const size_t l12 = (size_t)48 * g.vh;  // complex entries of a 12-real field
-    ls = LinkSet{c->fmt64, fmt32 < 0 ? STAG_LINKS_F32_18 : fmt32, c->links, nullptr, nullptr, nullptr};
+    std::memset(&ls, 0, sizeof(ls));
+    ls.fmt64 = c->fmt64;
+    ls.fmt32 = fmt32 < 0 ? STAG_LINKS_F32_18 : fmt32;
+    ls.d18 = c->links;
     stag_status e;
     if (c->fmt64 == STAG_LINKS_F64_12) {
         if (!c->links_d12 && (e = dmalloc(c, &c->links_d12, l12 * sizeof(double2)))) return e;
@@ -49,6 +52,32 @@ stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls) {
         if (!c->h12_ok) launch_links_to_h12(g, c->links, c->links_h12, c->s);
         c->h12_ok = true;
         ls.h12 = c->links_h12;
+    }
+    if (!c->naik) return STAG_OK;
+    // improved operator: long links from the master field, then their copies
+    ls.naik = 1;
+    ls.c1 = c->naik_c1;
+    ls.c3 = c->naik_c3;
+    if (!c->long_d18 && (e = dmalloc(c, &c->long_d18, (size_t)72 * g.vh * sizeof(double2)))) return e;
+    if (!c->long_ok) launch_long_links(g, c->links, c->long_d18, c->s);
+    c->long_ok = true;
+    ls.ld18 = c->long_d18;
+    if (c->fmt64 == STAG_LINKS_F64_12) {
+        if (!c->long_d12 && (e = dmalloc(c, &c->long_d12, l12 * sizeof(double2)))) return e;
+        if (!c->long_d12_ok) launch_links_to_d12(g, c->long_d18, c->long_d12, c->s);
+        c->long_d12_ok = true;
+        ls.ld12 = c->long_d12;
+    }
+    if (fmt32 == STAG_LINKS_F32_18) {
+        if (!c->long_s18 && (e = dmalloc(c, &c->long_s18, (size_t)72 * g.vh * sizeof(float2)))) return e;
+        if (!c->long_s18_ok) launch_links_to_s18(g, c->long_d18, c->long_s18, c->s);
+        c->long_s18_ok = true;
+        ls.ls18 = c->long_s18;
+    } else if (fmt32 == STAG_LINKS_F16_12) {
+        if (!c->long_h12 && (e = dmalloc(c, &c->long_h12, l12 * 4))) return e;
+        if (!c->long_h12_ok) launch_links_to_h12(g, c->long_d18, c->long_h12, c->s);
+        c->long_h12_ok = true;
+        ls.lh12 = c->long_h12;
     }
     return STAG_OK;
 }
@@ -81,6 +110,7 @@ void prof_collect(stag_ctx* c, const EvRec& rec, int iters) {
         if (hipEventElapsedTime(&ms, q.first.first, q.first.second) == hipSuccess) {
             c->prof_ms[kind] += ms;
             c->prof_cnt[kind] += 1;
+            c->prof_samples[kind].push_back(ms);
         }
     }
 }

@@ -121,6 +121,8 @@ def load_library() -> ctypes.CDLL:
         "stag_multishift_solve_mixed": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(P), P,
                                             ctypes.POINTER(CMixedOpts), ctypes.POINTER(CSolveInfo)]),
         "stag_set_link_format": (S, [H, I]),
+        "stag_set_naik": (S, [H, D, D]),
+        "stag_profile_samples": (S, [H, I, ctypes.POINTER(ctypes.c_float), I, ctypes.POINTER(I)]),
         "stag_fermion_action": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(D),
                                     ctypes.POINTER(CSolveInfo)]),
         "stag_fermion_force": (S, [H, D, ctypes.POINTER(CRational), D, I, P, P, D, ctypes.POINTER(CSolveInfo)]),
@@ -373,6 +375,10 @@ class Lattice:
     def set_link_format(self, fmt: int):
         self._check(self.lib.stag_set_link_format(self.h, int(fmt)))
 
+    def set_naik(self, c1: float = 9.0 / 8.0, c3: float = -1.0 / 24.0):
+        """Naik-improved operator with weights (c1, c3); (1, 0) restores the one-hop operator."""
+        self._check(self.lib.stag_set_naik(self.h, float(c1), float(c3)))
+
     def fermion_action(self, mass, rat, tol, maxiter, phi) -> float:
         r = RationalArg(rat)
         S = ctypes.c_double()
@@ -457,6 +463,14 @@ class Lattice:
         cnt = (ctypes.c_long * 3)()
         self._check(self.lib.stag_profile_read(self.h, ms, cnt))
         return list(ms), list(cnt)
+
+    def profile_samples(self, kind: int) -> np.ndarray:
+        """Recorded launch durations (microseconds) of one kind: 0 D_oe, 1 D_eo, 2 shift update."""
+        n = ctypes.c_int()
+        self._check(self.lib.stag_profile_samples(self.h, int(kind), None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_float * max(n.value, 1))()
+        self._check(self.lib.stag_profile_samples(self.h, int(kind), buf, n.value, ctypes.byref(n)))
+        return np.array(buf[:n.value], dtype=np.float64)
 
     def tune(self, tps: int, chunk: int):
         self._check(self.lib.stag_tune(self.h, int(tps), int(chunk)))

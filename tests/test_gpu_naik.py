@@ -1,0 +1,240 @@
+"""GPU parity of the Naik-improved operator (Sec. 8 Summary, improved quarks;
+reading: c1 = 9/8 one-hop plus c3 = -1/24 three-hop paths) against the
+oracle's path definition: D_oe / D_eo and A element by element over several
+tiles, ragged tails, lattices on which the three-hop wraps onto itself, every
+work split and both FP64 link formats; solves against the oracle's solver on
+the improved A; the sloppy formats within their roundoff bounds."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, naik
+from oracle import lattice as L
+from oracle.solvers import multishift_cg, true_residuals
+from paper_1710_09178_amd import stag
+from tests.gpu_util import dev, host, lattice, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((4, 4, 4, 4), 0.3),      # three hops forward = one hop backward, along a different path
+    ((2, 2, 2, 2), 0.5),      # every three-hop path returns to the neighbour
+    ((8, 6, 4, 10), 0.4),     # Vh = 960: several tiles and a ragged tail
+    ((6, 2, 8, 4), 1.0),      # strongly disordered links
+    ((16, 16, 16, 8), 0.2),   # z-slab tile map
+]
+
+
+def _naik_lattice(dims, U, fmt=stag.LINKS_F64_18):
+    lat = lattice(dims, U)
+    lat.set_link_format(fmt)
+    lat.set_naik(naik.C1, naik.C3)
+    return lat
+
+
+@pytest.mark.parametrize("dims,eps", CASES)
+@pytest.mark.parametrize("tps", [1, 2, 4])
+@pytest.mark.parametrize("fmt", [stag.LINKS_F64_18, stag.LINKS_F64_12])
+def test_naik_dslash_matches_oracle(dims, eps, tps, fmt):
+    log(f"naik dslash parity dims={dims} eps={eps} tps={tps} fmt={fmt}")
+    rng = synth.make_rng(920, hash(dims) % 1000)
+    U = synth.random_su3_near_identity(dims, eps, rng)
+    lat = _naik_lattice(dims, U, fmt)
+    lat.tune(tps, 16)
+    for out_par in (1, 0):
+        vin = synth.gaussian_half_vector(dims, rng)
+        y = lat.new_vec()
+        lat.dslash(y, lat.vec_import(dev(vin), 1 - out_par), out_par)
+        got = host(lat.vec_export(y, out_par))
+        exp = naik.dslash_half(U, vin, dims, out_par)
+        assert rel_err(got, exp) < 2e-14, (out_par, rel_err(got, exp))
+
+
+@pytest.mark.parametrize("dims,eps", CASES[:3])
+def test_naik_mdagm_matches_oracle(dims, eps):
+    log(f"naik A parity dims={dims}")
+    rng = synth.make_rng(921, 0)
+    U = synth.random_su3_near_identity(dims, eps, rng)
+    lat = _naik_lattice(dims, U)
+    vin = synth.gaussian_half_vector(dims, rng)
+    y = lat.new_vec()
+    lat.mdagm(y, lat.vec_import(dev(vin), 0), 0.1)
+    assert rel_err(host(lat.vec_export(y, 0)), naik.apply_A(U, vin, dims, 0.1)) < 2e-14
+
+
+@pytest.mark.parametrize("fmt", [stag.LINKS_F64_18, stag.LINKS_F64_12])
+def test_naik_full_size_32c8(fmt):
+    """32^3x8, eps = 0.2, the launch configuration the benchmark times: every
+    output element of D_oe and D_eo."""
+    dims = (32, 32, 32, 8)
+    log(f"naik dslash parity at 32^3x8 fmt={fmt}")
+    rng = synth.make_rng(922, fmt)
+    U = synth.random_su3_near_identity(dims, 0.2, rng)
+    lat = _naik_lattice(dims, U, fmt)
+    for out_par in (1, 0):
+        vin = synth.gaussian_half_vector(dims, rng)
+        y = lat.new_vec()
+        lat.dslash(y, lat.vec_import(dev(vin), 1 - out_par), out_par)
+        got = host(lat.vec_export(y, out_par))
+        assert rel_err(got, naik.dslash_half(U, vin, dims, out_par)) < 2e-14
+
+
+def test_long_links_follow_the_gauge_field():
+    """A new gauge field (set_gauge) and a link update both rebuild the long
+    links before the next operator call."""
+    dims = (8, 6, 4, 10)
+    rng = synth.make_rng(923, 0)
+    U1 = synth.random_su3_near_identity(dims, 0.4, rng)
+    U2 = synth.random_su3_near_identity(dims, 0.4, rng)
+    lat = _naik_lattice(dims, U1)
+    vin = synth.gaussian_half_vector(dims, rng)
+    x = lat.vec_import(dev(vin), 0)
+    y = lat.new_vec()
+    lat.dslash(y, x, 1)
+    assert rel_err(host(lat.vec_export(y, 1)), naik.dslash_half(U1, vin, dims, 1)) < 2e-14
+    lat.set_gauge(dev(U2))
+    lat.dslash(y, x, 1)
+    assert rel_err(host(lat.vec_export(y, 1)), naik.dslash_half(U2, vin, dims, 1)) < 2e-14
+    mom = lat.random_momentum(5, 0)
+    lat.link_update(mom, 0.05)
+    U3 = host(lat.get_gauge())
+    lat.dslash(y, x, 1)
+    assert rel_err(host(lat.vec_export(y, 1)), naik.dslash_half(U3, vin, dims, 1)) < 2e-14
+
+
+def test_naik_off_restores_the_one_hop_operator():
+    dims = (8, 6, 4, 10)
+    rng = synth.make_rng(924, 0)
+    U = synth.random_su3_near_identity(dims, 0.4, rng)
+    lat = _naik_lattice(dims, U)
+    vin = synth.gaussian_half_vector(dims, rng)
+    x = lat.vec_import(dev(vin), 0)
+    y = lat.new_vec()
+    lat.set_naik(1.0, 0.0)
+    lat.dslash(y, x, 1)
+    plain = lattice(dims, U)
+    y2 = plain.new_vec()
+    plain.dslash(y2, plain.vec_import(dev(vin), 0), 1)
+    assert np.array_equal(host(y), host(y2))
+    # other weights: the operator is linear in (c1, c3)
+    lat.set_naik(0.0, 1.0)
+    lat.dslash(y, x, 1)
+    exp = naik.dslash_half(U, vin, dims, 1, c1=0.0, c3=1.0)
+    assert rel_err(host(lat.vec_export(y, 1)), exp) < 2e-14
+
+
+def test_naik_force_and_trajectory_are_rejected():
+    dims = (4, 4, 4, 4)
+    rng = synth.make_rng(925, 0)
+    U = synth.random_su3_near_identity(dims, 0.3, rng)
+    lat = _naik_lattice(dims, U)
+    phi = lat.vec_import(dev(synth.gaussian_half_vector(dims, rng)), 0)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    with pytest.raises(stag.StagError) as ei:
+        lat.fermion_force(0.1, rat, 1e-10, 1000, phi, lat.new_mom())
+    assert ei.value.code == stag.STAG_ERR_INVALID_ARG
+
+
+def test_naik_multishift_matches_oracle():
+    """8 poles, ragged lattice: every solution within 2 tol kappa_k of the
+    oracle's solve of the improved A, true residuals (oracle operator) below tol."""
+    dims = (8, 6, 4, 10)
+    mass, tol = 0.1, 1e-10
+    log("naik multi-shift solve 8x6x4x10")
+    rng = synth.make_rng(926, 0)
+    U = synth.random_su3_near_identity(dims, 0.4, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    poles = list(np.logspace(-4, 0, 8))
+    lat = _naik_lattice(dims, U)
+    xs = [lat.new_vec() for _ in poles]
+    info = lat.multishift_solve(mass, {"c0": 0.0, "pole": poles, "residue": [1.0] * 8}, tol, 10000,
+                                lat.vec_import(dev(b), 0), xs)
+    A = lambda v: naik.apply_A(U, v, dims, mass)  # noqa: E731
+    ref = multishift_cg(A, b, poles, tol)
+    got = [host(lat.vec_export(x, 0)) for x in xs]
+    res = true_residuals(A, b, poles, got)
+    assert max(res) < tol, res
+    lam_max = 4 * mass * mass + (8 * (naik.C1 - naik.C3)) ** 2
+    for g, xr, s in zip(got, ref["x"], poles):
+        kappa = (lam_max + s) / (4 * mass * mass + s)
+        assert np.linalg.norm(g - xr) <= 2 * tol * kappa * np.linalg.norm(xr)
+    log(f"  {info['iters']} iterations (oracle {ref['iters']}), max true residual {max(res):.2e}")
+
+
+def test_naik_solve_32c8():
+    """The 12-pole x^(-1/4) solve of the 32^3x8 workload with the improved
+    operator: every pole's true residual, computed with the oracle's operator
+    on the GPU solutions, below 1e-10."""
+    dims = (32, 32, 32, 8)
+    mass, tol = 0.005, 1e-10
+    log("naik 12-pole solve at 32^3x8")
+    rng = synth.make_rng(927, 0)
+    U = synth.random_su3_near_identity(dims, 0.2, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm025_n12_m0.005")
+    lat = _naik_lattice(dims, U)
+    xs = [lat.new_vec() for _ in rat["pole"]]
+    info = lat.multishift_solve(mass, rat, tol, 100000, lat.vec_import(dev(b), 0), xs)
+    got = [host(lat.vec_export(x, 0)) for x in xs]
+    res = true_residuals(lambda v: naik.apply_A(U, v, dims, mass), b, rat["pole"], got)
+    log(f"  {info['iters']} iterations, true residuals (oracle operator) max {max(res):.2e}, "
+        f"GPU's own max {max(info['true_resid']):.2e}")
+    assert max(res) < tol
+
+
+def test_naik_mixed_solve_reaches_fp64_residual():
+    dims = (8, 6, 4, 10)
+    mass, tol = 0.05, 1e-10
+    rng = synth.make_rng(928, 0)
+    U = synth.random_su3_near_identity(dims, 0.4, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    poles = list(np.logspace(-4, 0, 8))
+    lat = _naik_lattice(dims, U)
+    xs = [lat.new_vec() for _ in poles]
+    lat.multishift_solve_mixed(mass, {"c0": 0.0, "pole": poles, "residue": [1.0] * 8}, tol, 100000,
+                               lat.vec_import(dev(b), 0), xs, sloppy=stag.LINKS_F32_18)
+    got = [host(lat.vec_export(x, 0)) for x in xs]
+    res = true_residuals(lambda v: naik.apply_A(U, v, dims, mass), b, poles, got)
+    assert max(res) < tol, res
+
+
+# ---- sloppy formats: roundoff bounds as for the one-hop operator, with the
+# weighted neighbour sums c1 P1(x) + |c3| P3(x) and up to 96 + 4 rounded
+# products per output real part
+U32, U16 = 2.0 ** -24, 2.0 ** -11
+BOUND_COEF = {stag.LINKS_F32_18: 100 * U32, stag.LINKS_F16_12: 2.1 * U16 * np.sqrt(2) + 100 * U32}
+
+
+def _shift3(a, mu, d):
+    for _ in range(3):
+        a = L.fwd(a, mu) if d > 0 else L.bwd(a, mu)
+    return a
+
+
+def _weighted_neighbour_sum(v_half, dims, in_par):
+    s = np.abs(v_half.real).sum(-1) + np.abs(v_half.imag).sum(-1)
+    full = L.half_to_full(s[:, None], dims, in_par)[..., 0]
+    p1 = sum(L.fwd(full, mu) + L.bwd(full, mu) for mu in range(4))
+    p3 = sum(_shift3(full, mu, 1) + _shift3(full, mu, -1) for mu in range(4))
+    tot = naik.C1 * p1 + abs(naik.C3) * p3
+    return L.full_to_half(tot[..., None], dims, 1 - in_par)[:, 0]
+
+
+@pytest.mark.parametrize("sloppy", [stag.LINKS_F32_18, stag.LINKS_F16_12])
+def test_naik_sloppy_dslash_32c8(sloppy):
+    dims = (32, 32, 32, 8)
+    log(f"naik sloppy Dslash at 32^3x8 format={sloppy}")
+    rng = synth.make_rng(929, sloppy)
+    U = synth.random_su3_near_identity(dims, 0.2, rng)
+    lat = _naik_lattice(dims, U)
+    for out_par in (1, 0):
+        vin = synth.gaussian_half_vector(dims, rng)
+        y = lat.new_vec()
+        lat.dslash_sloppy(y, lat.vec_import(dev(vin), 1 - out_par), out_par, sloppy)
+        got = host(lat.vec_export(y, out_par))
+        exp = naik.dslash_half(U, vin, dims, out_par)
+        P = _weighted_neighbour_sum(vin, dims, 1 - out_par)[:, None]
+        err = np.maximum(np.abs(got.real - exp.real), np.abs(got.imag - exp.imag))
+        ratio = err / (BOUND_COEF[sloppy] * P)
+        log(f"  out parity {out_par}: relative (max norm) {rel_err(got, exp):.3e}, max err / bound {ratio.max():.3f}")
+        assert ratio.max() <= 1.0
