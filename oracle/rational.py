@@ -40,6 +40,7 @@ class Rational:
     pole: list
     error: float                      # max relative error on [lo, hi]
     reference: list = field(default_factory=list)  # alternation points
+    c0_zero: bool = False             # type (n - 1, n): c0 = 0, 2n + 1 alternation points
 
     @property
     def n(self) -> int:
@@ -55,12 +56,12 @@ class Rational:
     def to_json(self) -> dict:
         return {"power": self.power, "lo": self.lo, "hi": self.hi, "n": self.n,
                 "c0": self.c0, "residue": list(self.residue), "pole": list(self.pole),
-                "error": self.error, "reference": list(self.reference)}
+                "error": self.error, "reference": list(self.reference), "c0_zero": self.c0_zero}
 
     @staticmethod
     def from_json(d: dict) -> "Rational":
         return Rational(d["power"], d["lo"], d["hi"], d["c0"], list(d["residue"]),
-                        list(d["pole"]), d["error"], list(d.get("reference", [])))
+                        list(d["pole"]), d["error"], list(d.get("reference", [])), bool(d.get("c0_zero", False)))
 
 
 def _horner(coef, y):
@@ -71,10 +72,14 @@ def _horner(coef, y):
 
 
 class _Remez:
-    def __init__(self, p, a_scaled, n):
+    """Type (nd, n) with nd = n (the paper's form with c_0) or nd = n - 1
+    (the Appendix's alternative whose constant term vanishes)."""
+
+    def __init__(self, p, a_scaled, n, nd=None):
         self.p = mp.mpf(p)
         self.a = mp.mpf(a_scaled)
         self.n = n
+        self.nd = n if nd is None else nd
 
     def f(self, y):
         return mp.power(y, self.p)
@@ -87,10 +92,11 @@ class _Remez:
         on the reference.  Linearised passes (E*Q taken from the previous
         pass) give a starting point close to the wanted root; Newton's method on the full nonlinear
         system P(y_j) - f_j (1 + (-1)^j E) Q(y_j) = 0 then converges quadratically."""
-        n = self.n
-        m = 2 * n + 2
+        n, nd = self.n, self.nd
+        m = nd + n + 2            # unknowns: nd + 1 of P, n of Q (Q(0) = 1), E
+        iq, ie = nd + 1, nd + n + 1   # first Q column, E column
         fj = [self.f(y) for y in ref]
-        pw = [[y ** i for i in range(n + 1)] for y in ref]
+        pw = [[y ** i for i in range(max(n, nd) + 1)] for y in ref]
         sg = [(-1) ** j for j in range(m)]
         qprev = [mp.mpf(1)]
         E_prev = None
@@ -98,41 +104,41 @@ class _Remez:
             A = mp.matrix(m, m)
             rhs = mp.matrix(m, 1)
             for j in range(m):
-                for i in range(n + 1):
+                for i in range(nd + 1):
                     A[j, i] = pw[j][i]
-                    if i >= 1:
-                        A[j, n + i] = -fj[j] * pw[j][i]
-                A[j, 2 * n + 1] = -sg[j] * fj[j] * _horner(qprev, ref[j])
+                for i in range(1, n + 1):
+                    A[j, iq + i - 1] = -fj[j] * pw[j][i]
+                A[j, ie] = -sg[j] * fj[j] * _horner(qprev, ref[j])
                 rhs[j] = fj[j]
             sol = mp.lu_solve(A, rhs)
-            qprev = [mp.mpf(1)] + [sol[n + i] for i in range(1, n + 1)]
-            E_new = sol[2 * n + 1]
+            qprev = [mp.mpf(1)] + [sol[iq + i] for i in range(n)]
+            E_new = sol[ie]
             if E_prev is not None and abs(E_new - E_prev) <= mp.mpf(1e-5) * abs(E_new):
                 break
             E_prev = E_new
         v = [sol[k] for k in range(m)]
         for _ in range(30):
-            pc = v[:n + 1]
-            qc = [mp.mpf(1)] + v[n + 1:2 * n + 1]
-            E = v[2 * n + 1]
+            pc = v[:nd + 1]
+            qc = [mp.mpf(1)] + v[iq:ie]
+            E = v[ie]
             J = mp.matrix(m, m)
             F = mp.matrix(m, 1)
             for j in range(m):
                 w = fj[j] * (1 + sg[j] * E)
                 qv = _horner(qc, ref[j])
                 F[j] = _horner(pc, ref[j]) - w * qv
-                for i in range(n + 1):
+                for i in range(nd + 1):
                     J[j, i] = pw[j][i]
-                    if i >= 1:
-                        J[j, n + i] = -w * pw[j][i]
-                J[j, 2 * n + 1] = -sg[j] * fj[j] * qv
+                for i in range(1, n + 1):
+                    J[j, iq + i - 1] = -w * pw[j][i]
+                J[j, ie] = -sg[j] * fj[j] * qv
             dv = mp.lu_solve(J, F)
             v = [v[k] - dv[k] for k in range(m)]
             if abs(dv[m - 1]) <= abs(v[m - 1]) * mp.mpf(10) ** (-30):
                 break
-        pc = v[:n + 1]
-        qc = [mp.mpf(1)] + v[n + 1:2 * n + 1]
-        return pc, qc, v[2 * n + 1]
+        pc = v[:nd + 1]
+        qc = [mp.mpf(1)] + v[iq:ie]
+        return pc, qc, v[ie]
 
     def _zero(self, pc, qc, lo, hi):
         elo = self.err(pc, qc, lo)
@@ -212,8 +218,12 @@ def _roots_negative_axis(qc, lo, hi, count):
 
 
 def remez(power: float, lo: float, hi: float, n: int, rel_tol: float = 1e-8,
-          max_iter: int = 60, verbose: bool = False) -> Rational:
-    """Best relative (n, n) rational approximation to x^power on [lo, hi]."""
+          max_iter: int = 60, verbose: bool = False, c0_zero: bool = False) -> Rational:
+    """Best relative (n, n) rational approximation to x^power on [lo, hi];
+    with c0_zero the best (n - 1, n) one, whose partial fractions have no
+    constant term (the alternative of the Appendix, which reports that the
+    (n, n) form halves the error at the same number of shifts).  The error
+    equioscillates at 2n + 2 points, or 2n + 1 for the (n - 1, n) type."""
     if not (0 < lo < hi):
         raise ValueError("need 0 < lo < hi")
     if n < 1:
@@ -225,7 +235,8 @@ def remez(power: float, lo: float, hi: float, n: int, rel_tol: float = 1e-8,
         la = mp.log(a)
         ref = None
         for deg in range(1, n + 1):
-            m = 2 * deg + 2
+            ndeg = deg - 1 if c0_zero else deg
+            m = ndeg + deg + 2
             if ref is None:
                 ref = [mp.exp(la * (1 + mp.cos(mp.pi * j / (m - 1))) / 2) for j in range(m)]
                 ref = sorted(ref)
@@ -240,7 +251,7 @@ def remez(power: float, lo: float, hi: float, n: int, rel_tol: float = 1e-8,
                     w = mp.mpf((t - told[k]) / (told[k + 1] - told[k]))
                     ref.append(mp.exp(old[k] + w * (old[k + 1] - old[k])))
                 ref[0], ref[-1] = a, mp.mpf(1)
-            R = _Remez(power, a, deg)
+            R = _Remez(power, a, deg, ndeg)
             for it in range(max_iter):
                 pc, qc, E = R.solve(ref)
                 ref, vals = R.exchange(pc, qc, ref)
@@ -251,9 +262,19 @@ def remez(power: float, lo: float, hi: float, n: int, rel_tol: float = 1e-8,
                     break
             pc, qc, E = R.solve(ref)
         # partial fractions in the scaled variable, then undo the scaling
-        poles_y = _roots_negative_axis(qc, a * mp.mpf(10) ** -8, mp.mpf(10) ** 8, n)
+        if c0_zero:
+            # The (n - 1, n) form of a positive power puts one root of Q on the
+            # positive axis beyond the interval (a pole at a negative shift
+            # that stands in for the missing constant): take every root of Q
+            # (all real) from mpmath's polynomial solver.
+            roots = mp.polyroots(list(reversed(qc)), maxsteps=400, extraprec=4 * mp.mp.prec)
+            if any(abs(mp.im(z)) > mp.mpf(10) ** (-dps // 2) * abs(z) for z in roots):
+                raise RuntimeError("denominator has complex roots")
+            poles_y = [-mp.re(z) for z in roots]
+        else:
+            poles_y = _roots_negative_axis(qc, a * mp.mpf(10) ** -8, mp.mpf(10) ** 8, n)
         dq = [i * qc[i] for i in range(1, n + 1)]
-        c0_y = pc[n] / qc[n]
+        c0_y = mp.mpf(0) if c0_zero else pc[n] / qc[n]
         res_y = [_horner(pc, -d) / _horner(dq, -d) for d in poles_y]
         scale = mp.mpf(hi)
         pw = mp.mpf(power)
@@ -264,7 +285,7 @@ def remez(power: float, lo: float, hi: float, n: int, rel_tol: float = 1e-8,
         err = abs(E)
         return Rational(float(power), float(lo), float(hi), float(c0),
                         [float(residue[k]) for k in order], [float(pole[k]) for k in order],
-                        float(err), [float(y * scale) for y in ref])
+                        float(err), [float(y * scale) for y in ref], c0_zero)
 
 
 def relative_error(r: Rational, x: np.ndarray, power: float | None = None) -> np.ndarray:
