@@ -128,6 +128,21 @@ stag_status stag_mom_export(stag_handle h, double* canon_out, const void* in_int
 stag_status stag_dslash(stag_handle h, void* out, const void* in, int out_parity);
 /* out_even = A in_even = (4 m^2 - D_eo D_oe) in_even.  in and out must not overlap. */
 stag_status stag_mdagm(stag_handle h, void* out_even, const void* in_even, double mass);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operator as stag_mdagm, the same kernels and bitwise the same result, with
+ * the odd temporary D_oe in_even held in a library-owned static device array
+ * of 32 MiB per GPU (resolved by stag_create, kept until the process ends)
+ * instead of the handle's workspace.  Makes no hipMalloc/hipFree call: the
+ * link copies a 12-real format or the Naik improvement needs are allocated by
+ * stag_set_link_format / stag_set_naik (STAG_ERR_INVALID_ARG if missing).
+ * STAG_ERR_INVALID_ARG when the odd half vector (48 B x Vh) exceeds 32 MiB
+ * (Vh > 699050 sites), for NULL, misaligned or equal pointers or a non-finite
+ * mass; STAG_ERR_NO_GAUGE before stag_set_gauge.  All handles on one GPU share
+ * the array: calls that overlap in time on one GPU (different streams or
+ * threads) race on it; calls ordered on one stream do not.  Asynchronous like
+ * stag_mdagm. */
+stag_status stag_mdagm_noalloc(stag_handle h, void* out_even, const void* in_even, double mass);
 
 /* ---- multi-shift CG (Sec. 4, eq. ratapprx) ------------------------------- */
 

@@ -283,6 +283,7 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
         c->err = "pinned host allocation failed";
         return bail(STAG_ERR_OOM);
     }
+    if ((s = scratch_init(c))) return bail(s);
     launch_fill_zero(c->mom, mb, c->s);
     if (hipStreamSynchronize(c->s) != hipSuccess) {
         c->err = "initialisation kernels failed";

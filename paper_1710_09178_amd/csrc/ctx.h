@@ -101,6 +101,8 @@ inline size_t half_bytes(const Geom& g) { return (size_t)3 * g.vh * sizeof(doubl
 inline double2* pool_vec(double2* pool, const Geom& g, int k) { return pool + (size_t)k * 3 * g.vh; }
 
 stag_status ensure_pool(stag_ctx* c, int n);
+// device address of the allocation-free operator's scratch array on c's device
+stag_status scratch_init(stag_ctx* c);
 // FP32 Krylov vectors (ring of residuals, p, Ap, odd w), allocated on first use
 stag_status ensure_fp32_workspace(stag_ctx* c);
 // the link copies needed by the FP64 operator and (fmt32 >= 0) the FP32 one, refreshed if stale

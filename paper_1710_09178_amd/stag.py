@@ -123,6 +123,7 @@ def load_library() -> ctypes.CDLL:
         "stag_set_link_format": (S, [H, I]),
         "stag_set_naik": (S, [H, D, D]),
         "stag_profile_samples": (S, [H, I, ctypes.POINTER(ctypes.c_float), I, ctypes.POINTER(I)]),
+        "stag_mdagm_noalloc": (S, [H, P, P, D]),
         "stag_fermion_action": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(D),
                                     ctypes.POINTER(CSolveInfo)]),
         "stag_fermion_force": (S, [H, D, ctypes.POINTER(CRational), D, I, P, P, D, ctypes.POINTER(CSolveInfo)]),
@@ -316,6 +317,10 @@ class Lattice:
 
     def mdagm(self, out: torch.Tensor, inp: torch.Tensor, mass: float):
         self._check(self.lib.stag_mdagm(self.h, self._vec(out, "out"), self._vec(inp, "inp"), float(mass)))
+
+    def mdagm_noalloc(self, out: torch.Tensor, inp: torch.Tensor, mass: float):
+        """stag_mdagm with its odd temporary in the library's static scratch array (no allocation)."""
+        self._check(self.lib.stag_mdagm_noalloc(self.h, self._vec(out, "out"), self._vec(inp, "inp"), float(mass)))
 
     def dslash_sloppy(self, out: torch.Tensor, inp: torch.Tensor, out_parity: int, fmt: int):
         """The precision form's FP32 operator (links in fmt) on FP64 vectors."""
