@@ -33,6 +33,11 @@ TABLES = {
     # one drives the molecular dynamics
     "xm050_n16_m0.1": (-0.5, 0.1 ** 2, 64.0, 16, "small trajectory tests, accurate action"),
     "xp025_n16_m0.1": (0.25, 0.1 ** 2, 64.0, 16, "small trajectory tests, accurate heat bath"),
+    # accurate action and heat-bath tables for the m = 0.02 RHMC (relative
+    # error < 1e-11, the accuracy eq. ratapprx asks of them), beside the
+    # 12-pole MD table
+    "xm050_n20_m0.02": (-0.5, 0.02 ** 2, 64.0, 20, "RHMC action, accurate"),
+    "xp025_n20_m0.02": (0.25, 0.02 ** 2, 64.0, 20, "RHMC heat bath, accurate"),
     # the paper's Appendix example: degree 24/24 for x^(1/4) on [5e-5, 34]
     "xp025_n24_paper": (0.25, 5e-5, 34.0, 24, "paper Appendix example (error < 1e-12)"),
 }
