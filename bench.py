@@ -45,11 +45,44 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def solve_bytes(vh, iters, ipp, base, lag=1):
+# fused loop: D_oe launch j also forms p_j from r_{j-1}, Ap_{j-1}, p_{j-1}
+# (read once each) and writes r_j and p_j (x_base read and written while the
+# base system is active); the first launch reads p_0 and r_0 = b
+B_FUSED_DOE = 1152 + 3 * 48 + 48 + 2 * 48     # links, r/Ap/p in, w out, r and p out
+B_FUSED_DOE_FIRST = 1152 + 48 + 48 + 48       # links, p_0 in, w out, r_0 read for |r_0|^2
+
+
+def fused_solve_bytes(vh, iters, ipp, base, lag):
+    """Algorithmic bytes of one solve in the fused loop that stops at step
+    S = iters: iteration 0 (first D_oe + D_eo), iterations 1..S (fused D_oe
+    + D_eo), S // lag window flushes and the final partial flush; each flush
+    reads its window's residuals once and every shifted system active at the
+    window's start (x_k, p_k read and written)."""
+    def shifts_from(j0):
+        return sum(1 for k, f in enumerate(ipp) if k != base and f > j0)
+    total = (B_FUSED_DOE_FIRST + B_DEO_CG) * vh
+    for j in range(1, iters + 1):
+        total += (B_FUSED_DOE + (96 if ipp[base] > j - 1 else 0) + B_DEO_CG) * vh
+    for w0 in range(0, iters, lag):
+        npend = min(lag, iters - w0)
+        total += (48 * npend + B_UPD_SHIFT * shifts_from(w0)) * vh
+    return total
+
+
+def flush_bytes(vh, iters, ipp, base, lag):
+    def shifts_from(j0):
+        return sum(1 for k, f in enumerate(ipp) if k != base and f > j0)
+    return sum((48 * lag + B_UPD_SHIFT * shifts_from(w0)) * vh for w0 in range(0, iters - lag + 1, lag))
+
+
+def solve_bytes(vh, iters, ipp, base, lag=1, fused=False):
     """Algorithmic bytes of one solve from the per-pole freeze iterations
     (shift k is active in iterations j < ipp[k]).  The shifted solutions and
     directions are read and written once per window of `lag` iterations, and
     the window's residuals are read back once (two of them are in registers)."""
+    if fused:
+        return fused_solve_bytes(vh, iters, ipp, base, lag)
+
     def shifts_from(j0):
         return sum(1 for k, f in enumerate(ipp) if k != base and f > j0)
     total = 0
@@ -95,12 +128,14 @@ def cpu_baseline(U, b, rat, vh, lag, target_s=20.0):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dslash_oe_fp64_32c3x8_hbm_traffic.md")
 DSLASH_SOURCES = ["paper_1710_09178_amd/csrc/dslash.hip", "paper_1710_09178_amd/csrc/dslash.h",
-                  "paper_1710_09178_amd/csrc/common.h"]
+                  "paper_1710_09178_amd/csrc/common.h", "paper_1710_09178_amd/csrc/msfused.h"]
 
 
-def measured_traffic():
-    """HBM bytes per D_oe launch from the committed FETCH_SIZE/WRITE_SIZE
-    summary, or None once the Dslash sources differ from the ones profiled."""
+def measured_traffic(fused=True):
+    """Bytes per D_oe launch (FETCH_SIZE + WRITE_SIZE, calibrated; L2-to-fabric
+    requests, which include Infinity-Cache hits) from the committed summary
+    of the same loop, or None once the Dslash sources differ from the ones
+    profiled."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -110,7 +145,7 @@ def measured_traffic():
     except OSError:
         return None
     import re
-    t = re.search(r"traffic_bytes_per_launch dslash_oe (\d+)", text)
+    t = re.search(r"traffic_bytes_per_launch %s (\d+)" % ("dslash_oe_fused" if fused else "dslash_oe"), text)
     src = re.search(r"dslash_sources_sha256 ([0-9a-f]{64})", text)
     if not t or not src or src.group(1) != h.hexdigest():
         return None
@@ -196,8 +231,8 @@ def pmc_mode():
 
 
 def trajectory_trace_mode(n_traj=3):
-    """A few RHMC trajectories at 16^3x8 (beta 5.4, m 0.02, 12-pole tables,
-    tau 1, 20 steps) from a near-identity start, after one untimed one: a
+    """A few RHMC trajectories at 16^3x8 (beta 5.4, m 0.02, the 12-pole MD
+    table with 20-pole action and heat-bath tables, tau 1, 20 steps) from a near-identity start, after one untimed one: a
     short program for a kernel trace of the trajectory's launches."""
     import torch
 
@@ -208,12 +243,13 @@ def trajectory_trace_mode(n_traj=3):
     lat = Lattice(dims)
     lat.set_gauge(torch.from_numpy(synth.random_su3_near_identity(dims, 0.5, synth.make_rng(5, 0))).cuda())
     r_f = synth.load_rational("xm050_n12_m0.02")
-    r_h = synth.load_rational("xp025_n12_m0.02")
+    r_a = synth.load_rational("xm050_n20_m0.02")
+    r_h = synth.load_rational("xp025_n20_m0.02")
     kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
-    lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, inject_u=0.0, traj_index=0, **kw)
+    lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_a, r_h, inject_u=0.0, traj_index=0, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_f, r_h, inject_u=0.0, traj_index=1 + i, **kw)
+    res = [lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_a, r_h, inject_u=0.0, traj_index=1 + i, **kw)
            for i in range(n_traj)]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n_traj
@@ -235,6 +271,11 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-naik", action="store_true")
     ap.add_argument("--no-memory-check", action="store_true")
+    ap.add_argument("--no-fused", action="store_true", help="three launches per CG iteration instead of two")
+    ap.add_argument("--c1-hot", action="store_true", help="also the 32^3x8 solve on Haar links (long solves)")
+    ap.add_argument("--learned-long", action="store_true",
+                    help="learned-force chains at 20 leapfrog steps (exact, and exact every 4th kick with the "
+                         "truncated solve or the model between); use with --chain-traj 400")
     ap.add_argument("--chain-traj", type=int, default=24, help="trajectories per learned-force comparison chain")
     ap.add_argument("--inner-iters", type=int, default=200,
                     help="iterations of the truncated solve that feeds the learned model's auxiliary channel")
@@ -276,6 +317,10 @@ def main():
     if args.tps:
         lat.tune(args.tps, 16)
     lat.set_shift_window(args.lag)
+    # the library's default loop choice: fused on Dslash grids of <= 512
+    # blocks of 64 sites, so three launches per iteration at 32^3x8
+    fused = not args.no_fused and args.lag >= 2 and (vh_of(DIMS) + 63) // 64 <= 512
+    lat.set_fused_iteration(1 if not args.no_fused else 0)
     lat.set_gauge(torch.from_numpy(U).cuda())
     bd = lat.vec_import(torch.from_numpy(b).cuda(), 0)
     xs = [lat.new_vec() for _ in range(n)]
@@ -299,7 +344,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
-    bytes_total = sum(solve_bytes(vh, i["iters"], i["iters_per_pole"], base, args.lag) for i in infos)
+    bytes_total = sum(solve_bytes(vh, i["iters"], i["iters_per_pole"], base, args.lag, fused) for i in infos)
     value = bytes_total / elapsed / 1e9
 
     # one more solve: true residuals, and hipEvents around every kernel launch
@@ -310,16 +355,28 @@ def main():
     doe_samples = lat.profile_samples(0)
     lat.profile_enable(0)
     avg_us = [1e3 * ms[i] / max(cnt[i], 1) for i in range(3)]
-    doe_gbs = B_DOE * vh / (avg_us[0] * 1e-6) / 1e9
+    ipp_c = chk["iters_per_pole"]
+    if fused:
+        # D_oe with the folded base update: its bytes averaged over its launches
+        b_doe = (B_FUSED_DOE * cnt[0] + 96 * sum(1 for j in range(1, cnt[0] + 1) if ipp_c[base] > j - 1)) \
+            / max(cnt[0], 1)
+        upd_bytes = flush_bytes(vh, chk["iters"], ipp_c, base, args.lag)
+    else:
+        b_doe = B_DOE
+        upd_bytes = solve_bytes(vh, chk["iters"], ipp_c, base, args.lag) - (B_DOE + B_DEO_CG) * vh * chk["iters"]
+    doe_gbs = b_doe * vh / (avg_us[0] * 1e-6) / 1e9
     deo_gbs = B_DEO_CG * vh / (avg_us[1] * 1e-6) / 1e9
-    upd_bytes = solve_bytes(vh, chk["iters"], chk["iters_per_pole"], base, args.lag) \
-        - (B_DOE + B_DEO_CG) * vh * chk["iters"]
     upd_gbs = upd_bytes / max(cnt[2], 1) / (avg_us[2] * 1e-6) / 1e9
 
     forms = {}
     if not args.no_forms:
         log("precision forms")
         forms = precision_forms(lat, rat, bd, xs, vh, base, ms_per_step)
+
+    hot = None
+    if args.c1_hot:
+        log("32^3x8 on Haar links")
+        hot = c1_hot()
 
     memory = None
     if not args.no_memory_check:
@@ -339,7 +396,13 @@ def main():
     rh = None
     if not args.no_trajectory:
         log("RHMC at 16^3x8" + ("" if args.no_surrogate else " with and without the learned force model"))
-        rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj, inner_iters=args.inner_iters)
+        if args.learned_long:
+            # the workload's 20 leapfrog steps, long chains: exact force, and the
+            # exact force on every 4th kick with the truncated solve or the model between
+            rh = rhmc(with_model=True, n_traj=args.chain_traj, inner_iters=args.inner_iters, chain_steps=20,
+                      every_list=(4,), ablation=False)
+        else:
+            rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj, inner_iters=args.inner_iters)
 
     out = {
         "metric": "multishift-CG Dslash GB/s (% HBM peak) at 32^3x8; sec/RHMC trajectory",
@@ -357,13 +420,20 @@ def main():
         "config": {"workload": "fp64 multi-shift CG, staggered even-odd operator, 32^3x8, 12 poles of x^(-1/4), "
                                "m=0.005, tol=1e-10",
                    "lattice": list(DIMS), "poles": n, "mass": MASS, "tol": TOL, "links": "exp(i 0.2 H) in SU(3)"},
-        "roofline": {"bound": "hbm", "kernel": "D_oe Dslash (in the multi-shift CG)",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("D_oe Dslash with the folded base-system update (fused CG iteration)" if fused
+                                else "D_oe Dslash (in the multi-shift CG)"),
                      "achieved": round(doe_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(doe_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "avg_launch_us": round(avg_us[0], 3), "algorithmic_bytes_per_launch": B_DOE * vh},
-        "kernels": {"dslash_oe": {"avg_us": round(avg_us[0], 3), "GB/s": round(doe_gbs, 1), "launches": cnt[0]},
+                     "frac": round(doe_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(fused),
+                     "avg_launch_us": round(avg_us[0], 3), "algorithmic_bytes_per_launch": round(b_doe * vh)},
+        "fused_iteration": fused,
+        "kernels": {"dslash_oe" + ("_fused" if fused else ""): {"avg_us": round(avg_us[0], 3),
+                                                                 "GB/s": round(doe_gbs, 1), "launches": cnt[0],
+                                                                 "bytes_per_site": round(b_doe, 1)},
                     "dslash_eo_cg": {"avg_us": round(avg_us[1], 3), "GB/s": round(deo_gbs, 1), "launches": cnt[1]},
-                    "shift_update": {"avg_us": round(avg_us[2], 3), "GB/s": round(upd_gbs, 1), "launches": cnt[2]}},
+                    ("window_flush" if fused else "shift_update"): {"avg_us": round(avg_us[2], 3),
+                                                                     "GB/s": round(upd_gbs, 1),
+                                                                     "launches": cnt[2]}},
         "ms_per_step_pct": _pct(step_ms),
         "dslash_oe_us_pct": _pct(doe_samples),
         "iterations": infos[0]["iters"],
@@ -378,6 +448,8 @@ def main():
         out["batched_form"] = batched
     if improved:
         out["naik_operator"] = improved
+    if hot:
+        out["c1_hot"] = hot
     if memory:
         out["memory_check"] = memory
         out["roofline"]["beyond_cache"] = {
@@ -422,6 +494,10 @@ def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
                      "iterations_total": im["iters"], "iterations_per_pole": im["iters_per_pole"],
                      "true_resid_max": max(chk["true_resid"]), "tol_sloppy": 1e-5, "reliable_every": 50}
     return out
+
+
+def vh_of(dims):
+    return dims[0] * dims[1] * dims[2] * dims[3] // 2
 
 
 def _pct(v):
@@ -491,11 +567,16 @@ def memory_check(lat, bd, vh, reps=20):
     del U, small
     bdev = big_lat.vec_import(torch.from_numpy(b).cuda(), 0)
     xs = [big_lat.new_vec() for _ in rat["pole"]]
-    big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
-    ms = (time.perf_counter() - t0) * 1e3
+    solve_ms = {}
+    for fz in (True, False):
+        big_lat.set_fused_iteration(2 if fz else 0)
+        big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
+        solve_ms[fz] = ((time.perf_counter() - t0) * 1e3, info)
+    ms, info = solve_ms[False]
+    # the plain D_oe kernel inside the three-launch loop
     big_lat.profile_enable(3 * (info["iters"] + 64))
     chk = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=True)
     vh48 = big_lat.Vh
@@ -504,7 +585,8 @@ def memory_check(lat, bd, vh, reps=20):
     big_lat.profile_enable(0)
     base = int(np.argmin(rat["pole"]))
     out["solve_48c3x16"] = {
-        "ms_per_solve": round(ms, 3), "iterations": info["iters"], "true_resid_max": max(chk["true_resid"]),
+        "ms_per_solve_fused": round(solve_ms[True][0], 3), "ms_per_solve": round(ms, 3),
+        "iterations": info["iters"], "true_resid_max": max(chk["true_resid"]),
         "value_GB/s": round(solve_bytes(vh48, info["iters"], info["iters_per_pole"], base, 8) / (ms * 1e-3) / 1e9, 1),
         "links_GB": round(2 * 4 * 144 * vh48 / 1e9, 3),
         "dslash_oe_us": doe, "dslash_oe_GB/s_at_p50": round(B_DOE * vh48 / (doe["p50"] * 1e-6) / 1e9, 1),
@@ -512,6 +594,47 @@ def memory_check(lat, bd, vh, reps=20):
         "dslash_eo_cg_us": deo, "dslash_eo_cg_GB/s_at_p50": round(B_DEO_CG * vh48 / (deo["p50"] * 1e-6) / 1e9, 1)}
     del big_lat, xs, bdev
     torch.cuda.empty_cache()
+    return out
+
+
+def c1_hot(reps=2):
+    """The 32^3x8 12-pole solve (m = 0.005, tol 1e-10) on Haar-random links,
+    whose dense low spectrum makes the solves long (the regime of the paper's
+    production runs, thousands of iterations): FP64 with 18- and 12-real links
+    against the mixed FP32/FP64 solve with FP32-18 links, every pole to the
+    FP64 true residual 1e-10."""
+    import torch
+
+    import synth
+    from paper_1710_09178_amd import stag
+    from paper_1710_09178_amd.stag import Lattice
+    U = synth.haar_su3(DIMS, synth.make_rng(1, 7))
+    b = synth.gaussian_half_vector(DIMS, synth.make_rng(1, 1))
+    rat = synth.load_rational(TABLE)
+    lat = Lattice(DIMS)
+    lat.set_gauge(torch.from_numpy(U).cuda())
+    bd = lat.vec_import(torch.from_numpy(b).cuda(), 0)
+    xs = [lat.new_vec() for _ in rat["pole"]]
+    out = {"workload": "32^3x8 Haar links, m 0.005, 12 poles of x^(-1/4), tol 1e-10"}
+    for name, fmt, mixed in (("fp64_links18", stag.LINKS_F64_18, False), ("fp64_links12", stag.LINKS_F64_12, False),
+                             ("mixed_fp32_links18", stag.LINKS_F64_18, True)):
+        lat.set_link_format(fmt)
+        solve = (lambda tr: lat.multishift_solve_mixed(MASS, rat, TOL, 400000, bd, xs, None, sloppy=stag.LINKS_F32_18,
+                                                       true_resid=tr)) if mixed else \
+            (lambda tr: lat.multishift_solve(MASS, rat, TOL, 400000, bd, xs, None, true_resid=tr))
+        solve(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            info = solve(False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        chk = solve(True)
+        out[name] = {"ms_per_solve": round(ms, 2), "iterations": info["iters"],
+                     "iterations_per_pole": info["iters_per_pole"], "true_resid_max": max(chk["true_resid"])}
+    lat.set_link_format(stag.LINKS_F64_18)
+    for k in ("fp64_links12", "mixed_fp32_links18"):
+        out[k]["speedup_vs_fp64_links18"] = round(out["fp64_links18"]["ms_per_solve"] / out[k]["ms_per_solve"], 3)
     return out
 
 
@@ -599,7 +722,6 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     srcs = [synth.gaussian_half_vector(d, synth.make_rng(3, 5000 + 8 * i + j))
             for i, d in enumerate(dims) for j in range(nrhs)]
     b = torch.from_numpy(np.concatenate([v.reshape(-1) for v in srcs])).cuda()
-    del srcs
     B.set_shift_window(8)
     tuned = B.tune(0)
     out = {"workload": f"{len(dims)} lattices (16 each of 8^4, 12^3x6, 16^3x8, 24^3x6) x {nrhs} right-hand "
@@ -626,13 +748,47 @@ def batched_form(per_class=16, nrhs=4, reps=2):
         out[name] = row
         del x
     out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32_fp64"]["ms_per_solve"], 3)
+    # the same 256 systems one after another, one single-lattice handle per
+    # lattice (FP64, library defaults), for the batched form's speedup
+    from paper_1710_09178_amd.stag import Lattice
+    del B, b
+    torch.cuda.empty_cache()
+    lats, vecs = [], []
+    for i, d in enumerate(dims):
+        lat = Lattice(d)
+        lat.set_gauge(torch.from_numpy(synth.random_su3_near_identity(d, 0.2, synth.make_rng(3, 1000 + i))).cuda())
+        lats.append(lat)
+        vecs.append([lat.vec_import(torch.from_numpy(srcs[i * nrhs + j]).cuda(), 0) for j in range(nrhs)])
+    del srcs
+    xs = {}
+
+    def sequential():
+        iters = 0
+        for i, lat in enumerate(lats):
+            x = xs.setdefault(dims[i], [lat.new_vec() for _ in rat["pole"]])
+            for j in range(nrhs):
+                iters += lat.multishift_solve(masses[i], rat, 1e-10, 100000, vecs[i][j], x, None,
+                                              true_resid=False)["iters"]
+        return iters
+
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_iters = sequential()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3
+    out["sequential_fp64"] = {"ms_for_all_systems": round(seq_ms, 3), "iterations_total": seq_iters,
+                              "batched_speedup": round(seq_ms / out["fp64"]["ms_per_solve"], 3)}
+    del lats, vecs, xs
+    torch.cuda.empty_cache()
     return out
 
 
 def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.0, inner_iters=200,
-         chain_steps=40):
-    """RHMC at 16^3x8 (beta 5.4, m 0.02, 12-pole rational tables, tau 1, 20
-    leapfrog steps, MD tolerance 1e-8, action 1e-10) from a seeded hot start,
+         chain_steps=40, every_list=(2, 4), ablation=True):
+    """RHMC at 16^3x8 (beta 5.4, m 0.02, the 12-pole MD table with 20-pole
+    action and heat-bath tables, tau 1, 20 leapfrog steps, MD tolerance 1e-8,
+    action 1e-10) from a seeded hot start,
     thermalised by 60 pure-gauge and 5 dynamical trajectories (all accepted).
     sec_per_trajectory: n_exact exact-force trajectories continuing the chain.
 
@@ -654,25 +810,33 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     from paper_1710_09178_amd.stag import Lattice, Surrogate
     dims = (16, 16, 16, 8)
     beta, mass, tau, n_steps = 5.4, 0.02, 1.0, 20
-    r_f = synth.load_rational("xm050_n12_m0.02")
-    r_h = synth.load_rational("xp025_n12_m0.02")
+    r_f = synth.load_rational("xm050_n12_m0.02")     # MD force
+    r_a = synth.load_rational("xm050_n20_m0.02")     # action (Metropolis), error 4.9e-12
+    r_h = synth.load_rational("xp025_n20_m0.02")     # heat bath, error 3.4e-12
     lat = Lattice(dims)
     lat.set_gauge(torch.from_numpy(synth.haar_su3(dims, synth.make_rng(5, 0))).cuda())
     kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
     t = 0
     for _ in range(60):
-        lat.trajectory(beta, mass, 0.5, 20, r_f, r_f, r_h, no_fermions=True, inject_u=0.0, traj_index=t, **kw)
+        lat.trajectory(beta, mass, 0.5, 20, r_f, r_a, r_h, no_fermions=True, inject_u=0.0, traj_index=t, **kw)
         t += 1
     for _ in range(5):
-        lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, inject_u=0.0, traj_index=t, **kw)
+        lat.trajectory(beta, mass, tau, n_steps, r_f, r_a, r_h, inject_u=0.0, traj_index=t, **kw)
         t += 1
 
     def summary(res, sec):
         dH = np.array([r["dH"] for r in res])
+        acc = np.array([r["accepted"] for r in res], dtype=np.float64)
+        pmet = np.minimum(1.0, np.exp(-np.minimum(dH, 700.0)))
+        edh = np.exp(-np.minimum(dH, 700.0))
         return {"sec_per_traj": round(sec, 4), "traj_per_s": round(1.0 / sec, 3),
-                "acceptance": round(float(np.mean([r["accepted"] for r in res])), 3),
+                "acceptance": round(float(acc.mean()), 3),
+                "acceptance_stderr": round(float(acc.std() / np.sqrt(max(len(acc) - 1, 1))), 3),
+                "mean_min1_exp_minus_dH": round(float(pmet.mean()), 4),
+                "mean_min1_exp_minus_dH_stderr": round(float(pmet.std() / np.sqrt(max(len(pmet) - 1, 1))), 4),
                 "mean_abs_dH": round(float(np.mean(np.abs(dH))), 4),
-                "mean_exp_minus_dH": round(float(np.mean(np.exp(-np.minimum(dH, 700.0)))), 4),
+                "mean_exp_minus_dH": round(float(edh.mean()), 4),
+                "mean_exp_minus_dH_stderr": round(float(edh.std() / np.sqrt(max(len(edh) - 1, 1))), 4),
                 "cg_iters_per_traj": int(np.mean([r["cg_iters_total"] for r in res])),
                 "plaquette_end": round(res[-1]["plaquette"], 5), "trajectories": len(res)}
 
@@ -684,14 +848,19 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
         lat.set_gauge(U_therm)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        res = [lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, traj_index=t_first + i, **kw, **extra)
+        res = [lat.trajectory(beta, mass, tau, n_steps, r_f, r_a, r_h, traj_index=t_first + i, **kw, **extra)
                for i in range(n_exact)]
         torch.cuda.synchronize()
         return summary(res, (time.perf_counter() - t1) / n_exact)
 
     out = {"sec_per_trajectory": dict(timed_chain(), polyakov_loop_thermalised=[round(pl.real, 6), round(pl.imag, 6)],
-                                      workload="RHMC 16^3x8, beta 5.4, m 0.02, 12-pole x^(-1/2) and x^(1/4) "
-                                               "tables, tau 1, 20 leapfrog steps, thermalised from a hot start")}
+                                      workload="RHMC 16^3x8, beta 5.4, m 0.02, 12-pole x^(-1/2) MD table, "
+                                               "20-pole x^(-1/2) action and x^(1/4) heat-bath tables, tau 1, "
+                                               "20 leapfrog steps, thermalised from a hot start")}
+    # the same chain with three launches per CG iteration (no fused base update)
+    lat.set_fused_iteration(False)
+    out["sec_per_trajectory_three_launch_loop"] = timed_chain()
+    lat.set_fused_iteration(True)
     # precision form in the trajectory: MD force solves with FP32 Krylov vectors
     md = {"fp32_links18": timed_chain(md_link_format=2), "fp32_fp16links12": timed_chain(md_link_format=3)}
     for v in md.values():
@@ -706,7 +875,7 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     rec = []
     t0 = time.perf_counter()
     while sur.pairs < n_pairs:
-        rec.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_f, r_h, surrogate=sur, record_pairs=True,
+        rec.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_a, r_h, surrogate=sur, record_pairs=True,
                                   inner_iters=inner_iters, traj_index=t, **kw))
         t += 1
     t_rec = time.perf_counter() - t0
@@ -752,15 +921,16 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
         res = []
         t1 = time.perf_counter()
         for i in range(n_traj):
-            res.append(lat.trajectory(beta, mass, tau, chain_steps, r_f, r_f, r_h, traj_index=10 ** 6 + i,
+            res.append(lat.trajectory(beta, mass, tau, chain_steps, r_f, r_a, r_h, traj_index=10 ** 6 + i,
                                       **kw, **extra))
         torch.cuda.synchronize()
         return summary(res, (time.perf_counter() - t1) / n_traj)
 
     chains = {"exact": chain()}
-    for every in (2, 4):
+    for every in every_list:
         ms = dict(exact_every=every, coarse_force=True)
-        chains[f"ablation_no_inner_force_exact_every_{every}"] = chain(**ms)
+        if ablation:
+            chains[f"ablation_no_inner_force_exact_every_{every}"] = chain(**ms)
         chains[f"inner_truncated_solve_exact_every_{every}"] = chain(surrogate=ident, inner_iters=inner_iters, **ms)
         chains[f"inner_learned_model_exact_every_{every}"] = chain(surrogate=sur, inner_iters=inner_iters, **ms)
     for k, v in chains.items():

@@ -471,6 +471,18 @@ stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
  * first min(cap, *n_out) go to us_out (host array).  STAG_ERR_INVALID_ARG for
  * a kind outside [0, 2], cap < 0, n_out NULL, or us_out NULL with cap > 0. */
 stag_status stag_profile_samples(stag_handle h, int kind, float* us_out, int cap, int* n_out);
+/* The fused iteration of FP64 multi-shift solves (shift-update window >= 2):
+ * the base system's update of step j-1 is folded into the D_oe launch of
+ * iteration j, which forms p_j = (r_{j-1} - alpha Ap_{j-1}) + beta p_{j-1}
+ * where it reads it, and the shifted systems are updated by one flush launch
+ * per window -- two launches per iteration instead of three, and one memory
+ * round trip before the arithmetic of each.  mode 1 (default): on lattices
+ * whose Dslash grid (Vh / 64 blocks) is at most 512 blocks, where iterations
+ * are latency-bound; 2: at every size; 0: never (the three-launch loop).
+ * The two loops solve the same systems to the same tolerance; their reduction
+ * trees differ, so results agree to rounding, not bitwise.  Returns
+ * STAG_ERR_INVALID_ARG for a mode outside 0..2. */
+stag_status stag_set_fused_iteration(stag_handle h, int mode);
 /* Solvers replay each chunk of iterations from a hipGraph captured on first
  * use (kernel nodes only; up to 8 cached per handle, keyed by every launch
  * argument) unless profiling or reliable updates need per-launch work.  on = 0

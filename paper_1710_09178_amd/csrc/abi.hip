@@ -239,6 +239,7 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
     if (const char* e = std::getenv("STAG_TPS")) c->tps = std::atoi(e);
     if (c->tps != 1 && c->tps != 2 && c->tps != 4) c->tps = 2;
     if (const char* e = std::getenv("STAG_CHUNK")) c->chunk = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("STAG_FUSED")) c->fused = std::max(0, std::min(2, std::atoi(e)));
     c->user = (hipStream_t)hip_stream;
     auto bail = [&](stag_status s) {
         g_create_err = c->err;
@@ -264,7 +265,7 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
     const size_t mb = (size_t)2 * 4 * 8 * g.vh * sizeof(double);
     stag_status s;
     if ((s = dmalloc(c, &c->links, lb)) || (s = dmalloc(c, &c->links_backup, lb)) || (s = dmalloc(c, &c->mom, mb)) ||
-        (s = dmalloc(c, &c->r, kLagMax * hb)) || (s = dmalloc(c, &c->p, hb)) || (s = dmalloc(c, &c->Ap, hb)) ||
+        (s = dmalloc(c, &c->r, kLagMax * hb)) || (s = dmalloc(c, &c->p, hb)) || (s = dmalloc(c, &c->p2, hb)) || (s = dmalloc(c, &c->Ap, hb)) ||
         (s = dmalloc(c, &c->w_o, hb)) || (s = dmalloc(c, &c->tmp_e, hb)) || (s = dmalloc(c, &c->tmp_o, hb)) ||
         (s = dmalloc(c, &c->xi, hb)) || (s = dmalloc(c, &c->phi, hb)) || (s = dmalloc(c, &c->st, sizeof(MsState))) ||
         (s = dmalloc(c, &c->scal, 64)))
@@ -298,7 +299,7 @@ stag_status stag_destroy(stag_handle c) {
     if (c->s) hipStreamSynchronize(c->s);
     void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->long_d18, c->long_d12, c->long_s18, c->long_h12,
                     c->r32, c->p32, c->Ap32, c->w32,
-                    c->links, c->links_backup, c->mom, c->r, c->p, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
+                    c->links, c->links_backup, c->mom, c->r, c->p, c->p2, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
                     c->gpart, c->scal, c->mom_tmp, c->mom_aux};
     for (void* b : bufs)
@@ -978,6 +979,15 @@ stag_status stag_profile_samples(stag_handle c, int kind, float* us_out, int cap
     const auto& v = c->prof_samples[kind];
     *n_out = (int)v.size();
     for (int i = 0; i < cap && i < (int)v.size(); ++i) us_out[i] = 1e3f * v[i];
+    return STAG_OK;
+}
+
+// The fused FP64 multi-shift loop: 0 off, 1 on small grids (default), 2 always.
+stag_status stag_set_fused_iteration(stag_handle c, int on) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (on < 0 || on > 2) return fail(c, STAG_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+    c->fused = on;
     return STAG_OK;
 }
 

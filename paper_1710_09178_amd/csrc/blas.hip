@@ -10,6 +10,7 @@
 // block (a few thousand doubles, L2 resident), so each block derives the same
 // bitwise scalars without a grid-wide barrier.
 #include "common.h"
+#include "msfused.h"
 
 namespace stag {
 
@@ -357,6 +358,88 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
     if (row0) block_partial<1>(acc, qout);
 }
 
+// Window flush of the fused loop: the shifted systems' updates of npend
+// consecutive steps i0 .. i0 + npend - 1 (i0 a multiple of L), applied in
+// order to x_s, p_s of every shift active in step i0, from the scalars in
+// st->hist[t] and the residuals r_{i0+t+1} in ring slot (t + 1) % L -- the
+// arithmetic of the unfused step kernel's flush.  final = 0: launched after
+// iteration j = i0 + L, npend = L, skipped once the solve has stopped (gate);
+// final = 1: once after the loop, npend = fin.iter % L (the steps pending at
+// the stop).  Block row y takes the shift groups y, y + gridDim.y, ...
+template <int EPT>
+__global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const double2* __restrict__ ring, VecPtrs x, VecPtrs ps,
+                                                     const MsState* __restrict__ st, const int* __restrict__ gate,
+                                                     int n, int base, int L, int final_flush) {
+    if (!final_flush && *gate) return;
+    const int npend = final_flush ? st->fin.iter % L : L;
+    if (npend == 0) return;
+    __shared__ double w_as[kLagMax][kMaxPoles], w_bs[kLagMax][kMaxPoles], w_zn[kLagMax][kMaxPoles];
+    __shared__ int w_act[kLagMax][kMaxPoles];
+    __shared__ int sh_list[kMaxPoles];
+    __shared__ int sh_nact;
+    const int k = threadIdx.x;
+    if (k < 64) {
+        if (k < n)
+            for (int t = 0; t < npend; ++t) {
+                w_as[t][k] = st->hist[t].as[k];
+                w_bs[t][k] = st->hist[t].bs[k];
+                w_zn[t][k] = st->hist[t].zn[k];
+                w_act[t][k] = st->hist[t].act[k];
+            }
+        const int mine = k < n && k != base && st->hist[0].act[k];
+        const unsigned long long lmask = __ballot(mine != 0);
+        if (mine) sh_list[__popcll(lmask & ((1ull << k) - 1ull))] = k;
+        if (k == 0) sh_nact = __popcll(lmask);
+    }
+    __syncthreads();
+    const int nact = sh_nact;
+    constexpr int G = kFlushGroup;
+    for (int e = 0; e < EPT; ++e) {
+        const int i = (blockIdx.x * EPT + e) * kBlock + threadIdx.x;
+        if (i >= n3) continue;
+        double2 rw[kLagMax];
+#pragma unroll
+        for (int t = 0; t < kLagMax; ++t) {
+            if (t >= npend) break;
+            rw[t] = ring[(size_t)((t + 1) % L) * n3 + i];
+        }
+        for (int g0 = blockIdx.y * G; g0 < nact; g0 += gridDim.y * G) {
+            double2 pk[G], xk[G];
+#pragma unroll
+            for (int jj = 0; jj < G; ++jj) {
+                if (g0 + jj < nact) {
+                    const int q = sh_list[g0 + jj];
+                    pk[jj] = nt_load(ps.at<double2>(q) + i);
+                    xk[jj] = nt_load(x.at<double2>(q) + i);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kLagMax; ++t) {
+                if (t >= npend) break;
+#pragma unroll
+                for (int jj = 0; jj < G; ++jj) {
+                    if (g0 + jj < nact) {
+                        const int q = sh_list[g0 + jj];
+                        if (w_act[t][q]) {
+                            const double aq = w_as[t][q], bq = w_bs[t][q], zq = w_zn[t][q];
+                            xk[jj] = make_double2(xk[jj].x + aq * pk[jj].x, xk[jj].y + aq * pk[jj].y);
+                            pk[jj] = make_double2(zq * rw[t].x + bq * pk[jj].x, zq * rw[t].y + bq * pk[jj].y);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < G; ++jj) {
+                if (g0 + jj < nact) {
+                    const int q = sh_list[g0 + jj];
+                    nt_store(x.at<double2>(q) + i, xk[jj]);
+                    nt_store(ps.at<double2>(q) + i, pk[jj]);
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_rational_sum(int n3, const double2* __restrict__ b, VecPtrs x,
                                                          const MsState* __restrict__ st,
                                                          double2* __restrict__ out) {
@@ -454,6 +537,16 @@ template void launch_ms_step<double2>(const Geom&, double2*, const double2*, dou
 template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2*, VecPtrs, VecPtrs, MsState*,
                                      const double*, int, const double*, double*, int, int, MsStepConst,
                                      hipStream_t);
+
+void launch_ms_flush(const Geom& g, const double2* ring, VecPtrs x, VecPtrs ps, const MsState* st, const int* gate,
+                     int n, int base, int L, bool final_flush, int rows, hipStream_t s) {
+    if (ms_ept(g) == 1)
+        timed_launch(k_ms_flush<1>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, ring, x, ps, st, gate, n, base, L,
+                     (int)final_flush);
+    else
+        timed_launch(k_ms_flush<2>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, ring, x, ps, st, gate, n, base, L,
+                     (int)final_flush);
+}
 
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
     if (ms_ept(g) == 1)

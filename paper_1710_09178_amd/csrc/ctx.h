@@ -37,6 +37,7 @@ struct stag_ctx {
     double* mom_aux = nullptr;   // truncated-solve force fed to a learned model
     // FP64 Krylov workspace
     double2 *r = nullptr /* ring of kLagMax residuals */, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
+    double2* p2 = nullptr;   // second search direction (the fused loop double-buffers p)
     double2 *xi = nullptr, *phi = nullptr;
     // FP32 Krylov workspace (precision form)
     float2 *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *w32 = nullptr;
@@ -57,6 +58,7 @@ struct stag_ctx {
     int chunk = 16;                      // iterations enqueued between convergence polls
     int lag = 8;                         // shift-update window of the multi-shift solver
     int use_graph = 1;                   // replay iteration chunks from captured hipGraphs
+    int fused = 1;                       // FP64 solves fold the base update into the D_oe launch
     // captured iteration chunks, keyed by every argument their launches take
     struct ChunkGraph {
         std::vector<unsigned char> key;
@@ -114,6 +116,7 @@ inline void links_changed(stag_ctx* c) {
 
 struct SolveResult {
     int iters = 0;
+    bool fused = false;   // ran the fused loop
     int nonfinite = 0;
     int converged = 1;
     double bb = 0.0;

@@ -41,6 +41,14 @@ void launch_dslash_cg(const Geom& g, const LinkSet& ls, const double2* w_o, cons
 void launch_dslash_resid(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* x, const double2* b,
                          double c, double* part, int tps, hipStream_t s, float2* r32_out = nullptr);
 
+struct FusedIter;
+// Iteration j of the fused multi-shift CG: step j-1's scalars and base update
+// folded into w = D_oe p_j (first: j = 0, D_oe p_0 and |r_0|^2 partials only);
+// always 4 threads per site, grid dslash_fused_grid(g) = dslash_grid(g, 4)
+int dslash_fused_grid(const Geom& g);
+void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIter& f, double2* w_out, bool first,
+                         hipStream_t s);
+
 // FP32 operator (format fmt32)
 void launch_dslash32(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int out_par, int tps,
                      const int* gate, hipStream_t s);

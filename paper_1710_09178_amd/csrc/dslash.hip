@@ -25,6 +25,7 @@
 
 #include "common.h"
 #include "dslash.h"
+#include "msfused.h"
 
 namespace stag {
 
@@ -158,10 +159,12 @@ __device__ __forceinline__ void hop3_geometry(const Geom& g, int mu, int x, int 
 // acc += wf * U psi_f - wb * U'^dag psi_b for one direction: U is the link
 // (or long link) leaving the output site (parity out_par, index cb), U' the
 // one arriving from the backward neighbour cbb (which also indexes psi_b).
-template <class Link>
-__device__ __forceinline__ void hop_w(const Geom& g, const Link& L, const typename Link::C* __restrict__ in,
-                                      int out_par, int mu, int cb, int cbf, int cbb, typename Link::R wf,
-                                      typename Link::R wb, typename Link::C (&acc)[3]) {
+// `in` is the input vector: a pointer, or an accessor that forms each element
+// where it is read (the fused multi-shift iteration).
+template <class Link, class In>
+__device__ __forceinline__ void hop_w(const Geom& g, const Link& L, In in, int out_par, int mu, int cb, int cbf,
+                                      int cbb, typename Link::R wf, typename Link::R wb,
+                                      typename Link::C (&acc)[3]) {
     using C = typename Link::C;
     C U[9], W[9], pf[3], pb[3];
     L.load(g, out_par, mu, cb, U);
@@ -194,9 +197,9 @@ struct NaikOp {
 };
 
 // acc += sf * U psi_f - sb * U'^dag psi_b for one direction
-template <class Link>
-__device__ __forceinline__ void hop(const Geom& g, const Link& L, const typename Link::C* __restrict__ in, int out_par,
-                                    int mu, int cb, int x, int y, int z, int t, typename Link::C (&acc)[3]) {
+template <class Link, class In>
+__device__ __forceinline__ void hop(const Geom& g, const Link& L, In in, int out_par, int mu, int cb, int x, int y,
+                                    int z, int t, typename Link::C (&acc)[3]) {
     using C = typename Link::C;
     using R = typename Link::R;
     int cbf, cbb;
@@ -224,10 +227,9 @@ __device__ __forceinline__ void hop(const Geom& g, const Link& L, const typename
     }
 }
 
-template <class Link>
-__device__ __forceinline__ void hop(const Geom& g, const NaikOp<Link>& op, const typename Link::C* __restrict__ in,
-                                    int out_par, int mu, int cb, int x, int y, int z, int t,
-                                    typename Link::C (&acc)[3]) {
+template <class Link, class In>
+__device__ __forceinline__ void hop(const Geom& g, const NaikOp<Link>& op, In in, int out_par, int mu, int cb, int x,
+                                    int y, int z, int t, typename Link::C (&acc)[3]) {
     using R = typename Link::R;
     int cbf, cbb;
     bool nf, nb;
@@ -357,6 +359,187 @@ __global__ __launch_bounds__(kBlock) void k_dslash(Geom g, Link L, const typenam
     epi.finish(racc);
 }
 
+// p_j = (r_{j-1} - alpha Ap_{j-1}) + beta p_{j-1}, formed where it is read
+struct InUpd {
+    const double2* __restrict__ r;
+    const double2* __restrict__ a;
+    const double2* __restrict__ p;
+    double alpha, beta;
+    __device__ __forceinline__ double2 operator[](size_t i) const {
+        return cg_p_next(cg_r_next(r[i], a[i], alpha), p[i], beta);
+    }
+};
+
+// Iteration j of the fused multi-shift CG (FP64): w = D_oe p_j for the odd
+// sites of this block's tile, after
+//   * summing the partials of |r_{j-1}|^2 and of the three D_eo(j-1) dots in
+//     block order (every block, bitwise alike) and evaluating step j-1's
+//     scalars (fused_step_scalars; block 0 writes the state),
+//   * forming p_j at every neighbour from r_{j-1}, Ap_{j-1}, p_{j-1};
+// then the even sites with the tile's indices get r_j (ring slot j % L),
+// p_j (the other p buffer), x_base += alpha p_{j-1}, and the block partial of
+// |r_j|^2.  FIRST (j = 0): D_oe p_0 and the partials of |r_0|^2 only.  A
+// stopped solve (flag done[par]) skips the launch and carries the flag.
+//
+// The loop serves lattices whose grid is a few hundred blocks, where an
+// iteration is a chain of dependent memory round trips rather than a
+// bandwidth budget.  So one wave per direction (4 threads per site), and
+// every load that does not depend on the step's scalars -- the partials, the
+// state, both links, the neighbours' r, Ap, p and the owned site's r, Ap, p,
+// x_base -- is issued before the scalars are formed: one round trip before
+// the arithmetic instead of four.  (The improved operator's 16 links take the
+// plain order: scalars first, operands after.)
+template <class Link>
+struct is_naik_op {
+    static constexpr bool value = false;
+};
+template <class Link>
+struct is_naik_op<NaikOp<Link>> {
+    static constexpr bool value = true;
+};
+
+template <class Link, bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIter f, double2* __restrict__ w_out) {
+    using C = double2;
+    constexpr int TPS = 4, SB = kBlock / TPS;
+    MsState* st = f.st;
+    if (!FIRST && st->done[f.par]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->done[f.par ^ 1] = 1;
+        return;
+    }
+    __shared__ C part[TPS * 3 * SB];
+    __shared__ double lds[16];
+    const double2* r_prev = f.ring + (size_t)f.slot_prev * 3 * g.vh;
+    const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
+    const int tile = xcd_tile_slab(blockIdx.x, gridDim.x, g, SB);
+    const int cb = tile * SB + lane;
+    const bool site_ok = cb < g.vh;
+    int x = 0, y = 0, z = 0, t = 0, cbf = 0, cbb = 0;
+    bool nf = false, nb = false;
+    if (site_ok) {
+        cb_coords(g, 1, cb, x, y, z, t);
+        hop_geometry(g, mu, x, y, z, t, cbf, cbb, nf, nb);
+    }
+    // the owned even site (colour c, index site) of this thread: 3 SB = 192 of the 256 threads
+    const int oc = threadIdx.x / SB, osite = tile * SB + (threadIdx.x % SB);
+    const bool own = threadIdx.x < 3 * SB && osite < g.vh;
+    const size_t oi = (size_t)oc * g.vh + osite;
+    C acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = C{0, 0};
+    double alpha = 0.0, beta = 0.0;
+    int base_on = 0;
+    double2 o_r = {0, 0}, o_a = {0, 0}, o_p = {0, 0}, o_x = {0, 0};
+    if (FIRST) {
+        if (site_ok) hop(g, L, f.p_prev, 1, mu, cb, x, y, z, t, acc);
+        if (own) o_r = r_prev[oi];
+    } else {
+        constexpr int kU = 8;
+        const int nb2 = f.nb2;
+        double tq[kU], t1[kU], t2[kU], t3[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int b = min((int)threadIdx.x + u * kBlock, nb2 - 1);
+            tq[u] = f.qin[b];
+            t1[u] = f.dpart[b];
+            t2[u] = f.dpart[nb2 + b];
+            t3[u] = f.dpart[2 * nb2 + b];
+        }
+        const LaneState lst = load_lane_state(f);
+        if (own) {
+            o_r = r_prev[oi];
+            o_a = f.Ap[oi];
+            o_p = f.p_prev[oi];
+            o_x = f.x_base[oi];
+        }
+        // hop operands (plain links): both links and the neighbours' r, Ap, p
+        C U[9], W[9], fr[3], fa[3], fp[3], br[3], ba[3], bp[3];
+        if constexpr (!is_naik_op<Link>::value) {
+            if (site_ok) {
+                L.load(g, 1, mu, cb, U);
+                L.load(g, 0, mu, cbb, W);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const size_t jf = (size_t)c * g.vh + cbf, jb = (size_t)c * g.vh + cbb;
+                    fr[c] = r_prev[jf];
+                    fa[c] = f.Ap[jf];
+                    fp[c] = f.p_prev[jf];
+                    br[c] = r_prev[jb];
+                    ba[c] = f.Ap[jb];
+                    bp[c] = f.p_prev[jb];
+                }
+            }
+        }
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if ((int)threadIdx.x + u * kBlock < nb2) {
+                v[0] += tq[u];
+                v[1] += t1[u];
+                v[2] += t2[u];
+                v[3] += t3[u];
+            }
+        for (int b = threadIdx.x + kU * kBlock; b < nb2; b += kBlock) {
+            v[0] += f.qin[b];
+            v[1] += f.dpart[b];
+            v[2] += f.dpart[nb2 + b];
+            v[3] += f.dpart[2 * nb2 + b];
+        }
+        block_sum<4>(v, lds);
+        const StepOut so = fused_step_scalars(f, v, lst);
+        if (so.stop) return;
+        alpha = so.alpha;
+        beta = so.beta;
+        base_on = so.base_on;
+        if (site_ok) {
+            if constexpr (is_naik_op<Link>::value) {
+                const InUpd in{r_prev, f.Ap, f.p_prev, alpha, beta};
+                hop(g, L, in, 1, mu, cb, x, y, z, t, acc);
+            } else {
+                C pf[3], pb[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    pf[c] = cg_p_next(cg_r_next(fr[c], fa[c], alpha), fp[c], beta);
+                    pb[c] = cg_p_next(cg_r_next(br[c], ba[c], alpha), bp[c], beta);
+                }
+                const double sf = nf ? -1.0 : 1.0, sb = nb ? -1.0 : 1.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    C fv = cmul(U[3 * a], pf[0]);
+                    fv = cadd(fv, cmul(U[3 * a + 1], pf[1]));
+                    fv = cadd(fv, cmul(U[3 * a + 2], pf[2]));
+                    C bv = cmulc(W[a], pb[0]);
+                    bv = cadd(bv, cmulc(W[3 + a], pb[1]));
+                    bv = cadd(bv, cmulc(W[6 + a], pb[2]));
+                    acc[a].x += sf * fv.x - sb * bv.x;
+                    acc[a].y += sf * fv.y - sb * bv.y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) part[(mu * 3 + c) * SB + lane] = acc[c];
+    __syncthreads();
+    double racc[1] = {0.0};
+    if (own) {
+        const int jj = threadIdx.x % SB;
+        C v = part[oc * SB + jj];
+#pragma unroll
+        for (int sl = 1; sl < TPS; ++sl) v = cadd(v, part[(sl * 3 + oc) * SB + jj]);
+        w_out[oi] = v;
+        if (FIRST) {
+            racc[0] = o_r.x * o_r.x + o_r.y * o_r.y;
+        } else {
+            const double2 rn = cg_r_next(o_r, o_a, alpha);
+            f.ring[(size_t)f.slot_new * 3 * g.vh + oi] = rn;
+            racc[0] = rn.x * rn.x + rn.y * rn.y;
+            if (base_on) f.x_base[oi] = make_double2(fma(alpha, o_p.x, o_x.x), fma(alpha, o_p.y, o_x.y));
+            f.p_new[oi] = cg_p_next(rn, o_p, beta);
+        }
+    }
+    block_partial<1>(racc, f.qout);
+}
+
 template <class Link, class Epi>
 void launch_tps(const Geom& g, const Link& L, const typename Link::C* in, int out_par, const Epi& epi, int tps,
                 const int* gate, hipStream_t s) {
@@ -401,6 +584,21 @@ void with_link32(const LinkSet& ls, Fn fn) {
 int dslash_grid(const Geom& g, int tps) {
     const int sb = kBlock / (tps == 1 ? 1 : (tps == 2 ? 2 : 4));
     return (g.vh + sb - 1) / sb;
+}
+
+// ---- fused multi-shift iteration (FP64), 4 threads per site
+int dslash_fused_grid(const Geom& g) { return dslash_grid(g, 4); }
+
+void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIter& f, double2* w_out, bool first,
+                         hipStream_t s) {
+    const int grid = dslash_fused_grid(g);
+    with_link64(ls, [&](auto L) {
+        using LT = decltype(L);
+        if (first)
+            k_dslash_fused<LT, true><<<grid, kBlock, 0, s>>>(g, L, f, w_out);
+        else
+            timed_launch(k_dslash_fused<LT, false>, dim3(grid), dim3(kBlock), s, g, L, f, w_out);
+    });
 }
 
 // ---- FP64 operator

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "ctx.h"
+#include "msfused.h"
 
 namespace stag {
 
@@ -100,9 +101,14 @@ void prof_end(stag_ctx* c, hipEvent_t a, int kind, EvRec& rec) {
 }
 // kernel times of iterations 0..iter (the last one only detects convergence in
 // its step kernel, after full Dslash launches)
-void prof_collect(stag_ctx* c, const EvRec& rec, int iters) {
+// Books the launches that did work: a solve that stops at step S runs S + 1
+// iterations' Dslash launches and S steps (three-launch loop), or S fused
+// D_oe launches after the eager iteration 0, S D_eo launches and S / L
+// window flushes (fused loop); launches queued behind the stop are not booked.
+void prof_collect(stag_ctx* c, const EvRec& rec, int iters, bool fused = false, int lag = 1) {
     long seen[3] = {0, 0, 0};
-    const long lim[3] = {iters + 1L, iters + 1L, (long)iters};
+    const long lim[3] = {fused ? (long)iters : iters + 1L, fused ? (long)iters : iters + 1L,
+                         fused ? (long)(iters / lag) : (long)iters};
     for (auto& q : rec) {
         const int kind = q.second;
         if (seen[kind]++ >= lim[kind]) continue;
@@ -177,13 +183,13 @@ void init_state(MsState* h, int n, const double* pole, const double* residue, do
 struct ChunkKey {
     Geom g;
     LinkSet ls;
-    const void* vec[4];
+    const void* vec[5];
     VecPtrs X, P;
     const void* st;
     const void* dpart;
     const void* qpart[2];
     double mt;
-    int tps, lag, chunk, nb2, v64, n, base;
+    int tps, lag, chunk, nb2, v64, n, base, fused, rows;
 };
 
 hipGraphExec_t cached_graph(stag_ctx* c, const ChunkKey& key) {
@@ -323,6 +329,142 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
     return STAG_OK;
 }
 
+// The fused loop (FP64, window L >= 2): iteration j is
+//   D_oe launch j: step j-1's scalars, r_j, p_j, x_base, w = D_oe p_j
+//   D_eo launch j: Ap_j and the three dots
+//   flush after iterations j with j % L == 0 (shifted systems, steps j-L..j-1)
+// with p double-buffered by parity (K.p, c->p2).  Iteration 0 is enqueued
+// eagerly, then chunks of `chunk` iterations from j = 1 (a multiple of 2 and
+// of L, so a captured chunk replays for every later one), and once the solve
+// has stopped a final flush for the steps of its last, partial window.
+constexpr int kFusedMaxBlocks = 512;
+
+stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int chunk, EvRec& rec) {
+    const Geom& g = c->g;
+    const double mt = c->st_host->mass_term;
+    const int n = c->st_host->n, base = c->st_host->base;
+    const int L = c->st_host->lag;
+    const int nb2 = dslash_fused_grid(g);   // both Dslash launches: 4 threads per site
+    const size_t n3 = (size_t)3 * g.vh;
+    double2* pbuf[2] = {c->p, c->p2};
+    const int nsh = n - 1;
+    const int rows = nsh > 0 ? std::max(1, std::min((nsh + kFlushGroup - 1) / kFlushGroup, 512 / ms_update_grid(g)))
+                             : 1;
+    auto iter_args = [&](int j) {
+        const int par = j & 1;
+        FusedIter f{};
+        f.ring = c->r;
+        f.Ap = c->Ap;
+        f.p_prev = pbuf[par ^ 1];
+        f.p_new = pbuf[par];
+        f.x_base = X.at<double2>(base);
+        f.st = c->st;
+        f.dpart = c->dpart;
+        f.qin = c->qpart[par ^ 1];
+        f.qout = c->qpart[par];
+        f.nb2 = nb2;
+        f.par = par;
+        f.n = n;
+        f.base = base;
+        f.lag = L;
+        f.slot_prev = (j + L - 1) % L;
+        f.slot_new = j % L;
+        return f;
+    };
+    // iteration 0: w = D_oe p_0 (p_0 = r_0 = b, both written by the init
+    // kernel), |r_0|^2 partials in the D_oe grid's layout into qpart[0]
+    {
+        FusedIter f0 = iter_args(0);
+        f0.p_prev = pbuf[0];
+        f0.slot_prev = 0;
+        launch_dslash_fused(g, ls, f0, c->w_o, true, c->s);
+        launch_dslash_cg(g, ls, c->w_o, pbuf[0], c->r, c->Ap, &c->st->done[1], c->dpart, 4, c->s, mt);
+    }
+    int it_issued = 1;
+    auto enqueue_chunk = [&]() {
+        for (int it = 0; it < chunk; ++it, ++it_issued) {
+            const int j = it_issued, par = j & 1;
+            const FusedIter f = iter_args(j);
+            hipEvent_t a;
+            prof_begin(c, &a);
+            launch_dslash_fused(g, ls, f, c->w_o, false, c->s);
+            prof_end(c, a, 0, rec);
+            prof_begin(c, &a);
+            launch_dslash_cg(g, ls, c->w_o, pbuf[par], c->r + (size_t)(j % L) * n3, c->Ap, &c->st->done[par ^ 1],
+                             c->dpart, 4, c->s, mt);
+            prof_end(c, a, 1, rec);
+            if (j % L == 0 && nsh > 0) {
+                prof_begin(c, &a);
+                launch_ms_flush(g, c->r, X, P, c->st, &c->st->done[par ^ 1], n, base, L, false, rows, c->s);
+                prof_end(c, a, 2, rec);
+            }
+        }
+    };
+    hipGraphExec_t exec = nullptr;
+    if (c->use_graph && !c->prof_on && chunk % 2 == 0 && chunk % L == 0) {
+        ChunkKey key;
+        std::memset(&key, 0, sizeof(key));
+        key.g = g;
+        key.ls = ls;
+        key.vec[0] = c->r;
+        key.vec[1] = pbuf[0];
+        key.vec[2] = c->Ap;
+        key.vec[3] = c->w_o;
+        key.vec[4] = pbuf[1];
+        key.X = X;
+        key.P = P;
+        key.st = c->st;
+        key.dpart = c->dpart;
+        key.qpart[0] = c->qpart[0];
+        key.qpart[1] = c->qpart[1];
+        key.mt = mt;
+        key.tps = 4;
+        key.lag = L;
+        key.n = n;
+        key.base = base;
+        key.chunk = chunk;
+        key.nb2 = nb2;
+        key.v64 = 1;
+        key.fused = 1;
+        key.rows = rows;
+        exec = cached_graph(c, key);
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            HIP_OR_FAIL(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
+            enqueue_chunk();
+            HIP_OR_FAIL(c, hipStreamEndCapture(c->s, &graph));
+            const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(c, STAG_ERR_HIP, "hipGraphInstantiate failed");
+            store_graph(c, key, exec);
+            it_issued = 1;
+        }
+    }
+    auto issue_chunk = [&](int slot) {
+        if (exec) {
+            hipGraphLaunch(exec, c->s);
+            it_issued += chunk;
+        } else {
+            enqueue_chunk();
+        }
+        // the flag the next D_oe launch would read
+        hipMemcpyAsync(&c->done_host[slot], &c->st->done[it_issued & 1], sizeof(int), hipMemcpyDeviceToHost, c->s);
+        hipEventRecord(c->chunk_ev[slot], c->s);
+    };
+    issue_chunk(0);
+    issue_chunk(1);
+    int cur = 0;
+    for (;;) {
+        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
+        if (c->done_host[cur]) break;
+        issue_chunk(cur);
+        cur ^= 1;
+    }
+    if (nsh > 0) launch_ms_flush(g, c->r, X, P, c->st, nullptr, n, base, L, true, rows, c->s);
+    HIP_OR_FAIL(c, hipGetLastError());
+    return STAG_OK;
+}
+
 // Multi-shift CG in Krylov precision V (x_k always FP64).
 template <class V>
 stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_rational* r, double tol, int maxiter,
@@ -335,7 +477,12 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
     MsState* h = c->st_host;
     int base;
     init_state(h, n, r->pole, r->residue, r->c0, mass, tol, maxiter, base);
-    h->lag = n > 1 ? c->lag : 1;
+    // the fused loop (FP64, window >= 2; it keeps r_{j-1} and r_j in the ring
+    // at once): by default on grids of at most kFusedMaxBlocks Dslash blocks,
+    // where an iteration is latency-bound; with on = 2 at every size
+    const bool fused = sizeof(V) == sizeof(double2) && c->lag >= 2 &&
+                       (c->fused == 2 || (c->fused == 1 && dslash_fused_grid(g) <= kFusedMaxBlocks));
+    h->lag = fused ? c->lag : (n > 1 ? c->lag : 1);
     HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
     Krylov<V> K(c);
     VecPtrs X{}, P{};
@@ -344,7 +491,12 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
         P.p[k] = (V*)c->pool_p + (size_t)k * 3 * g.vh;
     }
     launch_ms_init<V>(g, b, K.r, K.p, X, P, c->st, c->qpart[0], c->s);
-    if ((e = run_iterations<V>(c, ls, K, X, P, c->chunk, rec, [](int) {}))) return e;
+    res.fused = fused;
+    if (fused)
+        e = run_fused(c, ls, X, P, c->chunk, rec);
+    else
+        e = run_iterations<V>(c, ls, K, X, P, c->chunk, rec, [](int) {});
+    if (e) return e;
     HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
     const MsIter& f = h->fin;
@@ -437,7 +589,7 @@ stag_status ms_solve(stag_ctx* c, double mass, const stag_rational* r, double to
     EvRec rec;
     c->prof_used = 0;
     if ((e = ms_solve_t<double2>(c, ls, mass, r, tol, maxiter, b, x, ipp_out, res, rec))) return e;
-    prof_collect(c, rec, res.iters);
+    prof_collect(c, rec, res.iters, res.fused, c->st_host->lag);
     if (want_resid) {
         true_residuals(c, ls, mass, r, b, x);
         HIP_OR_FAIL(c, hipMemcpyAsync(c->st_host, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));

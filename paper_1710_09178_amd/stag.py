@@ -122,6 +122,7 @@ def load_library() -> ctypes.CDLL:
                                             ctypes.POINTER(CMixedOpts), ctypes.POINTER(CSolveInfo)]),
         "stag_set_link_format": (S, [H, I]),
         "stag_set_naik": (S, [H, D, D]),
+        "stag_set_fused_iteration": (S, [H, I]),
         "stag_profile_samples": (S, [H, I, ctypes.POINTER(ctypes.c_float), I, ctypes.POINTER(I)]),
         "stag_mdagm_noalloc": (S, [H, P, P, D]),
         "stag_fermion_action": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(D),
@@ -456,6 +457,10 @@ class Lattice:
     # ---- measurement / tuning
     def set_shift_window(self, lag: int):
         self._check(self.lib.stag_set_shift_window(self.h, int(lag)))
+
+    def set_fused_iteration(self, mode):
+        """0 / False: three-launch loop; 1 / True: fused on small grids (default); 2: fused at every size."""
+        self._check(self.lib.stag_set_fused_iteration(self.h, int(mode)))
 
     def set_graphs(self, on: bool):
         self._check(self.lib.stag_set_graphs(self.h, int(bool(on))))

@@ -83,13 +83,24 @@ def test_full_size_32c8_twelve_poles():
     assert np.allclose(info["true_resid"], res, rtol=1e-2, atol=1e-14)
     expect_sum = rat["c0"] * b + sum(c * x for c, x in zip(rat["residue"], xs))
     assert rel_err(s, expect_sum) < 1e-13
-    # the default window (8) against per-iteration updates, bitwise, at the
-    # full size where the step kernel runs many more blocks than the GPU holds
+    # the three-launch loop (the default at this size): window 8 against
+    # per-iteration updates, bitwise, at the full size where the step kernel
+    # runs many more blocks than the GPU holds; and the fused loop forced at
+    # this size against it, to rounding
+    lat.set_fused_iteration(2)
+    xs, _, info = _solve(lat, dims, 0.005, rat, 1e-10, b)
+    res = true_residuals(lambda v: dirac.apply_A(U, v, dims, 0.005), b, rat["pole"], xs)
+    assert res.max() < 1e-10, res
+    lat.set_fused_iteration(0)
+    xs8, _, info8 = _solve(lat, dims, 0.005, rat, 1e-10, b)
     lat.set_shift_window(1)
     xs1, s1, info1 = _solve(lat, dims, 0.005, rat, 1e-10, b)
-    assert info1["iters"] == info["iters"]
-    for x, x1 in zip(xs, xs1):
+    assert info1["iters"] == info8["iters"]
+    for x, x1 in zip(xs8, xs1):
         assert np.array_equal(x, x1)
+    assert abs(info8["iters"] - info["iters"]) <= 1
+    for x, x8 in zip(xs, xs8):
+        assert np.linalg.norm(x - x8) <= 1e-9 * np.linalg.norm(x8)
 
 
 def test_krylov_bound_unit_gauge():
@@ -156,21 +167,23 @@ def test_error_paths():
     assert e.value.code == STAG_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_shift_window_does_not_change_results(mixed):
+@pytest.mark.parametrize("mixed,fused", [(False, False), (True, False), (False, True)])
+def test_shift_window_does_not_change_results(mixed, fused):
     """Deferring the shifted updates over windows of 1..8 iterations keeps the
     arithmetic and its order: every solution is bitwise the same, including
-    windows that do not divide the iteration count (8x6x4x10, ragged tail)."""
+    windows that do not divide the iteration count (8x6x4x10, ragged tail),
+    in the three-launch loop and (windows 2..8) in the fused one."""
     dims = (8, 6, 4, 10)
     rng = synth.make_rng(0, 7)
     U = synth.random_su3_near_identity(dims, 0.4, rng)
     b = synth.gaussian_half_vector(dims, rng)
     lat = lattice(dims, U)
+    lat.set_fused_iteration(fused)
     rat = _rat(C0_POLES, np.linspace(0.5, 2.0, 8), c0=0.25)
     bd = lat.vec_import(dev(b), 0)
     ref = None
-    for lag in (1, 2, 3, 4, 5, 8):
-        log(f"shift window {lag} mixed={mixed}")
+    for lag in ((2, 3, 4, 5, 7, 8) if fused else (1, 2, 3, 4, 5, 8)):
+        log(f"shift window {lag} mixed={mixed} fused={fused}")
         lat.set_shift_window(lag)
         xs = [lat.new_vec() for _ in rat["pole"]]
         if mixed:
@@ -238,3 +251,51 @@ def test_pole_count_edge_cases(poles):
         assert np.linalg.norm(x - xr) <= 2e-12 * kappa * np.linalg.norm(xr)
     if len(poles) == 3:
         assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (16, 16, 16, 8)])
+def test_fused_iteration_matches_three_launch_loop(dims):
+    """The fused loop (base update folded into the D_oe launch, one flush per
+    window) against the three-launch loop: the same iteration counts within
+    one, every solution equal to 1e-9 relative, and the oracle's true
+    residuals below tol."""
+    log(f"fused vs three-launch loop dims={dims}")
+    rng = synth.make_rng(0, 13)
+    U = synth.random_su3_near_identity(dims, 0.3, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm050_n12_m0.02")
+    lat = lattice(dims, U)
+    out = {}
+    for fused in (True, False):
+        lat.set_fused_iteration(fused)
+        out[fused] = _solve(lat, dims, 0.02, rat, 1e-10, b)
+    xs, _, info = out[True]
+    xu, _, infou = out[False]
+    assert abs(info["iters"] - infou["iters"]) <= 1
+    assert all(abs(a - c) <= 1 for a, c in zip(info["iters_per_pole"], infou["iters_per_pole"]))
+    for x, y in zip(xs, xu):
+        assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y)
+    res = true_residuals(lambda v: dirac.apply_A(U, v, dims, 0.02), b, rat["pole"], xs)
+    assert res.max() < 1e-10, res
+
+
+@pytest.mark.parametrize("maxiter", [1, 5, 8, 9, 13])
+def test_fused_stop_inside_a_window(maxiter):
+    """Stopping at maxiter in every position of the 8-iteration window (the
+    final flush applies the partial window): the same solutions as the
+    three-launch loop stopped at the same iteration, to rounding."""
+    dims = (8, 6, 4, 10)
+    rng = synth.make_rng(0, 14)
+    U = synth.random_su3_near_identity(dims, 0.4, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    lat = lattice(dims, U)
+    bd = lat.vec_import(dev(b), 0)
+    rat = _rat(C0_POLES)
+    got = {}
+    for fused in (True, False):
+        lat.set_fused_iteration(fused)
+        xs = [lat.new_vec() for _ in rat["pole"]]
+        info = lat.multishift_solve(0.05, rat, 1e-10, maxiter, bd, xs, None, allow_not_converged=True)
+        assert info["iters"] == maxiter
+        got[fused] = np.stack([host(x) for x in xs])
+    assert np.abs(got[True] - got[False]).max() <= 1e-12 * np.abs(got[False]).max()
