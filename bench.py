@@ -576,13 +576,19 @@ def memory_check(lat, bd, vh, reps=20):
         info = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=False)
         solve_ms[fz] = ((time.perf_counter() - t0) * 1e3, info)
     ms, info = solve_ms[False]
-    # the plain D_oe kernel inside the three-launch loop
-    big_lat.profile_enable(3 * (info["iters"] + 64))
-    chk = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=True)
+    # the plain D_oe kernel inside the three-launch loop, links streamed
+    # non-temporally (the default at this size) and with plain loads
     vh48 = big_lat.Vh
-    doe = _pct(big_lat.profile_samples(0))
-    deo = _pct(big_lat.profile_samples(1))
-    big_lat.profile_enable(0)
+    doe_plain = None
+    for mode in (0, 1):
+        big_lat.set_link_streaming(mode)
+        big_lat.profile_enable(3 * (info["iters"] + 64))
+        chk = big_lat.multishift_solve(MASS, rat, TOL, 100000, bdev, xs, None, true_resid=True)
+        doe = _pct(big_lat.profile_samples(0))
+        deo = _pct(big_lat.profile_samples(1))
+        big_lat.profile_enable(0)
+        if mode == 0:
+            doe_plain = doe
     base = int(np.argmin(rat["pole"]))
     out["solve_48c3x16"] = {
         "ms_per_solve_fused": round(solve_ms[True][0], 3), "ms_per_solve": round(ms, 3),
@@ -590,6 +596,8 @@ def memory_check(lat, bd, vh, reps=20):
         "value_GB/s": round(solve_bytes(vh48, info["iters"], info["iters_per_pole"], base, 8) / (ms * 1e-3) / 1e9, 1),
         "links_GB": round(2 * 4 * 144 * vh48 / 1e9, 3),
         "dslash_oe_us": doe, "dslash_oe_GB/s_at_p50": round(B_DOE * vh48 / (doe["p50"] * 1e-6) / 1e9, 1),
+        "dslash_oe_plain_link_loads_us": doe_plain,
+        "dslash_oe_plain_link_loads_GB/s_at_p50": round(B_DOE * vh48 / (doe_plain["p50"] * 1e-6) / 1e9, 1),
         "dslash_oe_frac_at_p50": round(B_DOE * vh48 / (doe["p50"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
         "dslash_eo_cg_us": deo, "dslash_eo_cg_GB/s_at_p50": round(B_DEO_CG * vh48 / (deo["p50"] * 1e-6) / 1e9, 1)}
     del big_lat, xs, bdev
@@ -723,11 +731,13 @@ def batched_form(per_class=16, nrhs=4, reps=2):
             for i, d in enumerate(dims) for j in range(nrhs)]
     b = torch.from_numpy(np.concatenate([v.reshape(-1) for v in srcs])).cuda()
     B.set_shift_window(8)
-    tuned = B.tune(0)
+    tuned, choice = B.autotune(0)
     out = {"workload": f"{len(dims)} lattices (16 each of 8^4, 12^3x6, 16^3x8, 24^3x6) x {nrhs} right-hand "
                        f"sides x 12 poles of x^(-1/4), masses U[0.005, 0.05], tol 1e-10",
            "systems": len(dims) * nrhs, "sites": int(sum(np.prod(d) for d in dims)),
-           "tune_us_tps_1_2_4_8": [round(u, 2) for u in tuned]}
+           "autotune_us": dict(zip(["tps1", "tps2", "tps4", "tps1_nt", "tps2_nt", "tps4_nt", "tps8"],
+                                   [round(u, 2) for u in tuned])),
+           "autotune_choice": {"threads_per_site": choice[0], "nontemporal_links": choice[1]}}
     for name, prec in (("fp64", 0), ("mixed_fp32_fp64", 1)):
         B.solve(masses, rat, b, precision=prec, true_resid=False)
         torch.cuda.synchronize()

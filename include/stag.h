@@ -449,6 +449,20 @@ stag_status stag_batch_set_shift_window(stag_batch_handle b, int lag);
  * for 1, 2, 4 and 8 threads per site (precision 0 or 1) and keeps the
  * fastest.  us_out: NULL or host [4] microseconds per application. */
 stag_status stag_batch_tune(stag_batch_handle b, int precision, double* us_out);
+/* Autotuner with a persisted cache: the batched operator is timed (precision
+ * 0 or 1, 10 applications each) for every work split -- 1, 2 or 4 threads per
+ * site (tiles of 256, 128, 64 sites) with plain or non-temporal link loads,
+ * and 8 lanes per site (one hop per lane) -- and the fastest is kept.
+ * cache_path (NULL or "" for none): a text file of lines
+ * "key threads_per_site link_nt microseconds", key = device architecture,
+ * precision, right-hand sides and the multiset of lattice shapes; a batch
+ * whose key is in the file takes its entry without timing, a tuned one is
+ * appended.  us_out: NULL or host [7] microseconds in the candidate order
+ * (tps 1, 2, 4 plain; 1, 2, 4 non-temporal; 8), -1 when read from the cache.
+ * choice_out: NULL or host [3] = {threads per site, link_nt, from cache}.
+ * Results of the solver do not depend on the choice. */
+stag_status stag_batch_autotune(stag_batch_handle b, int precision, const char* cache_path, double* us_out,
+                                int* choice_out);
 /* Set the Dslash work split directly: 1, 2 or 4 threads per site share the
  * four directions of a site through LDS; 8 lanes per site take one hop each
  * and combine by lane exchanges.  Results agree to rounding.  Tuning. */
@@ -483,6 +497,13 @@ stag_status stag_profile_samples(stag_handle h, int kind, float* us_out, int cap
  * trees differ, so results agree to rounding, not bitwise.  Returns
  * STAG_ERR_INVALID_ARG for a mode outside 0..2. */
 stag_status stag_set_fused_iteration(stag_handle h, int mode);
+/* How every FP64 operator application of h loads the links (and long links):
+ * mode 1 (default) with non-temporal loads when the FP64 field(s) exceed
+ * 512 MB -- they cannot stay in the 256 MB Infinity Cache between Dslash
+ * launches, and streaming them past it keeps the shared vectors cached --
+ * and plain loads otherwise; 0 always plain, 2 always non-temporal.  Results
+ * are bitwise the same in every mode.  STAG_ERR_INVALID_ARG for other modes. */
+stag_status stag_set_link_streaming(stag_handle h, int mode);
 /* Solvers replay each chunk of iterations from a hipGraph captured on first
  * use (kernel nodes only; up to 8 cached per handle, keyed by every launch
  * argument) unless profiling or reliable updates need per-launch work.  on = 0

@@ -240,6 +240,7 @@ stag_status stag_create(stag_handle* out, const int dims[4], void* hip_stream) {
     if (c->tps != 1 && c->tps != 2 && c->tps != 4) c->tps = 2;
     if (const char* e = std::getenv("STAG_CHUNK")) c->chunk = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("STAG_FUSED")) c->fused = std::max(0, std::min(2, std::atoi(e)));
+    if (const char* e = std::getenv("STAG_LINK_NT")) c->link_nt = std::max(0, std::min(2, std::atoi(e)));
     c->user = (hipStream_t)hip_stream;
     auto bail = [&](stag_status s) {
         g_create_err = c->err;
@@ -988,6 +989,16 @@ stag_status stag_set_fused_iteration(stag_handle c, int on) {
     if (e) return e;
     if (on < 0 || on > 2) return fail(c, STAG_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
     c->fused = on;
+    return STAG_OK;
+}
+
+// How the FP64 operator loads its links: 0 plain loads, 1 non-temporal when
+// the field exceeds the Infinity Cache (default), 2 always non-temporal.
+stag_status stag_set_link_streaming(stag_handle c, int mode) {
+    stag_status e = check_common(c, false);
+    if (e) return e;
+    if (mode < 0 || mode > 2) return fail(c, STAG_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+    c->link_nt = mode;
     return STAG_OK;
 }
 

@@ -70,6 +70,7 @@ struct BatchDev {
     int ntiles;
     int tile_sites;
     int nrhs;
+    int link_nt;   // links streamed with non-temporal loads (fields beyond the Infinity Cache)
 };
 
 // Launchers (batch.hip).  V = double2 (FP64 links, FP64 Krylov vectors) or

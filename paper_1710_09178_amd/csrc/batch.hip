@@ -3,6 +3,8 @@
 // every right-hand side of its lattice (links read once per nrhs vectors).
 // Scalars are per system (lattice, right-hand side); reductions are per tile
 // and are summed over the lattice's tiles by the consuming kernel.
+#include <type_traits>
+
 #include "batch.h"
 
 namespace stag {
@@ -19,6 +21,28 @@ template <>
 struct BPrec<float2> {
     using R = float;
 };
+
+// a link entry; NT: non-temporal (link fields larger than the Infinity Cache)
+template <bool NT>
+__device__ __forceinline__ double2 bload(const double2* p) {
+    if constexpr (NT) {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v t = __builtin_nontemporal_load((const d2v*)p);
+        return make_double2(t.x, t.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ float2 bload(const float2* p) {
+    if constexpr (NT) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        const f2v t = __builtin_nontemporal_load((const f2v*)p);
+        return make_float2(t.x, t.y);
+    } else {
+        return *p;
+    }
+}
 
 __device__ __forceinline__ void bhop_geometry(const Geom& g, int mu, int x, int y, int z, int t, int& cbf, int& cbb,
                                               bool& nf, bool& nb) {
@@ -126,7 +150,7 @@ struct BEpiResid {
 
 // One block per tile: TPS threads per site split the 4 directions; every
 // thread applies its links to all right-hand sides of the lattice.
-template <int TPS, class V, class Epi>
+template <int TPS, class V, class Epi, bool NT>
 __global__ __launch_bounds__(kBlock) void k_bdslash(BatchDev bd, const V* __restrict__ links, const V* __restrict__ in,
                                                     int out_par, Epi epi, const int* __restrict__ inst_done) {
     constexpr int SB = kBlock / TPS;
@@ -161,9 +185,9 @@ __global__ __launch_bounds__(kBlock) void k_bdslash(BatchDev bd, const V* __rest
             const V* uf = lk + link_off(g, out_par, mu, 0) + cb;
             const V* ub = lk + link_off(g, 1 - out_par, mu, 0) + cbb;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = uf[(size_t)e * g.vh];
+            for (int e = 0; e < 9; ++e) U[e] = bload<NT>(uf + (size_t)e * g.vh);
 #pragma unroll
-            for (int e = 0; e < 9; ++e) W[e] = ub[(size_t)e * g.vh];
+            for (int e = 0; e < 9; ++e) W[e] = bload<NT>(ub + (size_t)e * g.vh);
             const Rl sf = nf ? Rl(-1) : Rl(1);
             const Rl sb = nb ? Rl(-1) : Rl(1);
 #pragma unroll
@@ -290,12 +314,22 @@ __global__ __launch_bounds__(kBlock) void k_bdslash8(BatchDev bd, const V* __res
 template <class V, class Epi>
 void bdslash_tps(const BatchDev& bd, int tps, const V* links, const V* in, int out_par, const Epi& epi,
                  const int* inst_done, hipStream_t s) {
-    switch (tps) {
-        case 1: k_bdslash<1, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
-        case 2: k_bdslash<2, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
-        case 8: k_bdslash8<V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
-        default: k_bdslash<4, V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+    if (tps == 8) {
+        k_bdslash8<V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done);
+        return;
     }
+    auto go = [&](auto nt) {
+        constexpr bool NT = decltype(nt)::value;
+        switch (tps) {
+            case 1: k_bdslash<1, V, Epi, NT><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+            case 2: k_bdslash<2, V, Epi, NT><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+            default: k_bdslash<4, V, Epi, NT><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+        }
+    };
+    if (bd.link_nt)
+        go(std::true_type{});
+    else
+        go(std::false_type{});
 }
 
 // r = p = p_k = b, x_k = 0, per-rhs partials of |b|^2

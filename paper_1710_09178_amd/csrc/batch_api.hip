@@ -4,7 +4,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -28,6 +32,7 @@ struct stag_batch {
     BInst* inst_d = nullptr;
     BTile* tiles_d = nullptr;
     int tps = 2;
+    int link_nt = -1;            // links loaded non-temporally: -1 by field size, 0 no, 1 yes (tuned)
     int lag = 8;                 // shift-update window (divides the 16-iteration chunk)
     int tiles_cap = 0;
     size_t total_vh = 0;
@@ -117,7 +122,12 @@ stag_status build_tiles(stag_batch* c) {
 }
 
 BatchDev bdev(const stag_batch* c) {
-    return BatchDev{c->inst_d, c->tiles_d, (int)c->tiles_h.size(), kBlock / c->tps, c->nrhs};
+    // the links of all lattices are streamed from HBM by every operator
+    // application once they exceed what the Infinity Cache keeps (FP64:
+    // 1.2 GB for the 64-lattice batch; the single-lattice operator's rule)
+    const size_t link_bytes = (size_t)72 * c->total_vh * 16;
+    const int nt = c->link_nt >= 0 ? c->link_nt : (link_bytes > ((size_t)512 << 20) ? 1 : 0);
+    return BatchDev{c->inst_d, c->tiles_d, (int)c->tiles_h.size(), kBlock / c->tps, c->nrhs, nt};
 }
 
 stag_status ensure_bpool(stag_batch* c, int n) {
@@ -507,6 +517,97 @@ stag_status stag_batch_set_tps(stag_batch_handle c, int tps) {
     if (tps != 1 && tps != 2 && tps != 4 && tps != 8)
         return bfail(c, STAG_ERR_INVALID_ARG, "threads per site must be 1, 2, 4 or 8");
     c->tps = tps;
+    return build_tiles(c);
+}
+
+// The autotuner's key for a batch: device, precision, right-hand sides and the
+// multiset of lattice shapes.
+std::string tune_key(stag_batch* c, int precision) {
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) dev = prop.gcnArchName;
+    for (auto& ch : dev)
+        if (ch == ' ' || ch == '|') ch = '_';
+    std::map<std::string, int> shapes;
+    for (const BInst& I : c->inst_h) {
+        char b[64];
+        snprintf(b, sizeof b, "%dx%dx%dx%d", I.g.nx, I.g.ny, I.g.nz, I.g.nt);
+        shapes[b] += 1;
+    }
+    std::ostringstream k;
+    k << dev << "|p" << precision << "|r" << c->nrhs << "|";
+    for (auto& kv : shapes) k << kv.first << "*" << kv.second << ",";
+    return k.str();
+}
+
+extern "C" stag_status stag_batch_autotune(stag_batch_handle c, int precision, const char* cache_path, double* us_out,
+                                           int* choice_out) {
+    if (!c) return bfail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
+    if (precision != 0 && precision != 1) return bfail(c, STAG_ERR_INVALID_ARG, "precision must be 0 or 1");
+    // candidates: threads per site (tile of 256/tps sites) x link loads
+    const int cand_tps[7] = {1, 2, 4, 1, 2, 4, 8};
+    const int cand_nt[7] = {0, 0, 0, 1, 1, 1, 0};
+    if (us_out)
+        for (int q = 0; q < 7; ++q) us_out[q] = -1.0;
+    const std::string key = tune_key(c, precision);
+    stag_status e;
+    if (cache_path && *cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream ls(line);
+            std::string k;
+            int tps = 0, nt = -1;
+            if ((ls >> k >> tps >> nt) && k == key && (tps == 1 || tps == 2 || tps == 4 || tps == 8) &&
+                (nt == 0 || nt == 1)) {
+                c->tps = tps;
+                c->link_nt = nt;
+                if (choice_out) choice_out[0] = tps, choice_out[1] = nt, choice_out[2] = 1;
+                return build_tiles(c);
+            }
+        }
+    }
+    if (precision == 1 && (e = ensure_links32(c))) return e;
+    hipEvent_t a, b;
+    BHIP(c, hipEventCreate(&a));
+    BHIP(c, hipEventCreate(&b));
+    double best = 1e300;
+    int best_q = 0;
+    for (int q = 0; q < 7; ++q) {
+        c->tps = cand_tps[q];
+        c->link_nt = cand_nt[q];
+        if ((e = build_tiles(c))) return e;
+        const BatchDev bd = bdev(c);
+        auto run = [&]() {
+            if (precision == 0)
+                launch_bdslash<double2>(bd, c->tps, c->links64, c->p, c->w, 1, nullptr, c->s);
+            else
+                launch_bdslash<float2>(bd, c->tps, c->links32, (const float2*)c->p, (float2*)c->w, 1, nullptr, c->s);
+        };
+        run();
+        hipEventRecord(a, c->s);
+        const int reps = 10;
+        for (int i = 0; i < reps; ++i) run();
+        hipEventRecord(b, c->s);
+        BHIP(c, hipEventSynchronize(b));
+        float ms = 0;
+        hipEventElapsedTime(&ms, a, b);
+        const double us = 1e3 * ms / reps;
+        if (us_out) us_out[q] = us;
+        if (us < best) {
+            best = us;
+            best_q = q;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    c->tps = cand_tps[best_q];
+    c->link_nt = cand_nt[best_q];
+    if (choice_out) choice_out[0] = c->tps, choice_out[1] = c->link_nt, choice_out[2] = 0;
+    if (cache_path && *cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << key << " " << c->tps << " " << c->link_nt << " " << best << "\n";
+    }
     return build_tiles(c);
 }
 

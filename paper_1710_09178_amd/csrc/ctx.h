@@ -59,6 +59,7 @@ struct stag_ctx {
     int lag = 8;                         // shift-update window of the multi-shift solver
     int use_graph = 1;                   // replay iteration chunks from captured hipGraphs
     int fused = 1;                       // FP64 solves fold the base update into the D_oe launch
+    int link_nt = 1;                     // non-temporal FP64 link loads: 0 never, 1 by field size, 2 always
     // captured iteration chunks, keyed by every argument their launches take
     struct ChunkGraph {
         std::vector<unsigned char> key;

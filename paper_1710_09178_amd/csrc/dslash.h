@@ -18,7 +18,7 @@ struct LinkSet {
     const float2* s18;
     const void* h12;         // __half2 [2][4][6][Vh]
     int naik;
-    int pad_;                // keeps the struct free of implicit padding (graph keys compare bytes)
+    int nt;                  // FP64 links loaded non-temporally (fields larger than the Infinity Cache)
     double c1, c3;
     const double2* ld18;
     const double2* ld12;
@@ -48,6 +48,10 @@ struct FusedIter;
 int dslash_fused_grid(const Geom& g);
 void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIter& f, double2* w_out, bool first,
                          hipStream_t s);
+// the D_eo launch of the fused loop: launch_dslash_cg with 4 threads per site
+// and the operands' loads issued before the stop flag is tested
+void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
+                            double2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term);
 
 // FP32 operator (format fmt32)
 void launch_dslash32(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int out_par, int tps,

@@ -38,28 +38,46 @@ __device__ __forceinline__ void rebuild_row2(C (&m)[9]) {
     m[8] = cconj(csub(cmul(m[0], m[4]), cmul(m[1], m[3])));
 }
 
-struct LinkD18 {
+// FP64 link entry; NT: a non-temporal load, for link fields larger than the
+// Infinity Cache, which every Dslash streams once from HBM: they then do not
+// evict the vectors the neighbours share.
+template <bool NT>
+__device__ __forceinline__ double2 link_entry(const double2* p) {
+    if constexpr (NT) {
+        typedef double d2v __attribute__((ext_vector_type(2)));
+        const d2v t = __builtin_nontemporal_load((const d2v*)p);
+        return make_double2(t.x, t.y);
+    } else {
+        return *p;
+    }
+}
+
+template <bool NT>
+struct LinkD18T {
     using C = double2;
     using R = double;
     const double2* __restrict__ u;
     __device__ __forceinline__ void load(const Geom& g, int par, int mu, int cb, C (&m)[9]) const {
         const double2* p = u + link_off(g, par, mu, 0) + cb;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) m[e] = p[(size_t)e * g.vh];
+        for (int e = 0; e < 9; ++e) m[e] = link_entry<NT>(p + (size_t)e * g.vh);
     }
 };
+using LinkD18 = LinkD18T<false>;
 
-struct LinkD12 {
+template <bool NT>
+struct LinkD12T {
     using C = double2;
     using R = double;
     const double2* __restrict__ u;
     __device__ __forceinline__ void load(const Geom& g, int par, int mu, int cb, C (&m)[9]) const {
         const double2* p = u + link12_off(g, par, mu, 0) + cb;
 #pragma unroll
-        for (int e = 0; e < 6; ++e) m[e] = p[(size_t)e * g.vh];
+        for (int e = 0; e < 6; ++e) m[e] = link_entry<NT>(p + (size_t)e * g.vh);
         rebuild_row2(m);
     }
 };
+using LinkD12 = LinkD12T<false>;
 
 struct LinkS18 {
     using C = float2;
@@ -403,10 +421,9 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
     using C = double2;
     constexpr int TPS = 4, SB = kBlock / TPS;
     MsState* st = f.st;
-    if (!FIRST && st->done[f.par]) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->done[f.par ^ 1] = 1;
-        return;
-    }
+    // the stop flag is tested once this launch's other loads are in flight
+    // (a stopped solve's queued launches pay one round trip for them)
+    const int stopped = FIRST ? 0 : st->done[f.par];
     __shared__ C part[TPS * 3 * SB];
     __shared__ double lds[16];
     const double2* r_prev = f.ring + (size_t)f.slot_prev * 3 * g.vh;
@@ -469,6 +486,10 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
                     bp[c] = f.p_prev[jb];
                 }
             }
+        }
+        if (stopped) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) st->done[f.par ^ 1] = 1;
+            return;
         }
         double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -540,6 +561,89 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
     block_partial<1>(racc, f.qout);
 }
 
+// D_eo launch of the fused loop: Ap = mt p - D_eo w and the block partials of
+// <p,Ap>, <r,Ap>, <Ap,Ap> (the arithmetic of the EpiCG epilogue), with 4
+// threads per site and every load -- links, the neighbours' w, the owned
+// site's p and r -- issued before the stop flag is tested.
+template <class Link>
+__global__ __launch_bounds__(kBlock) void k_dslash_cg_fused(Geom g, Link L, const double2* __restrict__ w,
+                                                            const double2* __restrict__ p,
+                                                            const double2* __restrict__ r, double2* __restrict__ Ap,
+                                                            double* __restrict__ part, double mt,
+                                                            const int* __restrict__ gate) {
+    using C = double2;
+    constexpr int TPS = 4, SB = kBlock / TPS;
+    const int stopped = *gate;
+    __shared__ C lpart[TPS * 3 * SB];
+    const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
+    const int tile = xcd_tile_slab(blockIdx.x, gridDim.x, g, SB);
+    const int cb = tile * SB + lane;
+    const bool site_ok = cb < g.vh;
+    int x = 0, y = 0, z = 0, t = 0, cbf = 0, cbb = 0;
+    bool nf = false, nb = false;
+    if (site_ok) {
+        cb_coords(g, 0, cb, x, y, z, t);
+        hop_geometry(g, mu, x, y, z, t, cbf, cbb, nf, nb);
+    }
+    const int oc = threadIdx.x / SB, osite = tile * SB + (threadIdx.x % SB);
+    const bool own = threadIdx.x < 3 * SB && osite < g.vh;
+    const size_t oi = (size_t)oc * g.vh + osite;
+    double2 o_p = {0, 0}, o_r = {0, 0};
+    if (own) {
+        o_p = p[oi];
+        o_r = r[oi];
+    }
+    C acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = C{0, 0};
+    if constexpr (is_naik_op<Link>::value) {
+        if (stopped) return;
+        if (site_ok) hop(g, L, w, 0, mu, cb, x, y, z, t, acc);
+    } else {
+        C U[9], W[9], pf[3], pb[3];
+        if (site_ok) {
+            L.load(g, 0, mu, cb, U);
+            L.load(g, 1, mu, cbb, W);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pf[c] = w[(size_t)c * g.vh + cbf];
+                pb[c] = w[(size_t)c * g.vh + cbb];
+            }
+        }
+        if (stopped) return;
+        if (site_ok) {
+            const double sf = nf ? -1.0 : 1.0, sb = nb ? -1.0 : 1.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                C fv = cmul(U[3 * a], pf[0]);
+                fv = cadd(fv, cmul(U[3 * a + 1], pf[1]));
+                fv = cadd(fv, cmul(U[3 * a + 2], pf[2]));
+                C bv = cmulc(W[a], pb[0]);
+                bv = cadd(bv, cmulc(W[3 + a], pb[1]));
+                bv = cadd(bv, cmulc(W[6 + a], pb[2]));
+                acc[a].x += sf * fv.x - sb * bv.x;
+                acc[a].y += sf * fv.y - sb * bv.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lpart[(mu * 3 + c) * SB + lane] = acc[c];
+    __syncthreads();
+    double dots[3] = {0.0, 0.0, 0.0};
+    if (own) {
+        const int jj = threadIdx.x % SB;
+        C v = lpart[oc * SB + jj];
+#pragma unroll
+        for (int sl = 1; sl < TPS; ++sl) v = cadd(v, lpart[(sl * 3 + oc) * SB + jj]);
+        const C a = C{mt * o_p.x - v.x, mt * o_p.y - v.y};
+        Ap[oi] = a;
+        dots[0] = o_p.x * a.x + o_p.y * a.y;
+        dots[1] = o_r.x * a.x + o_r.y * a.y;
+        dots[2] = a.x * a.x + a.y * a.y;
+    }
+    block_partial<3>(dots, part);
+}
+
 template <class Link, class Epi>
 void launch_tps(const Geom& g, const Link& L, const typename Link::C* in, int out_par, const Epi& epi, int tps,
                 const int* gate, hipStream_t s) {
@@ -552,18 +656,27 @@ void launch_tps(const Geom& g, const Link& L, const typename Link::C* in, int ou
 }
 
 // dispatch on the storage format of the operator and on the improvement
-template <class Fn>
-void with_link64(const LinkSet& ls, Fn fn) {
+template <bool NT, class Fn>
+void with_link64_nt(const LinkSet& ls, Fn fn) {
+    using D18 = LinkD18T<NT>;
+    using D12 = LinkD12T<NT>;
     if (ls.naik) {
         if (ls.fmt64 == STAG_LINKS_F64_12)
-            fn(NaikOp<LinkD12>{LinkD12{ls.d12}, LinkD12{ls.ld12}, ls.c1, ls.c3});
+            fn(NaikOp<D12>{D12{ls.d12}, D12{ls.ld12}, ls.c1, ls.c3});
         else
-            fn(NaikOp<LinkD18>{LinkD18{ls.d18}, LinkD18{ls.ld18}, ls.c1, ls.c3});
+            fn(NaikOp<D18>{D18{ls.d18}, D18{ls.ld18}, ls.c1, ls.c3});
     } else if (ls.fmt64 == STAG_LINKS_F64_12) {
-        fn(LinkD12{ls.d12});
+        fn(D12{ls.d12});
     } else {
-        fn(LinkD18{ls.d18});
+        fn(D18{ls.d18});
     }
+}
+template <class Fn>
+void with_link64(const LinkSet& ls, Fn fn) {
+    if (ls.nt)
+        with_link64_nt<true>(ls, fn);
+    else
+        with_link64_nt<false>(ls, fn);
 }
 template <class Fn>
 void with_link32(const LinkSet& ls, Fn fn) {
@@ -588,6 +701,15 @@ int dslash_grid(const Geom& g, int tps) {
 
 // ---- fused multi-shift iteration (FP64), 4 threads per site
 int dslash_fused_grid(const Geom& g) { return dslash_grid(g, 4); }
+
+void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
+                            double2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term) {
+    const int grid = dslash_fused_grid(g);
+    with_link64(ls, [&](auto L) {
+        timed_launch(k_dslash_cg_fused<decltype(L)>, dim3(grid), dim3(kBlock), s, g, L, w_o, p, r, Ap, dpart,
+                     mass_term, gate);
+    });
+}
 
 void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIter& f, double2* w_out, bool first,
                          hipStream_t s) {

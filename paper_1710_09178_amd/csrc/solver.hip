@@ -29,6 +29,14 @@ stag_status ensure_pool(stag_ctx* c, int n) {
     return STAG_OK;
 }
 
+// Link fields up to this size are served largely by the 256 MB Infinity
+// Cache between the Dslash launches of a solve: the 151 MB FP64 field of
+// 32^3x8 stays there, and even the 302 MB of links and long links of the
+// improved operator at 32^3x8 run 6% slower with non-temporal loads.  Larger
+// fields are streamed from HBM every time (48^3x16, 1.02 GB: D_oe 221 -> 201 us
+// with non-temporal loads).
+constexpr size_t kLinkCacheBytes = (size_t)512 << 20;
+
 stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls) {
     const Geom& g = c->g;
     const size_t l12 = (size_t)48 * g.vh;  // complex entries of a 12-real field
@@ -36,6 +44,14 @@ stag_status get_links(stag_ctx* c, int fmt32, LinkSet& ls) {
     ls.fmt64 = c->fmt64;
     ls.fmt32 = fmt32 < 0 ? STAG_LINKS_F32_18 : fmt32;
     ls.d18 = c->links;
+    // FP64 operator fields (links, and long links) beyond kLinkCacheBytes are
+    // streamed with non-temporal loads; STAG_LINK_NT = 0 / 1 / 2 forces never /
+    // by size (default) / always
+    {
+        const size_t per_field = (size_t)2 * 4 * (c->fmt64 == STAG_LINKS_F64_12 ? 96 : 144) * g.vh;
+        const size_t bytes = per_field * (c->naik ? 2 : 1);
+        ls.nt = c->link_nt == 2 || (c->link_nt == 1 && bytes > kLinkCacheBytes);
+    }
     stag_status e;
     if (c->fmt64 == STAG_LINKS_F64_12) {
         if (!c->links_d12 && (e = dmalloc(c, &c->links_d12, l12 * sizeof(double2)))) return e;
@@ -378,7 +394,7 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int 
         f0.p_prev = pbuf[0];
         f0.slot_prev = 0;
         launch_dslash_fused(g, ls, f0, c->w_o, true, c->s);
-        launch_dslash_cg(g, ls, c->w_o, pbuf[0], c->r, c->Ap, &c->st->done[1], c->dpart, 4, c->s, mt);
+        launch_dslash_cg_fused(g, ls, c->w_o, pbuf[0], c->r, c->Ap, &c->st->done[1], c->dpart, c->s, mt);
     }
     int it_issued = 1;
     auto enqueue_chunk = [&]() {
@@ -390,8 +406,8 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int 
             launch_dslash_fused(g, ls, f, c->w_o, false, c->s);
             prof_end(c, a, 0, rec);
             prof_begin(c, &a);
-            launch_dslash_cg(g, ls, c->w_o, pbuf[par], c->r + (size_t)(j % L) * n3, c->Ap, &c->st->done[par ^ 1],
-                             c->dpart, 4, c->s, mt);
+            launch_dslash_cg_fused(g, ls, c->w_o, pbuf[par], c->r + (size_t)(j % L) * n3, c->Ap,
+                                   &c->st->done[par ^ 1], c->dpart, c->s, mt);
             prof_end(c, a, 1, rec);
             if (j % L == 0 && nsh > 0) {
                 prof_begin(c, &a);

@@ -123,6 +123,8 @@ def load_library() -> ctypes.CDLL:
         "stag_set_link_format": (S, [H, I]),
         "stag_set_naik": (S, [H, D, D]),
         "stag_set_fused_iteration": (S, [H, I]),
+        "stag_batch_autotune": (S, [H, I, ctypes.c_char_p, ctypes.POINTER(D), ctypes.POINTER(I)]),
+        "stag_set_link_streaming": (S, [H, I]),
         "stag_profile_samples": (S, [H, I, ctypes.POINTER(ctypes.c_float), I, ctypes.POINTER(I)]),
         "stag_mdagm_noalloc": (S, [H, P, P, D]),
         "stag_fermion_action": (S, [H, D, ctypes.POINTER(CRational), D, I, P, ctypes.POINTER(D),
@@ -462,6 +464,10 @@ class Lattice:
         """0 / False: three-launch loop; 1 / True: fused on small grids (default); 2: fused at every size."""
         self._check(self.lib.stag_set_fused_iteration(self.h, int(mode)))
 
+    def set_link_streaming(self, mode: int):
+        """0 plain link loads, 1 non-temporal beyond the Infinity Cache (default), 2 always non-temporal."""
+        self._check(self.lib.stag_set_link_streaming(self.h, int(mode)))
+
     def set_graphs(self, on: bool):
         self._check(self.lib.stag_set_graphs(self.h, int(bool(on))))
 
@@ -572,6 +578,15 @@ class Batch:
         us = (ctypes.c_double * 4)()
         self._check(self.lib.stag_batch_tune(self.h, int(precision), us))
         return list(us)
+
+    def autotune(self, precision=0, cache_path=None):
+        """Threads per site x link loads, with an optional persisted cache; returns
+        (microseconds per candidate, (tps, link_nt, from_cache))."""
+        us = (ctypes.c_double * 7)()
+        ch = (ctypes.c_int * 3)()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.stag_batch_autotune(self.h, int(precision), path, us, ch))
+        return list(us), tuple(ch)
 
 
 class Surrogate:

@@ -218,3 +218,31 @@ def test_full_size_64_lattices_against_oracle():
             # (about 1e-16 |A| |x|) is a visible fraction of the residual itself
             assert np.all(np.abs(lib - res) <= 0.1 * res + 1e-12), (precision, i, j)
         del x, xh
+
+
+def test_autotune_cache_and_link_loads(tmp_path):
+    """The autotuner times every candidate, appends its choice to the cache
+    file and takes it from there on the next call; the solver's results are
+    bitwise the same for plain and non-temporal link loads (choices forced
+    through the cache file)."""
+    B, Us, masses, bs, bd = _setup(2, seed=3)
+    cache = str(tmp_path / "tune.txt")
+    us, choice = B.autotune(0, cache)
+    assert all(u > 0 for u in us) and choice[2] == 0
+    lines = open(cache).read().split("\n")
+    key = lines[0].split()[0]
+    assert len([ln for ln in lines if ln.strip()]) == 1
+    us2, choice2 = B.autotune(0, cache)
+    assert choice2[:2] == choice[:2] and choice2[2] == 1 and all(u == -1.0 for u in us2)
+    rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
+    got = []
+    for nt in (0, 1):
+        forced = str(tmp_path / f"forced{nt}.txt")
+        with open(forced, "w") as f:
+            f.write(f"{key} 4 {nt} 1.0\n")
+        _, ch = B.autotune(0, forced)
+        assert ch == (4, nt, 1)
+        x, info = B.solve(masses, rat, bd)
+        assert info["true_resid"].max() < 1e-10
+        got.append(host(x))
+    assert np.array_equal(got[0], got[1])
