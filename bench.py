@@ -230,6 +230,81 @@ def pmc_mode():
     print(json.dumps({"pmc_mode": True, "iters": info["iters"], "copy_bytes": 512 * 2 ** 20}), flush=True)
 
 
+def force_channel_probe(n_samples=6):
+    """How much of the truncated-solve force error could covariant channels
+    built from truncated solves remove?  The thermalised 16^3x8 RHMC
+    configuration (as in rhmc()); for n_samples pseudofermions (one RHMC
+    trajectory apart): the exact force F, the forces of solves stopped after
+    100, 150 and 200 iterations, and of the 200-iteration solve split into the
+    4 lightest and the 8 heavier poles; the share of the 200-iteration error
+    carried by the light poles; and global least-squares combinations of
+    these channels fitted on half of the samples and evaluated on the other
+    half (relative errors |F_fit - F| / |F|)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice
+    torch.cuda.set_device(0)
+    dims = (16, 16, 16, 8)
+    beta, mass = 5.4, 0.02
+    r_f = synth.load_rational("xm050_n12_m0.02")
+    r_a = synth.load_rational("xm050_n20_m0.02")
+    r_h = synth.load_rational("xp025_n20_m0.02")
+    lat = Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.haar_su3(dims, synth.make_rng(5, 0))).cuda())
+    kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
+    t = 0
+    for _ in range(60):
+        lat.trajectory(beta, mass, 0.5, 20, r_f, r_a, r_h, no_fermions=True, inject_u=0.0, traj_index=t, **kw)
+        t += 1
+    for _ in range(5):
+        lat.trajectory(beta, mass, 1.0, 20, r_f, r_a, r_h, inject_u=0.0, traj_index=t, **kw)
+        t += 1
+    order = list(np.argsort(r_f["pole"]))
+
+    def sub(idx):
+        return {"c0": 0.0, "pole": [r_f["pole"][i] for i in idx], "residue": [r_f["residue"][i] for i in idx]}
+
+    samples = []
+    for j in range(n_samples):
+        xs = [lat.new_vec() for _ in r_h["pole"]]
+        phi = lat.new_vec()
+        lat.multishift_solve(mass, r_h, 1e-10, 100000, lat.random_source(99, 100000 + j), xs, phi, true_resid=False)
+
+        def force(rat, tol, maxiter):
+            m = lat.new_mom()
+            lat.fermion_force(mass, rat, tol, maxiter, phi, m, 0.0, allow_not_converged=True)
+            return lat.mom_export(m).cpu().numpy().reshape(-1)
+        samples.append({"F": force(r_f, 1e-10, 100000), "T200": force(r_f, 1e-30, 200),
+                        "T150": force(r_f, 1e-30, 150), "T100": force(r_f, 1e-30, 100),
+                        "L200": force(sub(order[:4]), 1e-30, 200), "H200": force(sub(order[4:]), 1e-30, 200),
+                        "Lex": force(sub(order[:4]), 1e-10, 100000)})
+        lat.trajectory(beta, mass, 1.0, 20, r_f, r_a, r_h, inject_u=0.0, traj_index=t, **kw)
+        t += 1
+        log(f"sample {j}")
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    half = n_samples // 2
+    out = {"force_channel_probe": True,
+           "truncated_200_rel_error": [round(rel(s["T200"], s["F"]), 5) for s in samples],
+           "truncated_100_rel_error": [round(rel(s["T100"], s["F"]), 5) for s in samples],
+           "light_poles_share_of_truncation_error": [
+               round(float(np.linalg.norm(s["L200"] - s["Lex"]) / np.linalg.norm(s["T200"] - s["F"])), 6)
+               for s in samples]}
+    for name, cols in {"T200": ["T200"], "L200+H200": ["L200", "H200"], "T200+T100": ["T200", "T100"],
+                       "T200+T150+T100": ["T200", "T150", "T100"]}.items():
+        A = np.concatenate([np.stack([s[c] for c in cols], 1) for s in samples[:half]])
+        y = np.concatenate([s["F"] for s in samples[:half]])
+        coef = np.linalg.lstsq(A, y, rcond=None)[0]
+        out["fit_" + name] = {"coefficients": [round(float(c), 5) for c in coef],
+                              "held_out_rel_error": [round(rel(np.stack([s[c] for c in cols], 1) @ coef, s["F"]), 5)
+                                                     for s in samples[half:]]}
+    print(json.dumps(out), flush=True)
+
+
 def trajectory_trace_mode(n_traj=3):
     """A few RHMC trajectories at 16^3x8 (beta 5.4, m 0.02, the 12-pole MD
     table with 20-pole action and heat-bath tables, tau 1, 20 steps) from a near-identity start, after one untimed one: a
@@ -284,6 +359,8 @@ def main():
     ap.add_argument("--trajectory-trace-mode", action="store_true",
                     help="a few 16^3x8 RHMC trajectories, for a kernel trace")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
+    ap.add_argument("--force-channel-probe", action="store_true",
+                    help="truncated-solve force channels against the exact force at 16^3x8 (one JSON line)")
     args = ap.parse_args()
     if args.summarize_trace:
         text, _ = summarize_trace(args.summarize_trace)
@@ -291,6 +368,9 @@ def main():
         return
     if args.trajectory_trace_mode:
         trajectory_trace_mode()
+        return
+    if args.force_channel_probe:
+        force_channel_probe()
         return
     if args.pmc_mode:
         pmc_mode()
@@ -469,7 +549,27 @@ def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
     import torch
     from paper_1710_09178_amd import stag
     out = {}
+    # FP64 reference solutions (18-real links), for the per-pole errors below
+    lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
+    x64 = [x.clone() for x in xs]
+
+    def pole_errors():
+        return [float(torch.linalg.vector_norm(x - r) / torch.linalg.vector_norm(r)) for x, r in zip(xs, x64)]
+
+    # operator errors against the FP64 operator (itself equal to the oracle
+    # to 1e-14): relative max-norm error of D_oe on a Gaussian even vector
+    ref = lat.new_vec()
+    lat.dslash(ref, bd, 1)
+    op_err = {}
+    for name, fmt in (("fp32_links18", stag.LINKS_F32_18), ("fp16_links12", stag.LINKS_F16_12)):
+        y = lat.new_vec()
+        lat.dslash_sloppy(y, bd, 1, fmt)
+        op_err[name] = float((y - ref).abs().max() / ref.abs().max())
     lat.set_link_format(stag.LINKS_F64_12)
+    y = lat.new_vec()
+    lat.dslash(y, bd, 1)
+    op_err["fp64_links12"] = float((y - ref).abs().max() / ref.abs().max())
+    out["dslash_oe_rel_error_vs_fp64"] = op_err
     lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -479,7 +579,8 @@ def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
     ms12 = (time.perf_counter() - t0) / reps * 1e3
     chk = lat.multishift_solve(MASS, rat, TOL, 100000, bd, xs, None, true_resid=True)
     out["fp64_links12"] = {"ms_per_solve": round(ms12, 3), "speedup_vs_fp64_18": round(fp64_ms / ms12, 3),
-                           "iterations": i12["iters"], "true_resid_max": max(chk["true_resid"])}
+                           "iterations": i12["iters"], "true_resid_max": max(chk["true_resid"]),
+                           "solution_rel_error_per_pole": [float("%.2e" % e) for e in pole_errors()]}
     lat.set_link_format(stag.LINKS_F64_18)
     for name, fmt in [("mixed_fp32_links18", stag.LINKS_F32_18), ("mixed_fp32_fp16links12", stag.LINKS_F16_12)]:
         lat.multishift_solve_mixed(MASS, rat, TOL, 100000, bd, xs, None, sloppy=fmt, true_resid=False)
@@ -492,7 +593,8 @@ def precision_forms(lat, rat, bd, xs, vh, base, fp64_ms, reps=3):
         chk = lat.multishift_solve_mixed(MASS, rat, TOL, 100000, bd, xs, None, sloppy=fmt, true_resid=True)
         out[name] = {"ms_per_solve": round(msm, 3), "speedup_vs_fp64_18": round(fp64_ms / msm, 3),
                      "iterations_total": im["iters"], "iterations_per_pole": im["iters_per_pole"],
-                     "true_resid_max": max(chk["true_resid"]), "tol_sloppy": 1e-5, "reliable_every": 50}
+                     "true_resid_max": max(chk["true_resid"]), "tol_sloppy": 1e-5, "reliable_every": 50,
+                     "solution_rel_error_per_pole": [float("%.2e" % e) for e in pole_errors()]}
     return out
 
 
@@ -933,6 +1035,8 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
         for i in range(n_traj):
             res.append(lat.trajectory(beta, mass, tau, chain_steps, r_f, r_a, r_h, traj_index=10 ** 6 + i,
                                       **kw, **extra))
+            if (i + 1) % 50 == 0:
+                log(f"  {i + 1} trajectories")
         torch.cuda.synchronize()
         return summary(res, (time.perf_counter() - t1) / n_traj)
 
