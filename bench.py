@@ -305,6 +305,43 @@ def force_channel_probe(n_samples=6):
     print(json.dumps(out), flush=True)
 
 
+def surrogate_trace_mode(n_pairs=64, epochs=4):
+    """The learned force model's kernels at 16^3x8 (131,072 links), for a
+    kernel trace: n_pairs stored (gauge field, force) pairs with the
+    auxiliary channel (random force fields stand in for the targets: the
+    kernels' work does not depend on the values), `epochs` training epochs
+    (one forward, backward and Adam step per pair), one evaluation with
+    gradients and 20 applications of the model to a momentum field."""
+    import torch
+
+    import synth
+    from paper_1710_09178_amd.stag import Lattice, Surrogate
+    torch.cuda.set_device(0)
+    dims = (16, 16, 16, 8)
+    lat = Lattice(dims)
+    lat.set_gauge(torch.from_numpy(synth.random_su3_near_identity(dims, 0.5, synth.make_rng(6, 0))).cuda())
+    sur = Surrogate(lat, n_pairs, seed=1)
+    aux = lat.random_momentum(7, 0)
+    sur.set_aux(aux)
+    for k in range(n_pairs):
+        sur.add_pair(lat.random_momentum(7, 1 + k))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = sur.train(epochs, 1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sur.eval(lat.random_momentum(7, 10 ** 6), want_grad=True)
+    mom = lat.new_mom()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        sur.force(mom, 0.05)
+    torch.cuda.synchronize()
+    t_apply = (time.perf_counter() - t0) / 20
+    print(json.dumps({"surrogate_trace_mode": True, "links": lat.V * 4, "pairs": n_pairs, "epochs": epochs,
+                      "train_s": round(t_train, 4), "us_per_pair_step": round(1e6 * t_train / (n_pairs * epochs), 2),
+                      "apply_us": round(1e6 * t_apply, 2), "loss": loss}), flush=True)
+
+
 def trajectory_trace_mode(n_traj=3):
     """A few RHMC trajectories at 16^3x8 (beta 5.4, m 0.02, the 12-pole MD
     table with 20-pole action and heat-bath tables, tau 1, 20 steps) from a near-identity start, after one untimed one: a
@@ -359,6 +396,8 @@ def main():
     ap.add_argument("--trajectory-trace-mode", action="store_true",
                     help="a few 16^3x8 RHMC trajectories, for a kernel trace")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
+    ap.add_argument("--surrogate-trace-mode", action="store_true",
+                    help="the learned model's kernels at 16^3x8, for a kernel trace")
     ap.add_argument("--force-channel-probe", action="store_true",
                     help="truncated-solve force channels against the exact force at 16^3x8 (one JSON line)")
     args = ap.parse_args()
@@ -371,6 +410,9 @@ def main():
         return
     if args.force_channel_probe:
         force_channel_probe()
+        return
+    if args.surrogate_trace_mode:
+        surrogate_trace_mode()
         return
     if args.pmc_mode:
         pmc_mode()
