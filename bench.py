@@ -372,8 +372,8 @@ def trajectory_trace_mode(n_traj=3):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--tps", type=int, default=0, help="Dslash threads per site (0 = library default)")
     ap.add_argument("--lag", type=int, default=8, help="shift-update window of the solver (1..8)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -458,3 +458,53 @@ def test_c4_size_loss_gradient_and_adam_match_oracle():
             assert (d <= tol).all(), (step, k, d.max())
         moved = np.abs(got["W2"] - p["W2"]).max()
         assert 0.5 * lr * (step + 1) < moved <= 1.01 * lr * (step + 1)
+
+
+def test_learned_inner_force_leapfrog_is_reversible():
+    """The inner-scale force of the learned schedule -- the model applied to
+    the force of a solve stopped after a fixed number of iterations -- is a
+    deterministic function of the links and the pseudofermion, so a
+    two-time-scale leapfrog with it (exact force on the outer kicks), run
+    forward, momenta flipped and run again, returns to the starting links and
+    the negated momenta: the property that keeps the schedules exact."""
+    dims = (8, 8, 8, 8)
+    log("learned-schedule leapfrog reversibility at 8^4")
+    rng = synth.make_rng(708, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.3, rng)
+    phi = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm050_n12_m0.02")
+    lat = lattice(dims, U0)
+    phid = lat.vec_import(dev(phi), 0)
+    sur = stag.Surrogate(lat, 1)
+    sur.set_params(_flat(_params(3)))
+    aux = lat.new_mom()
+    mom = lat.random_momentum(9, 2)
+    P0 = host(lat.mom_export(mom))
+    dt, n, every = 0.05, 4, 2
+
+    def kick(h, exact):
+        lat.gauge_force(5.4, mom, h)
+        if exact:
+            lat.fermion_force(0.02, rat, 1e-12, 100000, phid, mom, h)
+        else:
+            lat.fermion_force(0.02, rat, 1e-30, 30, phid, aux, 0.0, allow_not_converged=True)
+            sur.set_aux(aux)
+            sur.force(mom, h)
+            sur.set_aux(None)
+
+    def leapfrog():
+        kick(0.5 * dt, True)
+        for s in range(n):
+            lat.link_update(mom, dt)
+            k = s + 1
+            kick(dt if k < n else 0.5 * dt, k % every == 0)
+
+    leapfrog()
+    U1 = host(lat.get_gauge())
+    assert np.abs(U1 - U0).max() > 1e-3
+    mom.copy_(lat.mom_import(dev(-host(lat.mom_export(mom)))))
+    leapfrog()
+    U2 = host(lat.get_gauge())
+    P2 = host(lat.mom_export(mom))
+    assert np.abs(U2 - U0).max() < 1e-8, np.abs(U2 - U0).max()
+    assert np.abs(P2 + P0).max() < 1e-7 * np.abs(P0).max(), np.abs(P2 + P0).max()
