@@ -160,3 +160,62 @@ def test_A_hermitian_positive_bounded():
     nn = vdot(a, a).real
     bound = 4 * m * m + (8 * (naik.C1 + abs(naik.C3))) ** 2
     assert 4 * m * m * nn <= aa <= bound * nn
+
+
+# ---- the improved operator's pseudofermion force --------------------------
+
+def _move(U, omega, h):
+    from oracle.su3 import expi, to_matrix
+    return np.einsum("...ij,...jk->...ik", expi(h * to_matrix(omega)), U)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 2, 4), (6, 4, 4, 4)])
+def test_naik_force_matches_finite_differences(dims):
+    """F = -dS_f/dw for random directions w, against symmetric finite
+    differences (O(h^2)) of the improved operator's rational action, including
+    a lattice whose z extent 2 makes a three-link path run over one link twice."""
+    rng = synth.make_rng(930, 0)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    phi = synth.gaussian_half_vector(dims, rng)
+    F = naik.fermion_force(U, dims, 0.1, phi, rat, 1e-13)
+    for trial in range(2):
+        om = rng.standard_normal(F.shape)
+        h = 1e-4
+        fd = (naik.fermion_action(_move(U, om, h), dims, 0.1, phi, rat, 1e-13)
+              - naik.fermion_action(_move(U, om, -h), dims, 0.1, phi, rat, 1e-13)) / (2 * h)
+        an = -np.sum(om * F)
+        assert abs(fd - an) <= 1e-6 * abs(an), (dims, trial, fd, an)
+
+
+def test_naik_force_naive_limit():
+    """(c1, c3) = (1, 0) is the one-hop operator: the same force as the plain
+    operator's oracle (an independent derivation and code path)."""
+    from oracle import fermion
+    dims = (4, 4, 2, 4)
+    rng = synth.make_rng(931, 0)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    phi = synth.gaussian_half_vector(dims, rng)
+    F = naik.fermion_force(U, dims, 0.1, phi, rat, 1e-13, c1=1.0, c3=0.0)
+    F0 = fermion.fermion_force(U, dims, 0.1, phi, rat, 1e-13)
+    assert np.abs(F - F0).max() < 1e-10 * np.abs(F0).max()
+
+
+def test_naik_force_is_gauge_covariant():
+    """F(U^Omega, Omega phi) = Omega F Omega^dag (as traceless Hermitian matrices)."""
+    from oracle.su3 import to_coords, to_matrix
+    dims = (4, 4, 2, 4)
+    rng = synth.make_rng(932, 0)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    phi = synth.gaussian_half_vector(dims, rng)
+    Om = synth.haar_su3(dims, rng)[..., 0, :, :]
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Ug[..., mu, :, :] = np.einsum("...ij,...jk,...lk->...il", Om, U[..., mu, :, :], L.fwd(Om, mu).conj())
+    phig = L.full_to_half(np.einsum("...ij,...j->...i", Om, L.half_to_full(phi, dims, 0)), dims, 0)
+    F = to_matrix(naik.fermion_force(U, dims, 0.1, phi, rat, 1e-13))
+    Fg = to_matrix(naik.fermion_force(Ug, dims, 0.1, phig, rat, 1e-13))
+    rot = np.einsum("...ij,...mjk,...lk->...mil", Om, F, Om.conj())
+    assert np.abs(Fg - rot).max() < 1e-9 * np.abs(F).max()
