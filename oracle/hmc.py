@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import fermion, gauge
+from . import fermion, gauge, naik
 from .su3 import expi, reunitarise, to_matrix
 
 
@@ -44,19 +44,32 @@ class HMCParams:
     r_heatbath: dict    # heat-bath rational function (x^+1/4)
     tol_md: float = 1e-10
     tol_action: float = 1e-12
+    naik: tuple | None = None   # (c1, c3): the improved operator (Sec. 8 Summary) instead of the one-hop one
+
+
+def _fermion_force(U, dims, prm, phi, rat, tol):
+    if prm.naik:
+        return naik.fermion_force(U, dims, prm.mass, phi, rat, tol, *prm.naik)
+    return fermion.fermion_force(U, dims, prm.mass, phi, rat, tol)
+
+
+def _fermion_action(U, dims, prm, phi, rat, tol):
+    if prm.naik:
+        return naik.fermion_action(U, dims, prm.mass, phi, rat, tol, *prm.naik)
+    return fermion.fermion_action(U, dims, prm.mass, phi, rat, tol)
 
 
 def total_force(U, dims, prm: HMCParams, phi):
     F = gauge.gauge_force(U, dims, prm.beta)
     if phi is not None:
-        F = F + fermion.fermion_force(U, dims, prm.mass, phi, prm.r_md, prm.tol_md)
+        F = F + _fermion_force(U, dims, prm, phi, prm.r_md, prm.tol_md)
     return F
 
 
 def hamiltonian(U, P, dims, prm: HMCParams, phi):
     K = kinetic(P)
     Sg = gauge.gauge_action(U, dims, prm.beta)
-    Sf = 0.0 if phi is None else fermion.fermion_action(U, dims, prm.mass, phi, prm.r_action, prm.tol_action)
+    Sf = 0.0 if phi is None else _fermion_action(U, dims, prm, phi, prm.r_action, prm.tol_action)
     return K, Sg, Sf
 
 
@@ -71,13 +84,19 @@ def leapfrog(U, P, dims, prm: HMCParams, phi, force=None):
     return U, P
 
 
-def heatbath(U, dims, mass, xi, r_hb, tol):
+def heatbath(U, dims, mass, xi, r_hb, tol, naik_weights=None):
+    if naik_weights:
+        sol = naik.rational_solve(U, dims, mass, xi, r_hb, tol, *naik_weights)
+        out = r_hb["c0"] * xi
+        for c, x in zip(r_hb["residue"], sol["x"]):
+            out = out + c * x
+        return out
     return fermion.rational_apply(U, dims, mass, xi, r_hb, tol)
 
 
 def trajectory(U0, dims, prm: HMCParams, P0, xi, u, with_fermions=True):
     """One trajectory with given momenta P0, noise xi and Metropolis uniform u."""
-    phi = heatbath(U0, dims, prm.mass, xi, prm.r_heatbath, prm.tol_action) if with_fermions else None
+    phi = heatbath(U0, dims, prm.mass, xi, prm.r_heatbath, prm.tol_action, prm.naik) if with_fermions else None
     K0, Sg0, Sf0 = hamiltonian(U0, P0, dims, prm, phi)
     U1, P1 = leapfrog(U0, P0, dims, prm, phi)
     K1, Sg1, Sf1 = hamiltonian(U1, P1, dims, prm, phi)

@@ -67,3 +67,49 @@ def test_trajectory_accounting_and_philox_draws():
     assert abs(Sf0 - np.vdot(xi, xi).real) < 1e-5 * Sf0
     assert out["accepted"] == (u < np.exp(-out["dH"]))
     assert abs(out["dH"]) < 1.0
+
+
+NAIK = (9.0 / 8.0, -1.0 / 24.0)
+
+
+def _naik_params(n_steps, weights=NAIK):
+    prm = _params(n_steps)
+    prm.naik = weights
+    return prm
+
+
+def test_naik_dH_scales_as_dt_squared():
+    """The improved operator's force is the derivative of its action: the
+    leapfrog energy error then falls as dt^2 (a force inconsistent with the
+    action leaves an O(1) dH)."""
+    U0, P0, xi = _state(1)
+    dh = []
+    for n in (8, 16, 32):
+        out = hmc.trajectory(U0, DIMS, _naik_params(n), P0, xi, 0.5)
+        dh.append(abs(out["dH"]))
+    r1, r2 = dh[0] / dh[1], dh[1] / dh[2]
+    assert 3.2 < r1 < 4.5 and 3.7 < r2 < 4.3
+
+
+def test_naik_heatbath_inverts_action():
+    """phi = r_{1/4}(A) xi with the improved A: phi^dag r_{-1/2}(A) phi = xi^dag xi
+    up to the tables' approximation errors (the improved spectrum on these
+    near-identity links, free-field maximum 4m^2 + 16 (c1 - c3)^2 = 21.8,
+    lies inside the tables' interval [0.01, 64])."""
+    from oracle import naik
+    U0, _, xi = _state(2)
+    prm = _naik_params(4)
+    phi = hmc.heatbath(U0, DIMS, prm.mass, xi, prm.r_heatbath, 1e-13, NAIK)
+    Sf = naik.fermion_action(U0, DIMS, prm.mass, phi, prm.r_action, 1e-13, *NAIK)
+    xx = float(np.vdot(xi, xi).real)
+    assert abs(Sf - xx) < 1e-5 * xx
+
+
+def test_naik_one_hop_weights_reproduce_the_plain_trajectory():
+    """(c1, c3) = (1, 0) takes the improved code path (heat bath, force,
+    actions) and must reproduce the one-hop trajectory."""
+    U0, P0, xi = _state(4)
+    a = hmc.trajectory(U0, DIMS, _params(4), P0, xi, 0.5)
+    b = hmc.trajectory(U0, DIMS, _naik_params(4, (1.0, 0.0)), P0, xi, 0.5)
+    assert abs(a["dH"] - b["dH"]) < 1e-9
+    assert np.abs(a["U_proposed"] - b["U_proposed"]).max() < 1e-11
