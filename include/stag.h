@@ -202,10 +202,12 @@ stag_status stag_set_link_format(stag_handle h, int format);
  * the one-hop operator.  The long links are derived from the links (in the
  * format set by stag_set_link_format, and the sloppy formats on demand) at
  * the first operator call after every change of the links; the first use
- * allocates them (144 B per link in FP64).  The pseudofermion force and
- * trajectories with fermions need the one-hop operator: with the improvement
- * on they return STAG_ERR_INVALID_ARG.  Returns STAG_ERR_INVALID_ARG for
- * non-finite weights. */
+ * allocates them (144 B per link in FP64), together with a link-shaped
+ * scratch field of the pseudofermion force (another 144 B per link).  The
+ * pseudofermion force, and with it every trajectory, then differentiates the
+ * improved action: each link moves in its one-hop term and at the three
+ * positions of the three-link paths through it.  Returns
+ * STAG_ERR_INVALID_ARG for non-finite weights. */
 stag_status stag_set_naik(stag_handle h, double c1, double c3);
 
 /* The sloppy operator of the precision form, applied to FP64 internal vectors
@@ -246,7 +248,8 @@ stag_status stag_fermion_action(stag_handle h, double mass, const stag_rational*
                                 int maxiter, const void* phi_even, double* S_out,
                                 stag_solve_info* info);
 /* Pseudofermion force F = -dS_f/dw for S_f = phi^dag r(A) phi, per link in
- * algebra coordinates.  dt == 0: mom = F; otherwise mom += dt * F. */
+ * algebra coordinates (with the operator set by stag_set_naik).  dt == 0:
+ * mom = F; otherwise mom += dt * F. */
 stag_status stag_fermion_force(stag_handle h, double mass, const stag_rational* r, double tol,
                                int maxiter, const void* phi_even, void* mom, double dt,
                                stag_solve_info* info);

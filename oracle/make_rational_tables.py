@@ -38,6 +38,11 @@ TABLES = {
     # 12-pole MD table
     "xm050_n20_m0.02": (-0.5, 0.02 ** 2, 64.0, 20, "RHMC action, accurate"),
     "xp025_n20_m0.02": (0.25, 0.02 ** 2, 64.0, 20, "RHMC heat bath, accurate"),
+    # the same three tables on [m^2, 88] for the improved (Naik) operator,
+    # whose A is bounded by 4m^2 + (8 (|c1| + |c3|))^2 = 87.1 at (9/8, -1/24)
+    "xm050_n12_m0.02_h88": (-0.5, 0.02 ** 2, 88.0, 12, "improved-operator RHMC MD force"),
+    "xm050_n20_m0.02_h88": (-0.5, 0.02 ** 2, 88.0, 20, "improved-operator RHMC action, accurate"),
+    "xp025_n20_m0.02_h88": (0.25, 0.02 ** 2, 88.0, 20, "improved-operator RHMC heat bath, accurate"),
     # the paper's Appendix example: degree 24/24 for x^(1/4) on [5e-5, 34]
     "xp025_n24_paper": (0.25, 5e-5, 34.0, 24, "paper Appendix example (error < 1e-12)"),
 }

@@ -128,7 +128,11 @@ stag_status fermion_force_impl(stag_ctx* c, double mass, const stag_rational* r,
         launch_dslash(g, ls, xs[k], pool_vec(c->pool_y, g, k), 1, c->tps, nullptr, c->s);
     }
     const double* coef = (const double*)((const char*)c->st + offsetof(MsState, coef));
-    launch_fermion_force(g, c->links, X, Y, coef, r->n, mom, dt, c->s);
+    launch_fermion_force(g, c->links, X, Y, coef, r->n, mom, dt, c->s, c->naik ? c->naik_c1 : 1.0);
+    if (c->naik) {
+        if (!c->naik_w3 && (e = dmalloc(c, &c->naik_w3, (size_t)72 * g.vh * sizeof(double2)))) return e;
+        launch_naik_force3(g, c->links, X, Y, coef, r->n, c->naik_w3, c->naik_c3, mom, dt, c->s);
+    }
     return STAG_OK;
 }
 
@@ -299,7 +303,7 @@ stag_status stag_destroy(stag_handle c) {
     if (!c) return STAG_OK;
     if (c->s) hipStreamSynchronize(c->s);
     void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->long_d18, c->long_d12, c->long_s18, c->long_h12,
-                    c->r32, c->p32, c->Ap32, c->w32,
+                    c->naik_w3, c->r32, c->p32, c->Ap32, c->w32,
                     c->links, c->links_backup, c->mom, c->r, c->p, c->p2, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
                     c->gpart, c->scal, c->mom_tmp, c->mom_aux};
@@ -565,6 +569,7 @@ stag_status alloc_link_copies(stag_ctx* c) {
     if (c->fmt64 == STAG_LINKS_F64_12 && !c->links_d12 && (e = dmalloc(c, &c->links_d12, l12))) return e;
     if (c->naik && !c->long_d18 && (e = dmalloc(c, &c->long_d18, l18))) return e;
     if (c->naik && c->fmt64 == STAG_LINKS_F64_12 && !c->long_d12 && (e = dmalloc(c, &c->long_d12, l12))) return e;
+    if (c->naik && !c->naik_w3 && (e = dmalloc(c, &c->naik_w3, l18))) return e;
     return STAG_OK;
 }
 
@@ -617,8 +622,6 @@ stag_status stag_fermion_force(stag_handle c, double mass, const stag_rational* 
     if (!(tol > 0.0) || maxiter < 1) return fail(c, STAG_ERR_INVALID_ARG, "need tol > 0 and maxiter >= 1");
     if (!aligned16(phi) || !aligned16(mom)) return fail(c, STAG_ERR_INVALID_ARG, "phi/mom NULL or misaligned");
     if (!std::isfinite(dt)) return fail(c, STAG_ERR_INVALID_ARG, "dt must be finite");
-    if (c->naik)
-        return fail(c, STAG_ERR_INVALID_ARG, "the pseudofermion force is implemented for the one-hop operator only");
     if ((e = enter(c))) return e;
     SolveResult res;
     if ((e = fermion_force_impl(c, mass, r, tol, maxiter, (const double2*)phi, (double*)mom, dt, res))) return e;
@@ -754,8 +757,6 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         p->maxiter < 1)
         return fail(c, STAG_ERR_INVALID_ARG, "need n_steps >= 1, tau > 0, tolerances > 0, maxiter >= 1");
     const bool ferm = !p->no_fermions;
-    if (ferm && c->naik)
-        return fail(c, STAG_ERR_INVALID_ARG, "trajectories with fermions need the one-hop operator (no Naik force)");
     if (ferm) {
         if ((e = check_rational(c, &p->r_md, p->mass)) || (e = check_rational(c, &p->r_action, p->mass)) ||
             (e = check_rational(c, &p->r_heatbath, p->mass)))

@@ -353,8 +353,13 @@ void launch_finalize_pad(const double* part, int nb, double* out, int npad, hipS
 void launch_scale_rsqrt(const Geom& g, double2* v, const double* s2, hipStream_t s);
 
 // Forces and MD
+// w1 weights the one-hop term (c1 of the improved operator, 1 otherwise)
 void launch_fermion_force(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef,
-                          int n, double* mom, double dt, hipStream_t s);
+                          int n, double* mom, double dt, hipStream_t s, double w1 = 1.0);
+// the three-hop term of the improved operator's force, added to mom (w3: a
+// link-shaped scratch field, 144 B per link)
+void launch_naik_force3(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,
+                        double2* w3, double c3, double* mom, double dt, hipStream_t s);
 void launch_gauge_force(const Geom& g, const double2* links, double beta, double* mom, double dt,
                         hipStream_t s);
 void launch_link_update(const Geom& g, double2* links, const double* mom, double dt, hipStream_t s);

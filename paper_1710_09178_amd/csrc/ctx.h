@@ -32,6 +32,7 @@ struct stag_ctx {
     float2* long_s18 = nullptr;
     void* long_h12 = nullptr;
     bool long_ok = false, long_d12_ok = false, long_s18_ok = false, long_h12_ok = false;
+    double2* naik_w3 = nullptr;  // link-shaped scratch of the three-hop force term
     double* mom = nullptr;
     double* mom_tmp = nullptr;   // force staging when a trajectory records training pairs
     double* mom_aux = nullptr;   // truncated-solve force fed to a learned model

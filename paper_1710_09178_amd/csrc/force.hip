@@ -35,9 +35,10 @@ __device__ __forceinline__ void store_force(double* __restrict__ mom, const Geom
 
 // F_a(x,mu) = 2 Im tr(T_a s U_mu(x) W),  W = eps(x) sum_k c_k chi_k(x+mu) chi_k(x)^dag,
 // chi_k = X_k on even sites and Y_k = D_oe X_k on odd sites, eps = +1 (even) / -1 (odd).
+// (w1: the weight of the one-hop term, c1 for the improved operator, else 1)
 __global__ __launch_bounds__(kBlock) void k_fermion_force(Geom g, int par, const double2* __restrict__ links,
                                                           VecPtrs X, VecPtrs Y, const double* __restrict__ coef,
-                                                          int n, double* __restrict__ mom, double dt) {
+                                                          int n, double* __restrict__ mom, double dt, double w1) {
     const int cb = blockIdx.x * kBlock + threadIdx.x;
     if (cb >= g.vh) return;
     int x, y, z, t;
@@ -87,11 +88,110 @@ __global__ __launch_bounds__(kBlock) void k_fermion_force(Geom g, int par, const
         M3 M = m3_mul(U, W);
         double f[8];
         im_tr_ta(M, f);
-        const double fac = 2.0 * s * eps;
+        const double fac = 2.0 * s * eps * w1;
 #pragma unroll
         for (int a = 0; a < 8; ++a) f[a] *= fac;
         store_force(mom, g, par, mu, cb, f, dt);
     }
+}
+
+// ---- three-hop part of the improved operator's force
+// (the variation of each link in the three-link paths through it).
+__device__ __forceinline__ int step_mod(int v, int d, int n) {
+    v += d;
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+// W3(x, mu) = s3(x) eps(x) sum_k c_k chi_k(x+3mu) chi_k(x)^dag, one thread per
+// site of parity par, the four directions in turn; s3 is the path's sign
+// (eta_mu(x) once, -1 per link that leaves the last time slice).
+__global__ __launch_bounds__(kBlock) void k_naik_w3(Geom g, int par, VecPtrs X, VecPtrs Y,
+                                                    const double* __restrict__ coef, int n,
+                                                    double2* __restrict__ w3) {
+    const int cb = blockIdx.x * kBlock + threadIdx.x;
+    if (cb >= g.vh) return;
+    int c[4];
+    cb_coords(g, par, cb, c[0], c[1], c[2], c[3]);
+    const int nn[4] = {g.nx, g.ny, g.nz, g.nt};
+    const double eps = par == 0 ? 1.0 : -1.0;
+    for (int mu = 0; mu < 4; ++mu) {
+        int d[4] = {c[0], c[1], c[2], c[3]};
+        d[mu] = step_mod(c[mu], 3, nn[mu]);
+        const int cb3 = cb_index(g, d[0], d[1], d[2], d[3]);
+        double s = 1.0;
+        if (mu == 1) s = (c[0] & 1) ? -1.0 : 1.0;
+        if (mu == 2) s = ((c[0] + c[1]) & 1) ? -1.0 : 1.0;
+        if (mu == 3) {
+            s = ((c[0] + c[1] + c[2]) & 1) ? -1.0 : 1.0;
+            if (((c[3] + 3) / g.nt) & 1) s = -s;
+        }
+        M3 W;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) W.e[e] = make_double2(0.0, 0.0);
+        for (int k = 0; k < n; ++k) {
+            const double2* here = (par == 0 ? X.at<double2>(k) : Y.at<double2>(k));
+            const double2* there = (par == 0 ? Y.at<double2>(k) : X.at<double2>(k));
+            double2 a[3], b[3];
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) {
+                a[cc] = there[(size_t)cc * g.vh + cb3];
+                b[cc] = here[(size_t)cc * g.vh + cb];
+            }
+            const double ck = coef[k];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double2 v = cmul(a[i], cconj(b[j]));
+                    W.e[3 * i + j].x += ck * v.x;
+                    W.e[3 * i + j].y += ck * v.y;
+                }
+        }
+        const double fac = s * eps;
+        double2* out = w3 + link_off(g, par, mu, 0) + cb;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) out[(size_t)e * g.vh] = make_double2(fac * W.e[e].x, fac * W.e[e].y);
+    }
+}
+
+// F_a(z, mu) += 2 c3 Im tr(T_a U(z) [U(z+mu) U(z+2mu) W3(z) + U(z+mu) W3(z-mu) U(z-mu)
+//                                    + W3(z-2mu) U(z-2mu) U(z-mu)])
+// (plain links: every path's sign is in its W3).  One thread per link; added
+// to mom with factor dt, or 1 when dt == 0 (the one-hop kernel wrote F first).
+__global__ __launch_bounds__(kBlock) void k_naik_force3(Geom g, const double2* __restrict__ links,
+                                                        const double2* __restrict__ w3, double c3,
+                                                        double* __restrict__ mom, double dt) {
+    const int V = 2 * g.vh;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 4 * V) return;
+    const int mu = i / V, rem = i % V;
+    const int par = rem / g.vh, cb = rem % g.vh;
+    int c[4];
+    cb_coords(g, par, cb, c[0], c[1], c[2], c[3]);
+    const int nn[4] = {g.nx, g.ny, g.nz, g.nt};
+    auto at = [&](int d) {  // cb index and parity of z + d mu
+        int e[4] = {c[0], c[1], c[2], c[3]};
+        e[mu] = step_mod(c[mu], d, nn[mu]);
+        return cb_index(g, e[0], e[1], e[2], e[3]);
+    };
+    const int p1 = par ^ 1;
+    const int cp1 = at(1), cp2 = at(2), cm1 = at(-1), cm2 = at(-2);
+    // M = U(z+mu) [U(z+2mu) W3(z) + W3(z-mu) U(z-mu)] + W3(z-2mu) U(z-2mu) U(z-mu),
+    // built in an order that keeps few matrices live
+    M3 P = m3_mul(load_link(links, g, par, cp2, mu), load_link(w3, g, par, cb, mu));
+    const M3 Um1 = load_link(links, g, p1, cm1, mu);
+    P = m3_add(P, m3_mul(load_link(w3, g, p1, cm1, mu), Um1));
+    M3 M = m3_mul(load_link(links, g, p1, cp1, mu), P);
+    P = m3_mul(load_link(w3, g, par, cm2, mu), load_link(links, g, par, cm2, mu));
+    M = m3_add(M, m3_mul(P, Um1));
+    double f[8];
+    im_tr_ta(m3_mul(load_link(links, g, par, cb, mu), M), f);
+    const double fac = 2.0 * c3 * (dt == 0.0 ? 1.0 : dt);
+    double* m = mom + mom_off(g, par, mu, 0) + cb;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) m[(size_t)a * g.vh] += fac * f[a];
 }
 
 // F_a = -(beta/3) Im tr(T_a U_mu(x) A_mu(x)), A = sum of the six staples.
@@ -278,10 +378,17 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(size_t n, const double* __rest
 }  // namespace
 
 void launch_fermion_force(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,
-                          double* mom, double dt, hipStream_t s) {
+                          double* mom, double dt, hipStream_t s, double w1) {
     const int grid = (g.vh + kBlock - 1) / kBlock;
     for (int par = 0; par < 2; ++par)
-        k_fermion_force<<<grid, kBlock, 0, s>>>(g, par, links, X, Y, coef, n, mom, dt);
+        k_fermion_force<<<grid, kBlock, 0, s>>>(g, par, links, X, Y, coef, n, mom, dt, w1);
+}
+
+void launch_naik_force3(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,
+                        double2* w3, double c3, double* mom, double dt, hipStream_t s) {
+    const int grid = (g.vh + kBlock - 1) / kBlock;
+    for (int par = 0; par < 2; ++par) k_naik_w3<<<grid, kBlock, 0, s>>>(g, par, X, Y, coef, n, w3);
+    k_naik_force3<<<(8 * g.vh + kBlock - 1) / kBlock, kBlock, 0, s>>>(g, links, w3, c3, mom, dt);
 }
 
 void launch_gauge_force(const Geom& g, const double2* links, double beta, double* mom, double dt, hipStream_t s) {

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import dirac, naik
+from oracle import dirac, hmc, naik, philox
 from oracle import lattice as L
 from oracle.solvers import multishift_cg, true_residuals
 from paper_1710_09178_amd import stag
@@ -123,16 +123,106 @@ def test_naik_off_restores_the_one_hop_operator():
     assert rel_err(host(lat.vec_export(y, 1)), exp) < 2e-14
 
 
-def test_naik_force_and_trajectory_are_rejected():
-    dims = (4, 4, 4, 4)
-    rng = synth.make_rng(925, 0)
-    U = synth.random_su3_near_identity(dims, 0.3, rng)
-    lat = _naik_lattice(dims, U)
-    phi = lat.vec_import(dev(synth.gaussian_half_vector(dims, rng)), 0)
+FORCE_CASES = [
+    ((4, 4, 2, 4), 0.5, stag.LINKS_F64_18),
+    ((2, 2, 2, 2), 0.5, stag.LINKS_F64_18),    # a three-link path runs over one link twice
+    ((4, 4, 4, 4), 0.4, stag.LINKS_F64_12),    # forward and backward three-link paths share links
+    ((8, 6, 4, 10), 0.4, stag.LINKS_F64_18),   # several tiles and a ragged tail
+]
+
+
+@pytest.mark.parametrize("dims,eps,fmt", FORCE_CASES)
+def test_naik_force_and_action_match_oracle(dims, eps, fmt):
+    """Pseudofermion force and action of the improved operator against the
+    oracle's (whose force is pinned by finite differences of its action):
+    mom = F and the kick mom += dt F."""
+    log(f"naik force parity dims={dims} fmt={fmt}")
+    rng = synth.make_rng(925, hash(dims) % 1000)
+    U = synth.random_su3_near_identity(dims, eps, rng)
+    lat = _naik_lattice(dims, U, fmt)
+    phi = synth.gaussian_half_vector(dims, rng)
     rat = synth.load_rational("xm050_n8_m0.1")
-    with pytest.raises(stag.StagError) as ei:
-        lat.fermion_force(0.1, rat, 1e-10, 1000, phi, lat.new_mom())
-    assert ei.value.code == stag.STAG_ERR_INVALID_ARG
+    phid = lat.vec_import(dev(phi), 0)
+    mom = lat.new_mom()
+    lat.fermion_force(0.1, rat, 1e-12, 100000, phid, mom, 0.0)
+    exp = naik.fermion_force(U, dims, 0.1, phi, rat, 1e-12)
+    assert rel_err(host(lat.mom_export(mom)), exp) < 1e-9
+    P = synth.gaussian_momentum(dims, rng)
+    m2 = lat.mom_import(dev(P))
+    lat.fermion_force(0.1, rat, 1e-12, 100000, phid, m2, 0.05)
+    assert rel_err(host(lat.mom_export(m2)), P + 0.05 * exp) < 1e-9
+    S = lat.fermion_action(0.1, rat, 1e-12, 100000, phid)
+    assert abs(S - naik.fermion_action(U, dims, 0.1, phi, rat, 1e-12)) < 1e-10 * abs(S)
+
+
+def test_naik_trajectory_matches_oracle():
+    """One trajectory with the improved operator in heat bath, force and
+    actions against the oracle trajectory with the same momenta, noise and
+    uniform."""
+    dims = (4, 4, 2, 4)
+    log("naik trajectory parity 4x4x2x4")
+    rng = synth.make_rng(927, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.4, rng)
+    seed, traj = 2024, 5
+    prm = hmc.HMCParams(beta=5.4, mass=0.1, tau=0.5, n_steps=6,
+                        r_md=synth.load_rational("xm050_n8_m0.1"),
+                        r_action=synth.load_rational("xm050_n8_m0.1"),
+                        r_heatbath=synth.load_rational("xp025_n8_m0.1"),
+                        tol_md=1e-12, tol_action=1e-12, naik=(naik.C1, naik.C3))
+    P0 = philox.momentum(dims, seed, traj)
+    xi = philox.source(dims, seed, traj)
+    u = philox.uniform(seed, traj)
+    ref = hmc.trajectory(U0, dims, prm, P0, xi, u)
+    lat = _naik_lattice(dims, U0)
+    out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                         tol_md=1e-12, tol_action=1e-12, seed=seed, traj_index=traj)
+    log(f"  dH gpu {out['dH']:.12e} oracle {ref['dH']:.12e}")
+    K0, Sg0, Sf0 = ref["H0"]
+    K1, Sg1, Sf1 = ref["H1"]
+    for a, b in [(out["K_old"], K0), (out["Sg_old"], Sg0), (out["Sf_old"], Sf0),
+                 (out["K_new"], K1), (out["Sg_new"], Sg1), (out["Sf_new"], Sf1)]:
+        assert abs(a - b) <= 1e-10 * abs(b)
+    assert abs(out["dH"] - ref["dH"]) < 1e-8
+    assert out["accepted"] == int(ref["accepted"])
+    assert np.abs(host(lat.get_gauge()) - ref["U"]).max() < 1e-10
+
+
+def test_naik_leapfrog_reversible_at_16c8():
+    """At the RHMC workload's 16^3x8, a property that holds at any size:
+    leapfrog with the improved operator's force, run forward, momenta
+    flipped, run again, returns to the starting links and negated momenta."""
+    dims = (16, 16, 16, 8)
+    log("naik leapfrog reversibility at 16^3x8")
+    rng = synth.make_rng(928, 0)
+    U0 = synth.random_su3_near_identity(dims, 0.3, rng)
+    phi = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm050_n12_m0.02")
+    lat = _naik_lattice(dims, U0)
+    phid = lat.vec_import(dev(phi), 0)
+    mom = lat.random_momentum(9, 2)
+    P0 = host(lat.mom_export(mom))
+    dt, n = 0.05, 4
+
+    def kick(h):
+        lat.gauge_force(5.4, mom, h)
+        lat.fermion_force(0.02, rat, 1e-12, 100000, phid, mom, h)
+
+    def leapfrog():
+        kick(0.5 * dt)
+        for s in range(n):
+            lat.link_update(mom, dt)
+            kick(dt if s < n - 1 else 0.5 * dt)
+
+    leapfrog()
+    U1 = host(lat.get_gauge())
+    assert np.abs(U1 - U0).max() > 1e-3
+    mom.copy_(lat.mom_import(dev(-host(lat.mom_export(mom)))))
+    leapfrog()
+    dU = np.abs(host(lat.get_gauge()) - U0).max()
+    dP = np.abs(host(lat.mom_export(mom)) + P0).max()
+    log(f"  |dU| {dU:.2e} |dP| {dP:.2e}")
+    assert dU < 1e-9
+    assert dP < 1e-8 * np.abs(P0).max()
 
 
 def test_naik_multishift_matches_oracle():
