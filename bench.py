@@ -342,10 +342,11 @@ def surrogate_trace_mode(n_pairs=64, epochs=4):
                       "apply_us": round(1e6 * t_apply, 2), "loss": loss}), flush=True)
 
 
-def trajectory_trace_mode(n_traj=3):
+def trajectory_trace_mode(n_traj=3, improved=False):
     """A few RHMC trajectories at 16^3x8 (beta 5.4, m 0.02, the 12-pole MD
     table with 20-pole action and heat-bath tables, tau 1, 20 steps) from a near-identity start, after one untimed one: a
-    short program for a kernel trace of the trajectory's launches."""
+    short program for a kernel trace of the trajectory's launches.  improved:
+    the Naik-improved operator with the tables on [m^2, 88]."""
     import torch
 
     import synth
@@ -354,9 +355,12 @@ def trajectory_trace_mode(n_traj=3):
     dims = (16, 16, 16, 8)
     lat = Lattice(dims)
     lat.set_gauge(torch.from_numpy(synth.random_su3_near_identity(dims, 0.5, synth.make_rng(5, 0))).cuda())
-    r_f = synth.load_rational("xm050_n12_m0.02")
-    r_a = synth.load_rational("xm050_n20_m0.02")
-    r_h = synth.load_rational("xp025_n20_m0.02")
+    suffix = "_h88" if improved else ""
+    if improved:
+        lat.set_naik(9.0 / 8.0, -1.0 / 24.0)
+    r_f = synth.load_rational("xm050_n12_m0.02" + suffix)
+    r_a = synth.load_rational("xm050_n20_m0.02" + suffix)
+    r_h = synth.load_rational("xp025_n20_m0.02" + suffix)
     kw = dict(tol_md=1e-8, tol_action=1e-10, seed=11)
     lat.trajectory(5.4, 0.02, 1.0, 20, r_f, r_a, r_h, inject_u=0.0, traj_index=0, **kw)
     torch.cuda.synchronize()
@@ -365,7 +369,7 @@ def trajectory_trace_mode(n_traj=3):
            for i in range(n_traj)]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / n_traj
-    print(json.dumps({"trajectory_trace_mode": True, "sec_per_traj": round(dt, 4),
+    print(json.dumps({"trajectory_trace_mode": True, "improved": improved, "sec_per_traj": round(dt, 4),
                       "cg_iters": [r["cg_iters_total"] for r in res]}), flush=True)
 
 
@@ -395,6 +399,8 @@ def main():
     ap.add_argument("--pmc-mode", action="store_true", help="one solve + a 512 MiB copy, for counter runs")
     ap.add_argument("--trajectory-trace-mode", action="store_true",
                     help="a few 16^3x8 RHMC trajectories, for a kernel trace")
+    ap.add_argument("--improved", action="store_true",
+                    help="with --trajectory-trace-mode: the Naik-improved operator")
     ap.add_argument("--summarize-trace", metavar="KERNEL_TRACE_CSV")
     ap.add_argument("--surrogate-trace-mode", action="store_true",
                     help="the learned model's kernels at 16^3x8, for a kernel trace")
@@ -406,7 +412,7 @@ def main():
         print(text)
         return
     if args.trajectory_trace_mode:
-        trajectory_trace_mode()
+        trajectory_trace_mode(improved=args.improved)
         return
     if args.force_channel_probe:
         force_channel_probe()
