@@ -8,6 +8,7 @@ to anything else.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import Sequence
 
@@ -210,6 +211,18 @@ def _buf(t, nbytes: int, what: str, optional: bool = False) -> int | None:
     if got != nbytes:
         raise ValueError(f"{what}: expected {nbytes} bytes, got {got}")
     return _ptr(t)
+
+
+def append_jsonl(log, record: dict) -> None:
+    """Append record as one JSON line to log (a path, or an open text file):
+    the per-trajectory log of a chain."""
+    line = json.dumps(record, sort_keys=True) + "\n"
+    if isinstance(log, (str, os.PathLike)):
+        with open(log, "a") as f:
+            f.write(line)
+    else:
+        log.write(line)
+        log.flush()
 
 
 class RationalArg:
@@ -444,7 +457,10 @@ class Lattice:
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
                    no_fermions=False, surrogate=None, exact_every=1, coarse_force=False,
-                   record_pairs=False, inner_iters=0, md_link_format=0, spectrum=None) -> dict:
+                   record_pairs=False, inner_iters=0, md_link_format=0, spectrum=None, log=None) -> dict:
+        """One RHMC trajectory (stag_md_trajectory); returns the trajectory
+        info as a dict.  log: a path or open text file that receives the info
+        with the trajectory's parameters as one JSON line."""
         a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
         prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
                          self._mom(inject_mom, "inject_mom", True), self._vec(inject_xi, "inject_xi", True),
@@ -454,7 +470,13 @@ class Lattice:
                          *(map(float, spectrum) if spectrum is not None else (0.0, 0.0)))
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
-        return {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
+        out = {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
+        if log is not None:
+            append_jsonl(log, dict(out, seed=int(seed), traj_index=int(traj_index), beta=float(beta),
+                                   mass=float(mass), tau=float(tau), n_steps=int(n_steps),
+                                   exact_every=int(exact_every), model=surrogate is not None,
+                                   md_link_format=int(md_link_format)))
+        return out
 
     # ---- measurement / tuning
     def set_shift_window(self, lag: int):

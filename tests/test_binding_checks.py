@@ -98,3 +98,26 @@ def test_batch_masses_and_instance_are_checked():
     with pytest.raises(ValueError, match="bytes"):
         b.set_gauge(1, torch.zeros((256, 4, 3, 3), dtype=torch.complex128))
     assert b.lib.calls == []
+
+
+def test_trajectory_log_appends_one_json_line_per_trajectory(tmp_path):
+    """The per-trajectory log: one JSON object per call with the info fields
+    and the trajectory's parameters (library replaced by the recorder, so
+    the info is all zeros)."""
+    import io
+    import json
+    lat = _lattice()
+    rat = {"c0": 0.1, "residue": [0.5, 0.25], "pole": [0.01, 1.0]}
+    path = tmp_path / "chain.jsonl"
+    for t in range(2):
+        out = lat.trajectory(5.4, 0.02, 1.0, 20, rat, rat, rat, seed=7, traj_index=t, log=str(path))
+    buf = io.StringIO()
+    lat.trajectory(5.4, 0.02, 1.0, 20, rat, rat, rat, seed=7, traj_index=2, log=buf)
+    lines = path.read_text().splitlines() + buf.getvalue().splitlines()
+    assert lat.lib.calls.count("stag_md_trajectory") == 3
+    recs = [json.loads(x) for x in lines]
+    assert [r["traj_index"] for r in recs] == [0, 1, 2]
+    for r in recs:
+        assert set(out) <= set(r)
+        assert (r["seed"], r["beta"], r["mass"], r["tau"], r["n_steps"]) == (7, 5.4, 0.02, 1.0, 20)
+        assert r["model"] is False and r["accepted"] == 0

@@ -187,6 +187,36 @@ def test_naik_trajectory_matches_oracle():
     assert np.abs(host(lat.get_gauge()) - ref["U"]).max() < 1e-10
 
 
+@pytest.mark.parametrize("fmt", [2, 3])
+def test_naik_fp32_md_forces(fmt):
+    """Improved-operator trajectories with the MD force solves in FP32 Krylov
+    vectors (FP32-18 or FP16-12 long and one-hop links): deterministic, FP64
+    actions, dH close to the oracle's FP64 trajectory with the same fields."""
+    dims = (4, 4, 2, 4)
+    log(f"naik trajectory, MD solves in link format {fmt}")
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(927, 1))
+    seed, traj = 78, 3
+    prm = hmc.HMCParams(beta=5.4, mass=0.1, tau=0.5, n_steps=6,
+                        r_md=synth.load_rational("xm050_n8_m0.1"),
+                        r_action=synth.load_rational("xm050_n8_m0.1"),
+                        r_heatbath=synth.load_rational("xp025_n8_m0.1"),
+                        tol_md=1e-12, tol_action=1e-12, naik=(naik.C1, naik.C3))
+    ref = hmc.trajectory(U0, dims, prm, philox.momentum(dims, seed, traj), philox.source(dims, seed, traj),
+                         philox.uniform(seed, traj))
+    lat = _naik_lattice(dims, U0)
+    outs = []
+    for _ in range(2):
+        lat.set_gauge(dev(U0))
+        outs.append(lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action,
+                                   prm.r_heatbath, tol_md=1e-8, tol_action=1e-12, seed=seed, traj_index=traj,
+                                   md_link_format=fmt))
+    assert outs[0]["dH"] == outs[1]["dH"]
+    log(f"  fmt {fmt}: dH {outs[0]['dH']:.6e} oracle FP64 {ref['dH']:.6e}")
+    assert abs(outs[0]["Sf_old"] - ref["H0"][2]) <= 1e-10 * abs(ref["H0"][2])
+    tol = 1e-4 if fmt == 2 else 5e-2
+    assert abs(outs[0]["dH"] - ref["dH"]) < tol * max(1.0, abs(ref["dH"]))
+
+
 def test_naik_leapfrog_reversible_at_16c8():
     """At the RHMC workload's 16^3x8, a property that holds at any size:
     leapfrog with the improved operator's force, run forward, momenta
