@@ -944,7 +944,7 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     return out
 
 
-def improved_rhmc(lat, U_therm, summary, t_first, n_traj, beta, mass, tau, n_steps, kw, n_therm=3):
+def improved_rhmc(lat, U_therm, summary, t_first, n_traj, beta, mass, tau, n_steps, kw, n_therm=8):
     """The same RHMC with the Naik-improved operator (c1 = 9/8, c3 = -1/24) in
     heat bath, force and actions, tables on [m^2, 88] (A is bounded by 87.1):
     n_therm accepted trajectories from the one-hop chain's configuration, then
