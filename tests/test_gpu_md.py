@@ -54,6 +54,62 @@ def test_fermion_force_and_action(dims):
     assert abs(S - fermion.fermion_action(U, dims, 0.1, phi, rat, 1e-12)) < 1e-10 * abs(S)
 
 
+@pytest.mark.parametrize("improved", [False, True])
+def test_fermion_force_of_a_zero_field(improved):
+    """phi = 0: the solve returns zeros without iterating, the force is exactly
+    zero and a kick leaves the momenta unchanged (plain and improved operator)."""
+    dims = (4, 4, 2, 4)
+    rng = synth.make_rng(201, 7)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    lat = lattice(dims, U)
+    if improved:
+        lat.set_naik(9.0 / 8.0, -1.0 / 24.0)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    phi = lat.vec_import(dev(np.zeros((dims[0] * dims[1] * dims[2] * dims[3] // 2, 3), np.complex128)), 0)
+    mom = lat.new_mom()
+    lat.fermion_force(0.1, rat, 1e-12, 100, phi, mom, 0.0)
+    assert not np.any(host(lat.mom_export(mom)))
+    P = synth.gaussian_momentum(dims, rng)
+    m2 = lat.mom_import(dev(P))
+    lat.fermion_force(0.1, rat, 1e-12, 100, phi, m2, 0.05)
+    assert np.array_equal(host(lat.mom_export(m2)), P)
+
+
+def test_gauge_force_and_link_update_full_size_16c8():
+    """Gauge force, action, plaquette and one link update at 16^3x8 against
+    the oracle, every link."""
+    dims = (16, 16, 16, 8)
+    log("gauge force and link update parity at 16^3x8")
+    rng = synth.make_rng(200, 16)
+    U = synth.random_su3_near_identity(dims, 0.5, rng)
+    lat = lattice(dims, U)
+    mom = lat.new_mom()
+    lat.gauge_force(5.4, mom, 0.0)
+    assert rel_err(host(lat.mom_export(mom)), gauge.gauge_force(U, dims, 5.4)) < 1e-13
+    S, plaq = lat.gauge_action(5.4)
+    assert abs(S - gauge.gauge_action(U, dims, 5.4)) < 1e-11 * abs(S)
+    assert abs(plaq - gauge.mean_plaquette(U, dims)) < 1e-14
+    P = synth.gaussian_momentum(dims, rng)
+    lat.link_update(lat.mom_import(dev(P)), 0.05)
+    assert np.abs(host(lat.get_gauge()) - hmc.link_update(U, P, 0.05)).max() < 1e-13
+
+
+def test_fermion_force_full_size_16c8():
+    """Every link's pseudofermion force at the RHMC workload's 16^3x8 (the
+    launch configuration the trajectories use) against the oracle's."""
+    dims = (16, 16, 16, 8)
+    log("fermion force parity at 16^3x8")
+    rng = synth.make_rng(201, 16)
+    U = synth.random_su3_near_identity(dims, 0.3, rng)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    phi = synth.gaussian_half_vector(dims, rng)
+    lat = lattice(dims, U)
+    mom = lat.new_mom()
+    lat.fermion_force(0.1, rat, 1e-12, 100000, lat.vec_import(dev(phi), 0), mom, 0.0)
+    exp = fermion.fermion_force(U, dims, 0.1, phi, rat, 1e-12)
+    assert rel_err(host(lat.mom_export(mom)), exp) < 1e-9
+
+
 @pytest.mark.parametrize("dims", DIMS[:2])
 def test_link_update(dims):
     log(f"link update parity dims={dims}")

@@ -155,6 +155,22 @@ def test_naik_force_and_action_match_oracle(dims, eps, fmt):
     assert abs(S - naik.fermion_action(U, dims, 0.1, phi, rat, 1e-12)) < 1e-10 * abs(S)
 
 
+def test_naik_force_full_size_16c8():
+    """Every link's improved-operator force at the RHMC workload's 16^3x8
+    against the oracle's (the oracle's solve and force take ~30 s)."""
+    dims = (16, 16, 16, 8)
+    log("naik force parity at 16^3x8")
+    rng = synth.make_rng(925, 16)
+    U = synth.random_su3_near_identity(dims, 0.3, rng)
+    lat = _naik_lattice(dims, U)
+    phi = synth.gaussian_half_vector(dims, rng)
+    rat = synth.load_rational("xm050_n8_m0.1")
+    mom = lat.new_mom()
+    lat.fermion_force(0.1, rat, 1e-12, 100000, lat.vec_import(dev(phi), 0), mom, 0.0)
+    exp = naik.fermion_force(U, dims, 0.1, phi, rat, 1e-12)
+    assert rel_err(host(lat.mom_export(mom)), exp) < 1e-9
+
+
 def test_naik_trajectory_matches_oracle():
     """One trajectory with the improved operator in heat bath, force and
     actions against the oracle trajectory with the same momenta, noise and
