@@ -95,8 +95,10 @@ __global__ __launch_bounds__(kBlock) void k_fermion_force(Geom g, int par, const
     }
 }
 
-// ---- three-hop part of the improved operator's force
-// (the variation of each link in the three-link paths through it).
+// ---- three-hop part of the force of the improved operator (the "improved"
+// quarks of the Summary, Sec. 8, read as the Naik stencil): S_f of Sec. 3.1
+// differentiated through every three-link path a link lies on, at path
+// positions 0, 1 and 2 (paths starting at z, z-mu and z-2mu).
 __device__ __forceinline__ int step_mod(int v, int d, int n) {
     v += d;
     while (v < 0) v += n;
