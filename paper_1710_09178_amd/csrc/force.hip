@@ -36,63 +36,65 @@ __device__ __forceinline__ void store_force(double* __restrict__ mom, const Geom
 // F_a(x,mu) = 2 Im tr(T_a s U_mu(x) W),  W = eps(x) sum_k c_k chi_k(x+mu) chi_k(x)^dag,
 // chi_k = X_k on even sites and Y_k = D_oe X_k on odd sites, eps = +1 (even) / -1 (odd).
 // (w1: the weight of the one-hop term, c1 for the improved operator, else 1)
-__global__ __launch_bounds__(kBlock) void k_fermion_force(Geom g, int par, const double2* __restrict__ links,
+// One thread per link (mu, parity, site): consecutive threads take consecutive
+// sites of one (mu, parity) plane, so every stream is contiguous.
+__global__ __launch_bounds__(kBlock) void k_fermion_force(Geom g, const double2* __restrict__ links,
                                                           VecPtrs X, VecPtrs Y, const double* __restrict__ coef,
                                                           int n, double* __restrict__ mom, double dt, double w1) {
-    const int cb = blockIdx.x * kBlock + threadIdx.x;
-    if (cb >= g.vh) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 8 * g.vh) return;
+    const int mu = i / (2 * g.vh), rem = i % (2 * g.vh);
+    const int par = rem / g.vh, cb = rem % g.vh;
     int x, y, z, t;
     cb_coords(g, par, cb, x, y, z, t);
     const double eps = par == 0 ? 1.0 : -1.0;
-    for (int mu = 0; mu < 4; ++mu) {
-        int xn = x, yn = y, zn = z, tn = t;
-        double s;
-        if (mu == 0) {
-            xn = (x + 1 == g.nx) ? 0 : x + 1;
-            s = 1.0;
-        } else if (mu == 1) {
-            yn = (y + 1 == g.ny) ? 0 : y + 1;
-            s = (x & 1) ? -1.0 : 1.0;
-        } else if (mu == 2) {
-            zn = (z + 1 == g.nz) ? 0 : z + 1;
-            s = ((x + y) & 1) ? -1.0 : 1.0;
-        } else {
-            tn = (t + 1 == g.nt) ? 0 : t + 1;
-            s = ((x + y + z) & 1) ? -1.0 : 1.0;
-            if (t == g.nt - 1) s = -s;
-        }
-        const int cbn = cb_index(g, xn, yn, zn, tn);
-        M3 W;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) W.e[e] = make_double2(0.0, 0.0);
-        for (int k = 0; k < n; ++k) {
-            const double2* here = (par == 0 ? X.at<double2>(k) : Y.at<double2>(k));
-            const double2* there = (par == 0 ? Y.at<double2>(k) : X.at<double2>(k));
-            double2 a[3], b[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                a[c] = there[(size_t)c * g.vh + cbn];
-                b[c] = here[(size_t)c * g.vh + cb];
-            }
-            const double ck = coef[k];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const double2 v = cmul(a[i], cconj(b[j]));
-                    W.e[3 * i + j].x += ck * v.x;
-                    W.e[3 * i + j].y += ck * v.y;
-                }
-        }
-        M3 U = load_link(links, g, par, cb, mu);
-        M3 M = m3_mul(U, W);
-        double f[8];
-        im_tr_ta(M, f);
-        const double fac = 2.0 * s * eps * w1;
-#pragma unroll
-        for (int a = 0; a < 8; ++a) f[a] *= fac;
-        store_force(mom, g, par, mu, cb, f, dt);
+    int xn = x, yn = y, zn = z, tn = t;
+    double s;
+    if (mu == 0) {
+        xn = (x + 1 == g.nx) ? 0 : x + 1;
+        s = 1.0;
+    } else if (mu == 1) {
+        yn = (y + 1 == g.ny) ? 0 : y + 1;
+        s = (x & 1) ? -1.0 : 1.0;
+    } else if (mu == 2) {
+        zn = (z + 1 == g.nz) ? 0 : z + 1;
+        s = ((x + y) & 1) ? -1.0 : 1.0;
+    } else {
+        tn = (t + 1 == g.nt) ? 0 : t + 1;
+        s = ((x + y + z) & 1) ? -1.0 : 1.0;
+        if (t == g.nt - 1) s = -s;
     }
+    const int cbn = cb_index(g, xn, yn, zn, tn);
+    M3 W;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) W.e[e] = make_double2(0.0, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const double2* here = (par == 0 ? X.at<double2>(k) : Y.at<double2>(k));
+        const double2* there = (par == 0 ? Y.at<double2>(k) : X.at<double2>(k));
+        double2 a[3], b[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a[c] = there[(size_t)c * g.vh + cbn];
+            b[c] = here[(size_t)c * g.vh + cb];
+        }
+        const double ck = coef[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double2 v = cmul(a[r], cconj(b[j]));
+                W.e[3 * r + j].x += ck * v.x;
+                W.e[3 * r + j].y += ck * v.y;
+            }
+    }
+    M3 U = load_link(links, g, par, cb, mu);
+    M3 M = m3_mul(U, W);
+    double f[8];
+    im_tr_ta(M, f);
+    const double fac = 2.0 * s * eps * w1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) f[a] *= fac;
+    store_force(mom, g, par, mu, cb, f, dt);
 }
 
 // ---- three-hop part of the force of the improved operator (the "improved"
@@ -107,55 +109,54 @@ __device__ __forceinline__ int step_mod(int v, int d, int n) {
 }
 
 // W3(x, mu) = s3(x) eps(x) sum_k c_k chi_k(x+3mu) chi_k(x)^dag, one thread per
-// site of parity par, the four directions in turn; s3 is the path's sign
-// (eta_mu(x) once, -1 per link that leaves the last time slice).
-__global__ __launch_bounds__(kBlock) void k_naik_w3(Geom g, int par, VecPtrs X, VecPtrs Y,
-                                                    const double* __restrict__ coef, int n,
-                                                    double2* __restrict__ w3) {
-    const int cb = blockIdx.x * kBlock + threadIdx.x;
-    if (cb >= g.vh) return;
+// (mu, parity, site); s3 is the path's sign (eta_mu(x) once, -1 per link that
+// leaves the last time slice).
+__global__ __launch_bounds__(kBlock) void k_naik_w3(Geom g, VecPtrs X, VecPtrs Y, const double* __restrict__ coef,
+                                                    int n, double2* __restrict__ w3) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= 8 * g.vh) return;
+    const int mu = i / (2 * g.vh), rem = i % (2 * g.vh);
+    const int par = rem / g.vh, cb = rem % g.vh;
     int c[4];
     cb_coords(g, par, cb, c[0], c[1], c[2], c[3]);
     const int nn[4] = {g.nx, g.ny, g.nz, g.nt};
     const double eps = par == 0 ? 1.0 : -1.0;
-    for (int mu = 0; mu < 4; ++mu) {
-        int d[4] = {c[0], c[1], c[2], c[3]};
-        d[mu] = step_mod(c[mu], 3, nn[mu]);
-        const int cb3 = cb_index(g, d[0], d[1], d[2], d[3]);
-        double s = 1.0;
-        if (mu == 1) s = (c[0] & 1) ? -1.0 : 1.0;
-        if (mu == 2) s = ((c[0] + c[1]) & 1) ? -1.0 : 1.0;
-        if (mu == 3) {
-            s = ((c[0] + c[1] + c[2]) & 1) ? -1.0 : 1.0;
-            if (((c[3] + 3) / g.nt) & 1) s = -s;
-        }
-        M3 W;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) W.e[e] = make_double2(0.0, 0.0);
-        for (int k = 0; k < n; ++k) {
-            const double2* here = (par == 0 ? X.at<double2>(k) : Y.at<double2>(k));
-            const double2* there = (par == 0 ? Y.at<double2>(k) : X.at<double2>(k));
-            double2 a[3], b[3];
-#pragma unroll
-            for (int cc = 0; cc < 3; ++cc) {
-                a[cc] = there[(size_t)cc * g.vh + cb3];
-                b[cc] = here[(size_t)cc * g.vh + cb];
-            }
-            const double ck = coef[k];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const double2 v = cmul(a[i], cconj(b[j]));
-                    W.e[3 * i + j].x += ck * v.x;
-                    W.e[3 * i + j].y += ck * v.y;
-                }
-        }
-        const double fac = s * eps;
-        double2* out = w3 + link_off(g, par, mu, 0) + cb;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) out[(size_t)e * g.vh] = make_double2(fac * W.e[e].x, fac * W.e[e].y);
+    int d[4] = {c[0], c[1], c[2], c[3]};
+    d[mu] = step_mod(c[mu], 3, nn[mu]);
+    const int cb3 = cb_index(g, d[0], d[1], d[2], d[3]);
+    double s = 1.0;
+    if (mu == 1) s = (c[0] & 1) ? -1.0 : 1.0;
+    if (mu == 2) s = ((c[0] + c[1]) & 1) ? -1.0 : 1.0;
+    if (mu == 3) {
+        s = ((c[0] + c[1] + c[2]) & 1) ? -1.0 : 1.0;
+        if (((c[3] + 3) / g.nt) & 1) s = -s;
     }
+    M3 W;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) W.e[e] = make_double2(0.0, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const double2* here = (par == 0 ? X.at<double2>(k) : Y.at<double2>(k));
+        const double2* there = (par == 0 ? Y.at<double2>(k) : X.at<double2>(k));
+        double2 a[3], b[3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            a[cc] = there[(size_t)cc * g.vh + cb3];
+            b[cc] = here[(size_t)cc * g.vh + cb];
+        }
+        const double ck = coef[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double2 v = cmul(a[r], cconj(b[j]));
+                W.e[3 * r + j].x += ck * v.x;
+                W.e[3 * r + j].y += ck * v.y;
+            }
+    }
+    const double fac = s * eps;
+    double2* out = w3 + link_off(g, par, mu, 0) + cb;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) out[(size_t)e * g.vh] = make_double2(fac * W.e[e].x, fac * W.e[e].y);
 }
 
 // F_a(z, mu) += 2 c3 Im tr(T_a U(z) [U(z+mu) U(z+2mu) W3(z) + U(z+mu) W3(z-mu) U(z-mu)
@@ -381,16 +382,15 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(size_t n, const double* __rest
 
 void launch_fermion_force(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,
                           double* mom, double dt, hipStream_t s, double w1) {
-    const int grid = (g.vh + kBlock - 1) / kBlock;
-    for (int par = 0; par < 2; ++par)
-        k_fermion_force<<<grid, kBlock, 0, s>>>(g, par, links, X, Y, coef, n, mom, dt, w1);
+    const int grid = (8 * g.vh + kBlock - 1) / kBlock;
+    k_fermion_force<<<grid, kBlock, 0, s>>>(g, links, X, Y, coef, n, mom, dt, w1);
 }
 
 void launch_naik_force3(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,
                         double2* w3, double c3, double* mom, double dt, hipStream_t s) {
-    const int grid = (g.vh + kBlock - 1) / kBlock;
-    for (int par = 0; par < 2; ++par) k_naik_w3<<<grid, kBlock, 0, s>>>(g, par, X, Y, coef, n, w3);
-    k_naik_force3<<<(8 * g.vh + kBlock - 1) / kBlock, kBlock, 0, s>>>(g, links, w3, c3, mom, dt);
+    const int grid = (8 * g.vh + kBlock - 1) / kBlock;
+    k_naik_w3<<<grid, kBlock, 0, s>>>(g, X, Y, coef, n, w3);
+    k_naik_force3<<<grid, kBlock, 0, s>>>(g, links, w3, c3, mom, dt);
 }
 
 void launch_gauge_force(const Geom& g, const double2* links, double beta, double* mom, double dt, hipStream_t s) {
