@@ -451,7 +451,11 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
         if (site_ok) hop(g, L, f.p_prev, 1, mu, cb, x, y, z, t, acc);
         if (own) o_r = r_prev[oi];
     } else {
-        constexpr int kU = 8;
+        // the fused loop runs on grids of at most 512 blocks, whose partials
+        // two loads per thread and array cover (a larger grid adds the rest
+        // in the loop below); more unconditional loads would only repeat the
+        // clamped last index
+        constexpr int kU = 2;
         const int nb2 = f.nb2;
         double tq[kU], t1[kU], t2[kU], t3[kU];
 #pragma unroll
