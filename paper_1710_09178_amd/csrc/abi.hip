@@ -303,7 +303,7 @@ stag_status stag_destroy(stag_handle c) {
     if (!c) return STAG_OK;
     if (c->s) hipStreamSynchronize(c->s);
     void* bufs[] = {c->links_d12, c->links_s18, c->links_h12, c->long_d18, c->long_d12, c->long_s18, c->long_h12,
-                    c->naik_w3, c->r32, c->p32, c->Ap32, c->w32,
+                    c->naik_w3, c->r32, c->p32, c->p2_32, c->Ap32, c->w32,
                     c->links, c->links_backup, c->mom, c->r, c->p, c->p2, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
                     c->gpart, c->scal, c->mom_tmp, c->mom_aux};

@@ -366,8 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_ms_step(int n3, V* __restrict__ ring
 // iteration j = i0 + L, npend = L, skipped once the solve has stopped (gate);
 // final = 1: once after the loop, npend = fin.iter % L (the steps pending at
 // the stop).  Block row y takes the shift groups y, y + gridDim.y, ...
-template <int EPT>
-__global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const double2* __restrict__ ring, VecPtrs x, VecPtrs ps,
+template <class V, int EPT>
+__global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const V* __restrict__ ring, VecPtrs x, VecPtrs ps,
                                                      const MsState* __restrict__ st, const int* __restrict__ gate,
                                                      int n, int base, int L, int final_flush) {
     if (!final_flush && *gate) return;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const double2* __re
 #pragma unroll
         for (int t = 0; t < kLagMax; ++t) {
             if (t >= npend) break;
-            rw[t] = ring[(size_t)((t + 1) % L) * n3 + i];
+            rw[t] = to_d2(ring[(size_t)((t + 1) % L) * n3 + i]);
         }
         for (int g0 = blockIdx.y * G; g0 < nact; g0 += gridDim.y * G) {
             double2 pk[G], xk[G];
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const double2* __re
             for (int jj = 0; jj < G; ++jj) {
                 if (g0 + jj < nact) {
                     const int q = sh_list[g0 + jj];
-                    pk[jj] = nt_load(ps.at<double2>(q) + i);
+                    pk[jj] = to_d2(nt_load(ps.at<V>(q) + i));
                     xk[jj] = nt_load(x.at<double2>(q) + i);
                 }
             }
@@ -423,7 +423,9 @@ __global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const double2* __re
                         if (w_act[t][q]) {
                             const double aq = w_as[t][q], bq = w_bs[t][q], zq = w_zn[t][q];
                             xk[jj] = make_double2(xk[jj].x + aq * pk[jj].x, xk[jj].y + aq * pk[jj].y);
-                            pk[jj] = make_double2(zq * rw[t].x + bq * pk[jj].x, zq * rw[t].y + bq * pk[jj].y);
+                            // p_s is kept in the Krylov precision between steps
+                            pk[jj] = to_d2(from_d2<V>(make_double2(zq * rw[t].x + bq * pk[jj].x,
+                                                                   zq * rw[t].y + bq * pk[jj].y)));
                         }
                     }
                 }
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_ms_flush(int n3, const double2* __re
                 if (g0 + jj < nact) {
                     const int q = sh_list[g0 + jj];
                     nt_store(x.at<double2>(q) + i, xk[jj]);
-                    nt_store(ps.at<double2>(q) + i, pk[jj]);
+                    nt_store(ps.at<V>(q) + i, from_d2<V>(pk[jj]));
                 }
             }
         }
@@ -538,15 +540,20 @@ template void launch_ms_step<float2>(const Geom&, float2*, const float2*, float2
                                      const double*, int, const double*, double*, int, int, MsStepConst,
                                      hipStream_t);
 
-void launch_ms_flush(const Geom& g, const double2* ring, VecPtrs x, VecPtrs ps, const MsState* st, const int* gate,
+template <class V>
+void launch_ms_flush(const Geom& g, const V* ring, VecPtrs x, VecPtrs ps, const MsState* st, const int* gate,
                      int n, int base, int L, bool final_flush, int rows, hipStream_t s) {
     if (ms_ept(g) == 1)
-        timed_launch(k_ms_flush<1>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, ring, x, ps, st, gate, n, base, L,
-                     (int)final_flush);
+        timed_launch(k_ms_flush<V, 1>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, ring, x, ps, st, gate, n, base,
+                     L, (int)final_flush);
     else
-        timed_launch(k_ms_flush<2>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, ring, x, ps, st, gate, n, base, L,
-                     (int)final_flush);
+        timed_launch(k_ms_flush<V, 2>, dim3(gridq(g), rows), dim3(kBlock), s, 3 * g.vh, ring, x, ps, st, gate, n, base,
+                     L, (int)final_flush);
 }
+template void launch_ms_flush<double2>(const Geom&, const double2*, VecPtrs, VecPtrs, const MsState*, const int*, int,
+                                       int, int, bool, int, hipStream_t);
+template void launch_ms_flush<float2>(const Geom&, const float2*, VecPtrs, VecPtrs, const MsState*, const int*, int,
+                                      int, int, bool, int, hipStream_t);
 
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s) {
     if (ms_ept(g) == 1)

@@ -334,8 +334,10 @@ void launch_ms_step(const Geom& g, V* r, const V* Ap, V* p, VecPtrs x, VecPtrs p
                     int nb2, const double* qin, double* qout, int par, int rows, MsStepConst sc, hipStream_t s);
 // Window flush of the fused loop (see blas.hip): final = false after iteration
 // j (j % L == 0, gated by the stop flag that iteration's D_oe launch writes),
-// true once after the loop for the steps pending at the stop
-void launch_ms_flush(const Geom& g, const double2* ring, VecPtrs x, VecPtrs ps, const MsState* st, const int* gate,
+// true once after the loop for the steps pending at the stop; V: the Krylov
+// precision of the ring and of the shifted p_k (x_k stay FP64)
+template <class V>
+void launch_ms_flush(const Geom& g, const V* ring, VecPtrs x, VecPtrs ps, const MsState* st, const int* gate,
                      int n, int base, int L, bool final_flush, int rows, hipStream_t s);
 // p = r and partials of |r|^2 (restart of a CG from a given residual)
 void launch_cg_restart(const Geom& g, const float2* r, float2* p, double* qout, hipStream_t s);

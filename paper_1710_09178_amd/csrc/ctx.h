@@ -39,6 +39,7 @@ struct stag_ctx {
     // FP64 Krylov workspace
     double2 *r = nullptr /* ring of kLagMax residuals */, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
     double2* p2 = nullptr;   // second search direction (the fused loop double-buffers p)
+    float2* p2_32 = nullptr; // the same for FP32 Krylov vectors
     double2 *xi = nullptr, *phi = nullptr;
     // FP32 Krylov workspace (precision form)
     float2 *r32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *w32 = nullptr;

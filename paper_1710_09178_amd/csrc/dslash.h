@@ -41,17 +41,24 @@ void launch_dslash_cg(const Geom& g, const LinkSet& ls, const double2* w_o, cons
 void launch_dslash_resid(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* x, const double2* b,
                          double c, double* part, int tps, hipStream_t s, float2* r32_out = nullptr);
 
-struct FusedIter;
+template <class V>
+struct FusedIterT;
 // Iteration j of the fused multi-shift CG: step j-1's scalars and base update
 // folded into w = D_oe p_j (first: j = 0, D_oe p_0 and |r_0|^2 partials only);
-// always 4 threads per site, grid dslash_fused_grid(g) = dslash_grid(g, 4)
+// always 4 threads per site, grid dslash_fused_grid(g) = dslash_grid(g, 4).
+// double2: the FP64 operator (format fmt64); float2: FP32 Krylov vectors
+// with the FP32 operator (format fmt32).
 int dslash_fused_grid(const Geom& g);
-void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIter& f, double2* w_out, bool first,
+void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIterT<double2>& f, double2* w_out, bool first,
+                         hipStream_t s);
+void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIterT<float2>& f, float2* w_out, bool first,
                          hipStream_t s);
 // the D_eo launch of the fused loop: launch_dslash_cg with 4 threads per site
 // and the operands' loads issued before the stop flag is tested
 void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
                             double2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term);
+void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* p, const float2* r,
+                            float2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term);
 
 // FP32 operator (format fmt32)
 void launch_dslash32(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int out_par, int tps,

@@ -378,17 +378,18 @@ __global__ __launch_bounds__(kBlock) void k_dslash(Geom g, Link L, const typenam
 }
 
 // p_j = (r_{j-1} - alpha Ap_{j-1}) + beta p_{j-1}, formed where it is read
+template <class V>
 struct InUpd {
-    const double2* __restrict__ r;
-    const double2* __restrict__ a;
-    const double2* __restrict__ p;
+    const V* __restrict__ r;
+    const V* __restrict__ a;
+    const V* __restrict__ p;
     double alpha, beta;
-    __device__ __forceinline__ double2 operator[](size_t i) const {
+    __device__ __forceinline__ V operator[](size_t i) const {
         return cg_p_next(cg_r_next(r[i], a[i], alpha), p[i], beta);
     }
 };
 
-// Iteration j of the fused multi-shift CG (FP64): w = D_oe p_j for the odd
+// Iteration j of the fused multi-shift CG: w = D_oe p_j for the odd
 // sites of this block's tile, after
 //   * summing the partials of |r_{j-1}|^2 and of the three D_eo(j-1) dots in
 //     block order (every block, bitwise alike) and evaluating step j-1's
@@ -417,8 +418,13 @@ struct is_naik_op<NaikOp<Link>> {
 };
 
 template <class Link, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIter f, double2* __restrict__ w_out) {
-    using C = double2;
+__global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIterT<typename Link::C> f,
+                                                         typename Link::C* __restrict__ w_out) {
+    // C: the Krylov vectors' precision, that of the operator's format (FP64
+    // links with FP64 vectors, FP32 or FP16 links with FP32 vectors); the
+    // scalars, the update arithmetic, x_base and the partial sums are FP64
+    using C = typename Link::C;
+    using R = typename Link::R;
     constexpr int TPS = 4, SB = kBlock / TPS;
     MsState* st = f.st;
     // the stop flag is tested once this launch's other loads are in flight
@@ -426,7 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
     const int stopped = FIRST ? 0 : st->done[f.par];
     __shared__ C part[TPS * 3 * SB];
     __shared__ double lds[16];
-    const double2* r_prev = f.ring + (size_t)f.slot_prev * 3 * g.vh;
+    const C* r_prev = f.ring + (size_t)f.slot_prev * 3 * g.vh;
     const int lane = threadIdx.x & 63, mu = threadIdx.x >> 6;
     const int tile = xcd_tile_slab(blockIdx.x, gridDim.x, g, SB);
     const int cb = tile * SB + lane;
@@ -446,7 +452,8 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
     for (int c = 0; c < 3; ++c) acc[c] = C{0, 0};
     double alpha = 0.0, beta = 0.0;
     int base_on = 0;
-    double2 o_r = {0, 0}, o_a = {0, 0}, o_p = {0, 0}, o_x = {0, 0};
+    C o_r = {0, 0}, o_a = {0, 0}, o_p = {0, 0};
+    double2 o_x = {0, 0};
     if (FIRST) {
         if (site_ok) hop(g, L, f.p_prev, 1, mu, cb, x, y, z, t, acc);
         if (own) o_r = r_prev[oi];
@@ -518,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
         base_on = so.base_on;
         if (site_ok) {
             if constexpr (is_naik_op<Link>::value) {
-                const InUpd in{r_prev, f.Ap, f.p_prev, alpha, beta};
+                const InUpd<C> in{r_prev, f.Ap, f.p_prev, alpha, beta};
                 hop(g, L, in, 1, mu, cb, x, y, z, t, acc);
             } else {
                 C pf[3], pb[3];
@@ -527,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
                     pf[c] = cg_p_next(cg_r_next(fr[c], fa[c], alpha), fp[c], beta);
                     pb[c] = cg_p_next(cg_r_next(br[c], ba[c], alpha), bp[c], beta);
                 }
-                const double sf = nf ? -1.0 : 1.0, sb = nb ? -1.0 : 1.0;
+                const R sf = nf ? R(-1) : R(1), sb = nb ? R(-1) : R(1);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     C fv = cmul(U[3 * a], pf[0]);
@@ -553,12 +560,14 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
         for (int sl = 1; sl < TPS; ++sl) v = cadd(v, part[(sl * 3 + oc) * SB + jj]);
         w_out[oi] = v;
         if (FIRST) {
-            racc[0] = o_r.x * o_r.x + o_r.y * o_r.y;
+            const double2 rd = to_d2(o_r);
+            racc[0] = rd.x * rd.x + rd.y * rd.y;
         } else {
-            const double2 rn = cg_r_next(o_r, o_a, alpha);
+            const C rn = cg_r_next(o_r, o_a, alpha);
             f.ring[(size_t)f.slot_new * 3 * g.vh + oi] = rn;
-            racc[0] = rn.x * rn.x + rn.y * rn.y;
-            if (base_on) f.x_base[oi] = make_double2(fma(alpha, o_p.x, o_x.x), fma(alpha, o_p.y, o_x.y));
+            const double2 rd = to_d2(rn), pd = to_d2(o_p);
+            racc[0] = rd.x * rd.x + rd.y * rd.y;
+            if (base_on) f.x_base[oi] = make_double2(fma(alpha, pd.x, o_x.x), fma(alpha, pd.y, o_x.y));
             f.p_new[oi] = cg_p_next(rn, o_p, beta);
         }
     }
@@ -570,12 +579,14 @@ __global__ __launch_bounds__(kBlock) void k_dslash_fused(Geom g, Link L, FusedIt
 // threads per site and every load -- links, the neighbours' w, the owned
 // site's p and r -- issued before the stop flag is tested.
 template <class Link>
-__global__ __launch_bounds__(kBlock) void k_dslash_cg_fused(Geom g, Link L, const double2* __restrict__ w,
-                                                            const double2* __restrict__ p,
-                                                            const double2* __restrict__ r, double2* __restrict__ Ap,
+__global__ __launch_bounds__(kBlock) void k_dslash_cg_fused(Geom g, Link L, const typename Link::C* __restrict__ w,
+                                                            const typename Link::C* __restrict__ p,
+                                                            const typename Link::C* __restrict__ r,
+                                                            typename Link::C* __restrict__ Ap,
                                                             double* __restrict__ part, double mt,
                                                             const int* __restrict__ gate) {
-    using C = double2;
+    using C = typename Link::C;
+    using R = typename Link::R;
     constexpr int TPS = 4, SB = kBlock / TPS;
     const int stopped = *gate;
     __shared__ C lpart[TPS * 3 * SB];
@@ -592,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_cg_fused(Geom g, Link L, cons
     const int oc = threadIdx.x / SB, osite = tile * SB + (threadIdx.x % SB);
     const bool own = threadIdx.x < 3 * SB && osite < g.vh;
     const size_t oi = (size_t)oc * g.vh + osite;
-    double2 o_p = {0, 0}, o_r = {0, 0};
+    C o_p = {0, 0}, o_r = {0, 0};
     if (own) {
         o_p = p[oi];
         o_r = r[oi];
@@ -616,7 +627,7 @@ __global__ __launch_bounds__(kBlock) void k_dslash_cg_fused(Geom g, Link L, cons
         }
         if (stopped) return;
         if (site_ok) {
-            const double sf = nf ? -1.0 : 1.0, sb = nb ? -1.0 : 1.0;
+            const R sf = nf ? R(-1) : R(1), sb = nb ? R(-1) : R(1);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 C fv = cmul(U[3 * a], pf[0]);
@@ -639,11 +650,14 @@ __global__ __launch_bounds__(kBlock) void k_dslash_cg_fused(Geom g, Link L, cons
         C v = lpart[oc * SB + jj];
 #pragma unroll
         for (int sl = 1; sl < TPS; ++sl) v = cadd(v, lpart[(sl * 3 + oc) * SB + jj]);
-        const C a = C{mt * o_p.x - v.x, mt * o_p.y - v.y};
+        // (the arithmetic of the EpiCG epilogue, in the vectors' precision)
+        const R m = (R)mt;
+        const C a = C{m * o_p.x - v.x, m * o_p.y - v.y};
         Ap[oi] = a;
-        dots[0] = o_p.x * a.x + o_p.y * a.y;
-        dots[1] = o_r.x * a.x + o_r.y * a.y;
-        dots[2] = a.x * a.x + a.y * a.y;
+        const double2 pd = to_d2(o_p), rd = to_d2(o_r), ad = to_d2(a);
+        dots[0] = pd.x * ad.x + pd.y * ad.y;
+        dots[1] = rd.x * ad.x + rd.y * ad.y;
+        dots[2] = ad.x * ad.x + ad.y * ad.y;
     }
     block_partial<3>(dots, part);
 }
@@ -703,28 +717,57 @@ int dslash_grid(const Geom& g, int tps) {
     return (g.vh + sb - 1) / sb;
 }
 
-// ---- fused multi-shift iteration (FP64), 4 threads per site
+// ---- fused multi-shift iteration, 4 threads per site: FP64 (format fmt64)
+// or FP32 Krylov vectors (format fmt32)
 int dslash_fused_grid(const Geom& g) { return dslash_grid(g, 4); }
 
-void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
-                            double2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term) {
+namespace {
+template <class V, class Disp>
+void cg_fused_any(const Geom& g, const LinkSet& ls, Disp disp, const V* w_o, const V* p, const V* r, V* Ap,
+                  const int* gate, double* dpart, hipStream_t s, double mass_term) {
     const int grid = dslash_fused_grid(g);
-    with_link64(ls, [&](auto L) {
+    disp(ls, [&](auto L) {
         timed_launch(k_dslash_cg_fused<decltype(L)>, dim3(grid), dim3(kBlock), s, g, L, w_o, p, r, Ap, dpart,
                      mass_term, gate);
     });
 }
-
-void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIter& f, double2* w_out, bool first,
-                         hipStream_t s) {
+template <class V, class Disp>
+void fused_any(const Geom& g, const LinkSet& ls, Disp disp, const FusedIterT<V>& f, V* w_out, bool first,
+               hipStream_t s) {
     const int grid = dslash_fused_grid(g);
-    with_link64(ls, [&](auto L) {
+    disp(ls, [&](auto L) {
         using LT = decltype(L);
         if (first)
             k_dslash_fused<LT, true><<<grid, kBlock, 0, s>>>(g, L, f, w_out);
         else
             timed_launch(k_dslash_fused<LT, false>, dim3(grid), dim3(kBlock), s, g, L, f, w_out);
     });
+}
+struct Disp64 {
+    template <class Fn>
+    void operator()(const LinkSet& ls, Fn fn) const { with_link64(ls, fn); }
+};
+struct Disp32 {
+    template <class Fn>
+    void operator()(const LinkSet& ls, Fn fn) const { with_link32(ls, fn); }
+};
+}  // namespace
+
+void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const double2* w_o, const double2* p, const double2* r,
+                            double2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term) {
+    cg_fused_any(g, ls, Disp64{}, w_o, p, r, Ap, gate, dpart, s, mass_term);
+}
+void launch_dslash_cg_fused(const Geom& g, const LinkSet& ls, const float2* w_o, const float2* p, const float2* r,
+                            float2* Ap, const int* gate, double* dpart, hipStream_t s, double mass_term) {
+    cg_fused_any(g, ls, Disp32{}, w_o, p, r, Ap, gate, dpart, s, mass_term);
+}
+void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIterT<double2>& f, double2* w_out, bool first,
+                         hipStream_t s) {
+    fused_any(g, ls, Disp64{}, f, w_out, first, s);
+}
+void launch_dslash_fused(const Geom& g, const LinkSet& ls, const FusedIterT<float2>& f, float2* w_out, bool first,
+                         hipStream_t s) {
+    fused_any(g, ls, Disp32{}, f, w_out, first, s);
 }
 
 // ---- FP64 operator

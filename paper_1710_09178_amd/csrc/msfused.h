@@ -20,13 +20,24 @@ __device__ __forceinline__ double2 cg_r_next(double2 r, double2 a, double alpha)
 __device__ __forceinline__ double2 cg_p_next(double2 rn, double2 p, double beta) {
     return make_double2(fma(beta, p.x, rn.x), fma(beta, p.y, rn.y));
 }
+// FP32 Krylov vectors: the same FP64 fused multiply-adds, rounded to FP32
+// where the value is stored (and, identically, where a neighbour forms it)
+__device__ __forceinline__ float2 cg_r_next(float2 r, float2 a, double alpha) {
+    return make_float2((float)fma(-alpha, (double)a.x, (double)r.x), (float)fma(-alpha, (double)a.y, (double)r.y));
+}
+__device__ __forceinline__ float2 cg_p_next(float2 rn, float2 p, double beta) {
+    return make_float2((float)fma(beta, (double)p.x, (double)rn.x), (float)fma(beta, (double)p.y, (double)rn.y));
+}
 
-// Launch constants of iteration j >= 1 of the fused loop.
-struct FusedIter {
-    double2* ring;          // residual ring: r_i in slot i % lag
-    const double2* Ap;      // Ap_{j-1}
-    const double2* p_prev;  // p_{j-1}
-    double2* p_new;         // p_j (owned even sites)
+// Launch constants of iteration j >= 1 of the fused loop; V: the Krylov
+// vectors' precision (double2, or float2 for the FP32 form; the solutions
+// stay FP64).
+template <class V>
+struct FusedIterT {
+    V* ring;                // residual ring: r_i in slot i % lag
+    const V* Ap;            // Ap_{j-1}
+    const V* p_prev;        // p_{j-1}
+    V* p_new;               // p_j (owned even sites)
     double2* x_base;        // solution of the base system
     MsState* st;
     const double* dpart;    // <p,Ap>, <r,Ap>, <Ap,Ap> partials of D_eo(j-1), nb2 each
@@ -37,6 +48,7 @@ struct FusedIter {
     int n, base, lag;
     int slot_prev, slot_new;   // (j - 1) % lag, j % lag
 };
+using FusedIter = FusedIterT<double2>;
 
 // Scalars of step i = j - 1 from the block totals (rr = |r_i|^2 and the three
 // dots of D_eo(i)), evaluated by wave 0, one lane per shift, with the same
@@ -56,7 +68,8 @@ struct LaneState {
     int active, ipp, iter, bb_given, maxiter;
 };
 
-__device__ __forceinline__ LaneState load_lane_state(const FusedIter& f) {
+template <class FI>
+__device__ __forceinline__ LaneState load_lane_state(const FI& f) {
     LaneState l{};
     const MsState* st = f.st;
     const MsIter& s = st->it[f.par ^ 1];
@@ -80,7 +93,8 @@ __device__ __forceinline__ LaneState load_lane_state(const FusedIter& f) {
     return l;
 }
 
-__device__ __forceinline__ StepOut fused_step_scalars(const FusedIter& f, const double (&v)[4], const LaneState& ls) {
+template <class FI>
+__device__ __forceinline__ StepOut fused_step_scalars(const FI& f, const double (&v)[4], const LaneState& ls) {
     __shared__ double sh_alpha, sh_beta;
     __shared__ int sh_stop, sh_base_on;
     MsState* st = f.st;

@@ -143,8 +143,8 @@ struct Krylov;
 
 template <>
 struct Krylov<double2> {
-    double2 *r, *p, *Ap, *w;
-    explicit Krylov(stag_ctx* c) : r(c->r), p(c->p), Ap(c->Ap), w(c->w_o) {}
+    double2 *r, *p, *Ap, *w, *p2;
+    explicit Krylov(stag_ctx* c) : r(c->r), p(c->p), Ap(c->Ap), w(c->w_o), p2(c->p2) {}
     static void doe(const Geom& g, const LinkSet& ls, const double2* in, double2* out, int tps, const int* gate,
                     hipStream_t s) {
         launch_dslash(g, ls, in, out, 1, tps, gate, s);
@@ -157,8 +157,8 @@ struct Krylov<double2> {
 
 template <>
 struct Krylov<float2> {
-    float2 *r, *p, *Ap, *w;
-    explicit Krylov(stag_ctx* c) : r(c->r32), p(c->p32), Ap(c->Ap32), w(c->w32) {}
+    float2 *r, *p, *Ap, *w, *p2;
+    explicit Krylov(stag_ctx* c) : r(c->r32), p(c->p32), Ap(c->Ap32), w(c->w32), p2(c->p2_32) {}
     static void doe(const Geom& g, const LinkSet& ls, const float2* in, float2* out, int tps, const int* gate,
                     hipStream_t s) {
         launch_dslash32(g, ls, in, out, 1, tps, gate, s);
@@ -355,22 +355,24 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
 // has stopped a final flush for the steps of its last, partial window.
 constexpr int kFusedMaxBlocks = 512;
 
-stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int chunk, EvRec& rec) {
+template <class V>
+stag_status run_fused(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtrs X, VecPtrs P, int chunk,
+                      EvRec& rec) {
     const Geom& g = c->g;
     const double mt = c->st_host->mass_term;
     const int n = c->st_host->n, base = c->st_host->base;
     const int L = c->st_host->lag;
     const int nb2 = dslash_fused_grid(g);   // both Dslash launches: 4 threads per site
     const size_t n3 = (size_t)3 * g.vh;
-    double2* pbuf[2] = {c->p, c->p2};
+    V* pbuf[2] = {K.p, K.p2};
     const int nsh = n - 1;
     const int rows = nsh > 0 ? std::max(1, std::min((nsh + kFlushGroup - 1) / kFlushGroup, 512 / ms_update_grid(g)))
                              : 1;
     auto iter_args = [&](int j) {
         const int par = j & 1;
-        FusedIter f{};
-        f.ring = c->r;
-        f.Ap = c->Ap;
+        FusedIterT<V> f{};
+        f.ring = K.r;
+        f.Ap = K.Ap;
         f.p_prev = pbuf[par ^ 1];
         f.p_new = pbuf[par];
         f.x_base = X.at<double2>(base);
@@ -390,28 +392,28 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int 
     // iteration 0: w = D_oe p_0 (p_0 = r_0 = b, both written by the init
     // kernel), |r_0|^2 partials in the D_oe grid's layout into qpart[0]
     {
-        FusedIter f0 = iter_args(0);
+        FusedIterT<V> f0 = iter_args(0);
         f0.p_prev = pbuf[0];
         f0.slot_prev = 0;
-        launch_dslash_fused(g, ls, f0, c->w_o, true, c->s);
-        launch_dslash_cg_fused(g, ls, c->w_o, pbuf[0], c->r, c->Ap, &c->st->done[1], c->dpart, c->s, mt);
+        launch_dslash_fused(g, ls, f0, K.w, true, c->s);
+        launch_dslash_cg_fused(g, ls, K.w, pbuf[0], K.r, K.Ap, &c->st->done[1], c->dpart, c->s, mt);
     }
     int it_issued = 1;
     auto enqueue_chunk = [&]() {
         for (int it = 0; it < chunk; ++it, ++it_issued) {
             const int j = it_issued, par = j & 1;
-            const FusedIter f = iter_args(j);
+            const FusedIterT<V> f = iter_args(j);
             hipEvent_t a;
             prof_begin(c, &a);
-            launch_dslash_fused(g, ls, f, c->w_o, false, c->s);
+            launch_dslash_fused(g, ls, f, K.w, false, c->s);
             prof_end(c, a, 0, rec);
             prof_begin(c, &a);
-            launch_dslash_cg_fused(g, ls, c->w_o, pbuf[par], c->r + (size_t)(j % L) * n3, c->Ap,
+            launch_dslash_cg_fused(g, ls, K.w, pbuf[par], K.r + (size_t)(j % L) * n3, K.Ap,
                                    &c->st->done[par ^ 1], c->dpart, c->s, mt);
             prof_end(c, a, 1, rec);
             if (j % L == 0 && nsh > 0) {
                 prof_begin(c, &a);
-                launch_ms_flush(g, c->r, X, P, c->st, &c->st->done[par ^ 1], n, base, L, false, rows, c->s);
+                launch_ms_flush(g, (const V*)K.r, X, P, c->st, &c->st->done[par ^ 1], n, base, L, false, rows, c->s);
                 prof_end(c, a, 2, rec);
             }
         }
@@ -422,10 +424,10 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int 
         std::memset(&key, 0, sizeof(key));
         key.g = g;
         key.ls = ls;
-        key.vec[0] = c->r;
+        key.vec[0] = K.r;
         key.vec[1] = pbuf[0];
-        key.vec[2] = c->Ap;
-        key.vec[3] = c->w_o;
+        key.vec[2] = K.Ap;
+        key.vec[3] = K.w;
         key.vec[4] = pbuf[1];
         key.X = X;
         key.P = P;
@@ -440,7 +442,7 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int 
         key.base = base;
         key.chunk = chunk;
         key.nb2 = nb2;
-        key.v64 = 1;
+        key.v64 = sizeof(V) == sizeof(double2);
         key.fused = 1;
         key.rows = rows;
         exec = cached_graph(c, key);
@@ -476,7 +478,7 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, VecPtrs X, VecPtrs P, int 
         issue_chunk(cur);
         cur ^= 1;
     }
-    if (nsh > 0) launch_ms_flush(g, c->r, X, P, c->st, nullptr, n, base, L, true, rows, c->s);
+    if (nsh > 0) launch_ms_flush(g, (const V*)K.r, X, P, c->st, nullptr, n, base, L, true, rows, c->s);
     HIP_OR_FAIL(c, hipGetLastError());
     return STAG_OK;
 }
@@ -496,7 +498,7 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
     // the fused loop (FP64, window >= 2; it keeps r_{j-1} and r_j in the ring
     // at once): by default on grids of at most kFusedMaxBlocks Dslash blocks,
     // where an iteration is latency-bound; with on = 2 at every size
-    const bool fused = sizeof(V) == sizeof(double2) && c->lag >= 2 &&
+    const bool fused = c->lag >= 2 &&
                        (c->fused == 2 || (c->fused == 1 && dslash_fused_grid(g) <= kFusedMaxBlocks));
     h->lag = fused ? c->lag : (n > 1 ? c->lag : 1);
     HIP_OR_FAIL(c, hipMemcpyAsync(c->st, h, sizeof(MsState), hipMemcpyHostToDevice, c->s));
@@ -509,7 +511,7 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
     launch_ms_init<V>(g, b, K.r, K.p, X, P, c->st, c->qpart[0], c->s);
     res.fused = fused;
     if (fused)
-        e = run_fused(c, ls, X, P, c->chunk, rec);
+        e = run_fused<V>(c, ls, K, X, P, c->chunk, rec);
     else
         e = run_iterations<V>(c, ls, K, X, P, c->chunk, rec, [](int) {});
     if (e) return e;
@@ -622,7 +624,8 @@ stag_status ensure_fp32_workspace(stag_ctx* c) {
     stag_status e;
     if (!c->r32) {
         if ((e = dmalloc(c, &c->r32, kLagMax * half_bytes(g) / 2)) || (e = dmalloc(c, &c->p32, half_bytes(g) / 2)) ||
-            (e = dmalloc(c, &c->Ap32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->w32, half_bytes(g) / 2)))
+            (e = dmalloc(c, &c->p2_32, half_bytes(g) / 2)) || (e = dmalloc(c, &c->Ap32, half_bytes(g) / 2)) ||
+            (e = dmalloc(c, &c->w32, half_bytes(g) / 2)))
             return e;
     }
     return STAG_OK;
@@ -654,7 +657,7 @@ stag_status ms_solve_mixed(stag_ctx* c, double mass, const stag_rational* r, dou
     // phase 1: FP32 multi-shift to tol_sloppy
     if ((e = ms_solve_t<float2>(c, ls, mass, r, std::max(opts->tol_sloppy, tol), maxiter, b, x, ipp, r1, rec)))
         return e;
-    prof_collect(c, rec, r1.iters);
+    prof_collect(c, rec, r1.iters, r1.fused, c->st_host->lag);
     if (r1.nonfinite) {
         res = r1;
         return STAG_OK;

@@ -167,7 +167,7 @@ def test_error_paths():
     assert e.value.code == STAG_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("mixed,fused", [(False, False), (True, False), (False, True)])
+@pytest.mark.parametrize("mixed,fused", [(False, False), (True, False), (False, True), (True, True)])
 def test_shift_window_does_not_change_results(mixed, fused):
     """Deferring the shifted updates over windows of 1..8 iterations keeps the
     arithmetic and its order: every solution is bitwise the same, including
@@ -277,6 +277,38 @@ def test_fused_iteration_matches_three_launch_loop(dims):
         assert np.linalg.norm(x - y) <= 1e-9 * np.linalg.norm(y)
     res = true_residuals(lambda v: dirac.apply_A(U, v, dims, 0.02), b, rat["pole"], xs)
     assert res.max() < 1e-10, res
+
+
+@pytest.mark.parametrize("sloppy", [2, 3])
+def test_fp32_fused_loop_matches_three_launch_loop(sloppy):
+    """The FP32 multi-shift (FP32-18 or FP16-12 links) in the fused loop and
+    in the three-launch loop, each followed by the FP64 refinement: every
+    pole's true residual (oracle operator) below tol in both, and the
+    solutions within 2 tol kappa_k of each other."""
+    dims = (8, 6, 4, 10)
+    mass, tol = 0.05, 1e-10
+    log(f"FP32 fused vs three-launch multi-shift, link format {sloppy}")
+    rng = synth.make_rng(0, 15)
+    U = synth.random_su3_near_identity(dims, 0.4, rng)
+    b = synth.gaussian_half_vector(dims, rng)
+    lat = lattice(dims, U)
+    bd = lat.vec_import(dev(b), 0)
+    rat = _rat(C0_POLES)
+    got = {}
+    for fused in (True, False):
+        lat.set_fused_iteration(fused)
+        xs = [lat.new_vec() for _ in rat["pole"]]
+        info = lat.multishift_solve_mixed(mass, rat, tol, 100000, bd, xs, None, sloppy=sloppy)
+        assert max(info["true_resid"]) < tol
+        got[fused] = [host(lat.vec_export(x, 0)) for x in xs]
+        log(f"  fused={fused}: {info['iters']} iterations")
+    A = lambda v: dirac.apply_A(U, v, dims, mass)  # noqa: E731
+    res = true_residuals(A, b, rat["pole"], got[True])
+    assert max(res) < tol, res
+    lam_max = 4 * mass * mass + 64
+    for xf, xu, sh in zip(got[True], got[False], rat["pole"]):
+        kappa = (lam_max + sh) / (4 * mass * mass + sh)
+        assert np.linalg.norm(xf - xu) <= 2 * tol * kappa * np.linalg.norm(xu)
 
 
 @pytest.mark.parametrize("maxiter", [1, 5, 8, 9, 13])
