@@ -488,7 +488,8 @@ stag_status stag_profile_read(stag_handle h, double ms[3], long counts[3]);
  * first min(cap, *n_out) go to us_out (host array).  STAG_ERR_INVALID_ARG for
  * a kind outside [0, 2], cap < 0, n_out NULL, or us_out NULL with cap > 0. */
 stag_status stag_profile_samples(stag_handle h, int kind, float* us_out, int cap, int* n_out);
-/* The fused iteration of FP64 multi-shift solves (shift-update window >= 2):
+/* The fused iteration of multi-shift solves (shift-update window >= 2; FP64,
+ * and the FP32 phase of the precision form and of FP32 MD force solves):
  * the base system's update of step j-1 is folded into the D_oe launch of
  * iteration j, which forms p_j = (r_{j-1} - alpha Ap_{j-1}) + beta p_{j-1}
  * where it reads it, and the shifted systems are updated by one flush launch
