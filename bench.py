@@ -858,7 +858,8 @@ def batch_bytes(dims, nrhs, iters_per_pole, base, lag):
 def batched_form(per_class=16, nrhs=4, reps=2):
     """64 lattices (16 each of 8^4, 12^3x6, 16^3x8, 24^3x6) x 4 right-hand sides
     x the 12 poles of the x^(-1/4) table, masses uniform in [0.005, 0.05], in
-    one batched multi-shift solve; FP64 and mixed FP32/FP64."""
+    one batched multi-shift solve; FP64, mixed FP32/FP64, and FP64 reading 12
+    reals per link; the same systems solved one after another."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -908,6 +909,22 @@ def batched_form(per_class=16, nrhs=4, reps=2):
         out[name] = row
         del x
     out["mixed_speedup_vs_fp64"] = round(out["fp64"]["ms_per_solve"] / out["mixed_fp32_fp64"]["ms_per_solve"], 3)
+    # FP64 reading 12 reals per link (rows 0-1, row 2 rebuilt), same work split
+    from paper_1710_09178_amd import stag
+    B.set_link_format(stag.LINKS_F64_12)
+    B.solve(masses, rat, b, precision=0, true_resid=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, info = B.solve(masses, rat, b, precision=0, true_resid=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    x, chk = B.solve(masses, rat, b, precision=0, true_resid=True)
+    out["fp64_links12"] = {"ms_per_solve": round(dt * 1e3, 3), "iterations": info["iters"],
+                           "true_resid_max": float(chk["true_resid"].max()),
+                           "speedup_vs_links18": round(out["fp64"]["ms_per_solve"] / (dt * 1e3), 3)}
+    del x
+    B.set_link_format(stag.LINKS_F64_18)
     # the same 256 systems one after another, one single-lattice handle per
     # lattice (FP64, library defaults), for the batched form's speedup
     from paper_1710_09178_amd.stag import Lattice
@@ -939,6 +956,17 @@ def batched_form(per_class=16, nrhs=4, reps=2):
     seq_ms = (time.perf_counter() - t0) * 1e3
     out["sequential_fp64"] = {"ms_for_all_systems": round(seq_ms, 3), "iterations_total": seq_iters,
                               "batched_speedup": round(seq_ms / out["fp64"]["ms_per_solve"], 3)}
+    # the same with 12-real links on both sides
+    for lat in lats:
+        lat.set_link_format(stag.LINKS_F64_12)
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sequential()
+    torch.cuda.synchronize()
+    seq12 = (time.perf_counter() - t0) * 1e3
+    out["sequential_fp64_links12"] = {"ms_for_all_systems": round(seq12, 3),
+                                      "batched_speedup": round(seq12 / out["fp64_links12"]["ms_per_solve"], 3)}
     del lats, vecs, xs
     torch.cuda.empty_cache()
     return out

@@ -466,6 +466,13 @@ stag_status stag_batch_tune(stag_batch_handle b, int precision, double* us_out);
  * Results of the solver do not depend on the choice. */
 stag_status stag_batch_autotune(stag_batch_handle b, int precision, const char* cache_path, double* us_out,
                                 int* choice_out);
+/* Link format of the batched operators: STAG_LINKS_F64_18 (default) reads
+ * all 18 reals of a link; STAG_LINKS_F64_12 reads rows 0 and 1 (12 reals) and
+ * rebuilds row 2 = conj(row 0 x row 1), exact to rounding for SU(3) links
+ * (the FP32 operator of the mixed precision then does the same with its FP32
+ * copy).  The stored links are unchanged; the key of stag_batch_autotune's
+ * cache includes the format.  STAG_ERR_INVALID_ARG for any other format. */
+stag_status stag_batch_set_link_format(stag_batch_handle b, int format);
 /* Set the Dslash work split directly: 1, 2 or 4 threads per site share the
  * four directions of a site through LDS; 8 lanes per site take one hop each
  * and combine by lane exchanges.  Results agree to rounding.  Tuning. */

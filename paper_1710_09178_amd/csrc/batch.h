@@ -71,6 +71,7 @@ struct BatchDev {
     int tile_sites;
     int nrhs;
     int link_nt;   // links streamed with non-temporal loads (fields beyond the Infinity Cache)
+    int link12;    // read rows 0-1 of every link and rebuild row 2 = conj(row 0 x row 1)
 };
 
 // Launchers (batch.hip).  V = double2 (FP64 links, FP64 Krylov vectors) or

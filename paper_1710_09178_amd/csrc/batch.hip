@@ -44,6 +44,16 @@ __device__ __forceinline__ float2 bload(const float2* p) {
     }
 }
 
+// An SU(3) matrix's row 2 from rows 0 and 1: conj(row 0 x row 1).  With it
+// the operators read 12 of a link's 18 reals (rows 0-1; the storage keeps
+// all 9 entries as separate planes, so row 2's planes are simply not read).
+template <class V>
+__device__ __forceinline__ void brebuild_row2(V (&m)[9]) {
+    m[6] = cconj(csub(cmul(m[1], m[5]), cmul(m[2], m[4])));
+    m[7] = cconj(csub(cmul(m[2], m[3]), cmul(m[0], m[5])));
+    m[8] = cconj(csub(cmul(m[0], m[4]), cmul(m[1], m[3])));
+}
+
 __device__ __forceinline__ void bhop_geometry(const Geom& g, int mu, int x, int y, int z, int t, int& cbf, int& cbb,
                                               bool& nf, bool& nb) {
     if (mu == 0) {
@@ -150,7 +160,7 @@ struct BEpiResid {
 
 // One block per tile: TPS threads per site split the 4 directions; every
 // thread applies its links to all right-hand sides of the lattice.
-template <int TPS, class V, class Epi, bool NT>
+template <int TPS, class V, class Epi, bool NT, bool L12>
 __global__ __launch_bounds__(kBlock) void k_bdslash(BatchDev bd, const V* __restrict__ links, const V* __restrict__ in,
                                                     int out_par, Epi epi, const int* __restrict__ inst_done) {
     constexpr int SB = kBlock / TPS;
@@ -184,10 +194,15 @@ __global__ __launch_bounds__(kBlock) void k_bdslash(BatchDev bd, const V* __rest
             V U[9], W[9];
             const V* uf = lk + link_off(g, out_par, mu, 0) + cb;
             const V* ub = lk + link_off(g, 1 - out_par, mu, 0) + cbb;
+            constexpr int NE = L12 ? 6 : 9;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) U[e] = bload<NT>(uf + (size_t)e * g.vh);
+            for (int e = 0; e < NE; ++e) U[e] = bload<NT>(uf + (size_t)e * g.vh);
 #pragma unroll
-            for (int e = 0; e < 9; ++e) W[e] = bload<NT>(ub + (size_t)e * g.vh);
+            for (int e = 0; e < NE; ++e) W[e] = bload<NT>(ub + (size_t)e * g.vh);
+            if constexpr (L12) {
+                brebuild_row2(U);
+                brebuild_row2(W);
+            }
             const Rl sf = nf ? Rl(-1) : Rl(1);
             const Rl sb = nb ? Rl(-1) : Rl(1);
 #pragma unroll
@@ -267,11 +282,19 @@ __global__ __launch_bounds__(kBlock) void k_bdslash8(BatchDev bd, const V* __res
         const V* lk = links + blink_base(I);
         const V* u = bwd ? lk + link_off(g, 1 - out_par, mu, 0) + cbb : lk + link_off(g, out_par, mu, 0) + cb;
         const Rl cj = bwd ? Rl(-1) : Rl(1);
+        V M[9];
+        if (bd.link12) {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) M[e] = u[(size_t)e * g.vh];
+            brebuild_row2(M);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) M[e] = u[(size_t)e * g.vh];
+        }
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
             const int src = bwd ? 3 * (e % 3) + e / 3 : e;
-            const V v = u[(size_t)src * g.vh];
-            U[e] = V{v.x, cj * v.y};
+            U[e] = V{M[src].x, cj * M[src].y};
         }
         nbr = bwd ? cbb : cbf;
         sg = bwd ? (nb ? Rl(1) : Rl(-1)) : (nf ? Rl(-1) : Rl(1));
@@ -318,18 +341,31 @@ void bdslash_tps(const BatchDev& bd, int tps, const V* links, const V* in, int o
         k_bdslash8<V, Epi><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done);
         return;
     }
-    auto go = [&](auto nt) {
-        constexpr bool NT = decltype(nt)::value;
+    auto go = [&](auto nt, auto l12) {
+        constexpr bool NT = decltype(nt)::value, L12 = decltype(l12)::value;
         switch (tps) {
-            case 1: k_bdslash<1, V, Epi, NT><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
-            case 2: k_bdslash<2, V, Epi, NT><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
-            default: k_bdslash<4, V, Epi, NT><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done); break;
+            case 1:
+                k_bdslash<1, V, Epi, NT, L12><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done);
+                break;
+            case 2:
+                k_bdslash<2, V, Epi, NT, L12><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done);
+                break;
+            default:
+                k_bdslash<4, V, Epi, NT, L12><<<bd.ntiles, kBlock, 0, s>>>(bd, links, in, out_par, epi, inst_done);
+                break;
         }
     };
-    if (bd.link_nt)
-        go(std::true_type{});
-    else
-        go(std::false_type{});
+    if (bd.link_nt) {
+        if (bd.link12)
+            go(std::true_type{}, std::true_type{});
+        else
+            go(std::true_type{}, std::false_type{});
+    } else {
+        if (bd.link12)
+            go(std::false_type{}, std::true_type{});
+        else
+            go(std::false_type{}, std::false_type{});
+    }
 }
 
 // r = p = p_k = b, x_k = 0, per-rhs partials of |b|^2

@@ -33,6 +33,7 @@ struct stag_batch {
     BTile* tiles_d = nullptr;
     int tps = 2;
     int link_nt = -1;            // links loaded non-temporally: -1 by field size, 0 no, 1 yes (tuned)
+    int link12 = 0;              // operators read 12 reals per link (rows 0-1, row 2 rebuilt)
     int lag = 8;                 // shift-update window (divides the 16-iteration chunk)
     int tiles_cap = 0;
     size_t total_vh = 0;
@@ -125,9 +126,9 @@ BatchDev bdev(const stag_batch* c) {
     // the links of all lattices are streamed from HBM by every operator
     // application once they exceed what the Infinity Cache keeps (FP64:
     // 1.2 GB for the 64-lattice batch; the single-lattice operator's rule)
-    const size_t link_bytes = (size_t)72 * c->total_vh * 16;
+    const size_t link_bytes = (size_t)(c->link12 ? 48 : 72) * c->total_vh * 16;
     const int nt = c->link_nt >= 0 ? c->link_nt : (link_bytes > ((size_t)512 << 20) ? 1 : 0);
-    return BatchDev{c->inst_d, c->tiles_d, (int)c->tiles_h.size(), kBlock / c->tps, c->nrhs, nt};
+    return BatchDev{c->inst_d, c->tiles_d, (int)c->tiles_h.size(), kBlock / c->tps, c->nrhs, nt, c->link12};
 }
 
 stag_status ensure_bpool(stag_batch* c, int n) {
@@ -512,6 +513,14 @@ stag_status stag_batch_set_shift_window(stag_batch_handle c, int lag) {
     return STAG_OK;
 }
 
+stag_status stag_batch_set_link_format(stag_batch_handle c, int format) {
+    if (!c) return bfail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
+    if (format != STAG_LINKS_F64_18 && format != STAG_LINKS_F64_12)
+        return bfail(c, STAG_ERR_INVALID_ARG, "format must be STAG_LINKS_F64_18 or STAG_LINKS_F64_12");
+    c->link12 = format == STAG_LINKS_F64_12;
+    return STAG_OK;
+}
+
 stag_status stag_batch_set_tps(stag_batch_handle c, int tps) {
     if (!c) return bfail(nullptr, STAG_ERR_INVALID_ARG, "handle is NULL");
     if (tps != 1 && tps != 2 && tps != 4 && tps != 8)
@@ -535,7 +544,7 @@ std::string tune_key(stag_batch* c, int precision) {
         shapes[b] += 1;
     }
     std::ostringstream k;
-    k << dev << "|p" << precision << "|r" << c->nrhs << "|";
+    k << dev << "|p" << precision << "|r" << c->nrhs << "|l" << (c->link12 ? 12 : 18) << "|";
     for (auto& kv : shapes) k << kv.first << "*" << kv.second << ",";
     return k.str();
 }

@@ -166,6 +166,7 @@ def load_library() -> ctypes.CDLL:
         "stag_set_graphs": (S, [H, I]),
         "stag_batch_set_shift_window": (S, [H, I]),
         "stag_batch_set_tps": (S, [H, I]),
+        "stag_batch_set_link_format": (S, [H, I]),
         "stag_profile_enable": (S, [H, I]),
         "stag_profile_read": (S, [H, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]),
         "stag_tune": (S, [H, I, I]),
@@ -595,6 +596,10 @@ class Batch:
 
     def set_tps(self, tps: int):
         self._check(self.lib.stag_batch_set_tps(self.h, int(tps)))
+
+    def set_link_format(self, fmt: int):
+        """LINKS_F64_18 (default) or LINKS_F64_12: the operators read rows 0-1 of each link."""
+        self._check(self.lib.stag_batch_set_link_format(self.h, int(fmt)))
 
     def tune(self, precision=0):
         us = (ctypes.c_double * 4)()

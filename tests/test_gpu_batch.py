@@ -52,11 +52,21 @@ def test_eight_lanes_per_site_matches_oracle(precision, nrhs):
     _check_against_oracle(precision, nrhs, 8)
 
 
-def _check_against_oracle(precision, nrhs, tps):
-    log(f"batched solve precision={precision} nrhs={nrhs} tps={tps}")
+@pytest.mark.parametrize("precision,nrhs,tps", [(0, 4, None), (1, 3, None), (0, 2, 8), (1, 1, 8)])
+def test_twelve_real_link_reads_match_oracle(precision, nrhs, tps):
+    """The batched operators reading rows 0-1 of every link and rebuilding row
+    2 (FP64, and the mixed form's FP32 operator): solutions against the
+    oracle as with all 18 reals, for the LDS and the hop-per-lane splits."""
+    _check_against_oracle(precision, nrhs, tps, link12=True)
+
+
+def _check_against_oracle(precision, nrhs, tps, link12=False):
+    log(f"batched solve precision={precision} nrhs={nrhs} tps={tps} link12={link12}")
     B, Us, masses, bs, bdev_ = _setup(nrhs)
     if tps:
         B.set_tps(tps)
+    if link12:
+        B.set_link_format(stag.LINKS_F64_12)
     rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
     x, info = B.solve(masses, rat, bdev_, precision=precision, tol=1e-10)
     xh = host(x)
@@ -180,7 +190,8 @@ def test_full_size_64_lattices_against_oracle():
     table, masses uniform in [0.005, 0.05].  FP64: for every lattice (one
     right-hand side each, rotating) the oracle's operator gives every pole's
     true residual below 1e-10 and matches the library's own FP64 residual;
-    mixed precision: the same for one lattice of each volume."""
+    mixed precision, and FP64 reading 12 reals per link: the same for one
+    lattice of each volume."""
     from concurrent.futures import ThreadPoolExecutor
     classes = [(8, 8, 8, 8), (12, 12, 12, 6), (16, 16, 16, 8), (24, 24, 24, 6)]
     dims = [d for d in classes for _ in range(16)]
@@ -204,8 +215,10 @@ def test_full_size_64_lattices_against_oracle():
         o = offs[i] + j * 3 * vh
         return [xh[k][o:o + 3 * vh].reshape(vh, 3) for k in range(len(rat["pole"]))]
 
-    for precision, sample in ((0, range(len(dims))), (1, [0, 16, 32, 48])):
-        log(f"full-size batch precision={precision}")
+    for precision, link12, sample in ((0, False, range(len(dims))), (1, False, [0, 16, 32, 48]),
+                                      (0, True, [1, 17, 33, 49])):
+        log(f"full-size batch precision={precision} link12={link12}")
+        B.set_link_format(stag.LINKS_F64_12 if link12 else stag.LINKS_F64_18)
         x, info = B.solve(masses, rat, b, precision=precision, tol=1e-10)
         xh = host(x)
         for i in sample:
