@@ -393,6 +393,8 @@ def main():
                     help="learned-force chains at 20 leapfrog steps (exact, and exact every 4th kick with the "
                          "truncated solve or the model between); use with --chain-traj 400")
     ap.add_argument("--chain-traj", type=int, default=24, help="trajectories per learned-force comparison chain")
+    ap.add_argument("--improved-traj", type=int, default=10,
+                    help="timed trajectories of the improved-operator chain")
     ap.add_argument("--inner-iters", type=int, default=200,
                     help="iterations of the truncated solve that feeds the learned model's auxiliary channel")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -528,9 +530,11 @@ def main():
             # the workload's 20 leapfrog steps, long chains: exact force, and the
             # exact force on every 4th kick with the truncated solve or the model between
             rh = rhmc(with_model=True, n_traj=args.chain_traj, inner_iters=args.inner_iters, chain_steps=20,
+                      n_improved=args.improved_traj,
                       every_list=(4,), ablation=False)
         else:
-            rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj, inner_iters=args.inner_iters)
+            rh = rhmc(with_model=not args.no_surrogate, n_traj=args.chain_traj, inner_iters=args.inner_iters,
+                      n_improved=args.improved_traj)
 
     out = {
         "metric": "multishift-CG Dslash GB/s (% HBM peak) at 32^3x8; sec/RHMC trajectory",
@@ -992,9 +996,11 @@ def improved_rhmc(lat, U_therm, summary, t_first, n_traj, beta, mass, tau, n_ste
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     res = []
-    for _ in range(n_traj):
+    for k in range(n_traj):
         res.append(lat.trajectory(beta, mass, tau, n_steps, r_f, r_a, r_h, traj_index=t, **kw))
         t += 1
+        if (k + 1) % 50 == 0:
+            log(f"improved-operator chain: {k + 1} of {n_traj} trajectories")
     torch.cuda.synchronize()
     out = summary(res, (time.perf_counter() - t1) / n_traj)
     lat.set_naik(1.0, 0.0)
@@ -1004,7 +1010,7 @@ def improved_rhmc(lat, U_therm, summary, t_first, n_traj, beta, mass, tau, n_ste
 
 
 def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.0, inner_iters=200,
-         chain_steps=40, every_list=(2, 4), ablation=True):
+         chain_steps=40, every_list=(2, 4), ablation=True, n_improved=10):
     """RHMC at 16^3x8 (beta 5.4, m 0.02, the 12-pole MD table with 20-pole
     action and heat-bath tables, tau 1, 20 leapfrog steps, MD tolerance 1e-8,
     action 1e-10) from a seeded hot start,
@@ -1085,7 +1091,8 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     for v in md.values():
         v["speedup_vs_fp64"] = round(out["sec_per_trajectory"]["sec_per_traj"] / v["sec_per_traj"], 3)
     out["md_precision_forms"] = md
-    out["improved_operator"] = improved_rhmc(lat, U_therm, summary, t_first, n_exact, beta, mass, tau, n_steps, kw)
+    out["improved_operator"] = improved_rhmc(lat, U_therm, summary, t_first, n_improved, beta, mass, tau, n_steps,
+                                             kw)
     out["improved_operator"]["sec_per_traj_vs_one_hop"] = round(
         out["improved_operator"]["sec_per_traj"] / out["sec_per_trajectory"]["sec_per_traj"], 3)
     t = t_first + n_exact
