@@ -209,3 +209,30 @@ def test_mean_exp_minus_dH_is_one(improved):
     log(f"  <exp(-dH)> = {mean:.4f} +- {err:.4f}, <|dH|> = {np.mean(np.abs(dH)):.3f}")
     assert err < 0.05
     assert abs(mean - 1.0) < 4 * err
+
+
+def test_pure_gauge_plaquette_at_strong_coupling():
+    """Pure-gauge HMC at beta = 0.5 on 4^4 against the strong-coupling
+    expansion of the Wilson action: the one-plaquette integral gives
+    <Re tr P / 3> = beta/18 + beta^2/216 + O(beta^3) (the second-order term
+    from <(Re tr U)^2> = 1/2 over SU(3)).  300 trajectories after 50 to
+    equilibrate from a cold start; the chain mean (error from blocks of 25)
+    within the larger of four standard errors and 1e-3 (a bound on the
+    neglected higher orders at this beta)."""
+    dims = (4, 4, 4, 4)
+    beta = 0.5
+    log("pure-gauge plaquette at beta 0.5")
+    lat = lattice(dims, synth.random_su3_near_identity(dims, 0.0, synth.make_rng(303, 0)))
+    prm = _params(10, 1.0)
+    plaq = []
+    for t in range(350):
+        out = lat.trajectory(beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
+                             seed=9, traj_index=t, no_fermions=True)
+        if t >= 50:
+            plaq.append(out["plaquette"])
+    blocks = np.array(plaq).reshape(12, 25).mean(axis=1)
+    mean, err = blocks.mean(), blocks.std() / np.sqrt(len(blocks) - 1)
+    expect = beta / 18 + beta ** 2 / 216
+    log(f"  <P> = {mean:.5f} +- {err:.5f}, strong coupling {expect:.5f}")
+    assert abs(mean - expect) < max(4 * err, 1e-3)
+    assert err < 1e-3
