@@ -190,7 +190,9 @@ def test_mean_exp_minus_dH_is_one(improved):
     heat bath make <exp(-dH)> = 1 for every configuration: a 400-trajectory
     chain on 4^4 (tau 0.5, 10 steps, <|dH|> ~ 0.3) averages to 1 within four
     standard errors, with the one-hop and with the improved operator (whose
-    force and action are then consistent at the level the statistic sees)."""
+    force and action are then consistent at the level the statistic sees).
+    The same chain's initial fermion actions average to 3 Vh, the mean of
+    xi^dag xi for the heat bath's complex Gaussian noise."""
     from oracle import naik
     dims = (4, 4, 4, 4)
     log(f"<exp(-dH)> over a 400-trajectory chain, improved={improved}")
@@ -199,16 +201,23 @@ def test_mean_exp_minus_dH_is_one(improved):
     lat = lattice(dims, U0)
     if improved:
         lat.set_naik(naik.C1, naik.C3)
-    dH = []
+    dH, Sf = [], []
     for t in range(400):
         out = lat.trajectory(prm.beta, prm.mass, prm.tau, prm.n_steps, prm.r_md, prm.r_action, prm.r_heatbath,
                              tol_md=1e-10, tol_action=1e-12, seed=77, traj_index=t)
         dH.append(out["dH"])
+        Sf.append(out["Sf_old"])
     e = np.exp(-np.array(dH))
     mean, err = e.mean(), e.std() / np.sqrt(len(e) - 1)
     log(f"  <exp(-dH)> = {mean:.4f} +- {err:.4f}, <|dH|> = {np.mean(np.abs(dH)):.3f}")
     assert err < 0.05
     assert abs(mean - 1.0) < 4 * err
+    # the heat bath: S_f at the start is xi^dag xi up to the tables' error,
+    # whose mean is the number of complex components, 3 Vh
+    vh3 = 3 * dims[0] * dims[1] * dims[2] * dims[3] // 2
+    sm, se = np.mean(Sf), np.std(Sf) / np.sqrt(len(Sf) - 1)
+    log(f"  <S_f> / (3 Vh) = {sm / vh3:.4f} +- {se / vh3:.4f}")
+    assert abs(sm - vh3) < 4 * se
 
 
 def test_pure_gauge_plaquette_at_strong_coupling():
