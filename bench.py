@@ -41,6 +41,22 @@ B_UPD_FIXED = 336       # r (rw) 96, Ap 48, p (rw) 96, x_base (rw) 96
 B_UPD_SHIFT = 192       # per active shifted system: x_k and p_k read and written
 
 
+class no_gc:
+    """Python's cyclic garbage collector off inside a timed region (collected
+    just before): a full collection in this process takes ~40 ms and would
+    otherwise land in a random timed step.  The GPU work is unchanged."""
+
+    def __enter__(self):
+        import gc
+        gc.collect()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        import gc
+        gc.enable()
+        return False
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -465,14 +481,15 @@ def main():
         info = step()
     torch.cuda.synchronize()
     log(f"timing {args.steps} solves")
-    t0 = time.perf_counter()
-    infos, step_ms = [], []
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        infos.append(step())      # returns after the solve has finished (host-side info)
-        step_ms.append((time.perf_counter() - ts) * 1e3)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        infos, step_ms = [], []
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            infos.append(step())      # returns after the solve has finished (host-side info)
+            step_ms.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
     bytes_total = sum(solve_bytes(vh, i["iters"], i["iters_per_pole"], base, args.lag, fused) for i in infos)
     value = bytes_total / elapsed / 1e9
@@ -1072,11 +1089,13 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     def timed_chain(**extra):
         lat.set_gauge(U_therm)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        res = [lat.trajectory(beta, mass, tau, n_steps, r_f, r_a, r_h, traj_index=t_first + i, **kw, **extra)
-               for i in range(n_exact)]
-        torch.cuda.synchronize()
-        return summary(res, (time.perf_counter() - t1) / n_exact)
+        with no_gc():
+            t1 = time.perf_counter()
+            res = [lat.trajectory(beta, mass, tau, n_steps, r_f, r_a, r_h, traj_index=t_first + i, **kw, **extra)
+                   for i in range(n_exact)]
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / n_exact
+        return summary(res, dt)
 
     out = {"sec_per_trajectory": dict(timed_chain(), polyakov_loop_thermalised=[round(pl.real, 6), round(pl.imag, 6)],
                                       workload="RHMC 16^3x8, beta 5.4, m 0.02, 12-pole x^(-1/2) MD table, "

@@ -3,6 +3,7 @@
 
 #include <string>
 #include <utility>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -79,6 +80,9 @@ struct stag_ctx {
     std::vector<float> prof_samples[3];  // every recorded launch's milliseconds
     std::string err;
     int last_iters = 0;
+    // iterations the last solve of each kind took (key: poles, tolerance,
+    // mass term, window, precision, loop), the chunk scheduler's estimate
+    std::unordered_map<uint64_t, int> iter_hint;
 };
 
 namespace stag {

@@ -241,17 +241,55 @@ void store_graph(stag_ctx* c, const ChunkKey& key, hipGraphExec_t exec) {
 // next iteration.  Without extra work or profiling, a chunk is captured once
 // into a hipGraph (kernel nodes only) and replayed: the chunk length is a
 // multiple of 2 and of the window, so every chunk repeats the same launches.
+// Issue chunks into the two flag slots in turn and wait for them in order:
+// up to two in flight (one with two_in_flight false, and one once
+// past_estimate() holds), until a chunk's flag says the solve has stopped.
+template <class Issue, class Past>
+stag_status drive_chunks(stag_ctx* c, Issue& issue_chunk, bool two_in_flight, Past past_estimate) {
+    int q[2], nq = 0, next_slot = 0;
+    auto issue = [&]() {
+        issue_chunk(next_slot);
+        q[nq++] = next_slot;
+        next_slot ^= 1;
+    };
+    issue();
+    if (two_in_flight && !past_estimate()) issue();
+    for (;;) {
+        const int s0 = q[0];
+        q[0] = q[1];
+        --nq;
+        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[s0]));
+        if (c->done_host[s0]) break;
+        const int cap = (!two_in_flight || past_estimate()) ? 1 : 2;
+        while (nq < cap) issue();
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    return STAG_OK;
+}
+
+//
+// pred > 0: the iterations the solve is expected to take (the last solve of
+// the same kind).  Chunks that would run past it shrink to `small`
+// iterations, and once pred iterations are issued the next chunk waits for
+// the flag: a converged solve then leaves fewer early-exit launches queued.
+// Results do not depend on the chunking.
+inline int small_chunk(int chunk, int L) {
+    const int s = L % 2 == 0 ? L : 2 * L;
+    return s < chunk ? s : chunk;
+}
+
 template <class V, class Between>
 stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtrs X, VecPtrs P, int chunk,
                            EvRec& rec, Between between_chunks, bool two_in_flight = true,
-                           bool extra_work = false) {
+                           bool extra_work = false, int pred = 0) {
     const Geom& g = c->g;
     const double mt = c->st_host->mass_term;
     const int L = c->st_host->lag;
     const int nb2 = dslash_grid(g, c->tps);
+    const int small = small_chunk(chunk, L);
     int it_issued = 0;
-    auto enqueue_chunk = [&]() {
-        for (int it = 0; it < chunk; ++it, ++it_issued) {
+    auto enqueue_chunk = [&](int len) {
+        for (int it = 0; it < len; ++it, ++it_issued) {
             const int par = it_issued & 1;
             hipEvent_t a;
             prof_begin(c, &a);
@@ -283,8 +321,12 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
             prof_end(c, a, 2, rec);
         }
     };
-    hipGraphExec_t exec = nullptr;
-    if (c->use_graph && !c->prof_on && !extra_work && chunk % 2 == 0 && chunk % L == 0) {
+    const bool graphs = c->use_graph && !c->prof_on && !extra_work && chunk % 2 == 0 && chunk % L == 0;
+    // one captured graph per chunk length; every replay starts at a multiple
+    // of 2 and of L, like the capture
+    auto graph_for = [&](int len, hipGraphExec_t& exec) -> stag_status {
+        exec = nullptr;
+        if (!graphs) return STAG_OK;
         ChunkKey key;
         std::memset(&key, 0, sizeof(key));
         key.g = g;
@@ -304,45 +346,45 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
         key.lag = L;
         key.n = c->st_host->n;
         key.base = c->st_host->base;
-        key.chunk = chunk;
+        key.chunk = len;
         key.nb2 = nb2;
         key.v64 = sizeof(V) == sizeof(double2);
         exec = cached_graph(c, key);
         if (!exec) {
             hipGraph_t graph = nullptr;
+            const int saved = it_issued;
+            it_issued = 0;
             HIP_OR_FAIL(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
-            enqueue_chunk();
+            enqueue_chunk(len);
             HIP_OR_FAIL(c, hipStreamEndCapture(c->s, &graph));
+            it_issued = saved;
             const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             hipGraphDestroy(graph);
             if (ie != hipSuccess) return fail(c, STAG_ERR_HIP, "hipGraphInstantiate failed");
             store_graph(c, key, exec);
-            it_issued = 0;
         }
-    }
+        return STAG_OK;
+    };
+    hipGraphExec_t exec = nullptr, exec_small = nullptr;
+    stag_status e;
+    if ((e = graph_for(chunk, exec))) return e;
+    if (pred > 0 && small < chunk && (e = graph_for(small, exec_small))) return e;
     auto issue_chunk = [&](int slot) {
-        if (exec) {
-            hipGraphLaunch(exec, c->s);
-            it_issued += chunk;
+        // the launch of device iteration pred (the expected stop) sets the flag
+        const int len = (pred > 0 && it_issued + chunk > pred + 1) ? small : chunk;
+        hipGraphExec_t ex = len == chunk ? exec : exec_small;
+        if (ex) {
+            hipGraphLaunch(ex, c->s);
+            it_issued += len;
         } else {
-            enqueue_chunk();
+            enqueue_chunk(len);
         }
         between_chunks(it_issued & 1);
         // the flag the next iteration would read
         hipMemcpyAsync(&c->done_host[slot], &c->st->done[it_issued & 1], sizeof(int), hipMemcpyDeviceToHost, c->s);
         hipEventRecord(c->chunk_ev[slot], c->s);
     };
-    issue_chunk(0);
-    if (two_in_flight) issue_chunk(1);
-    int cur = 0;
-    for (;;) {
-        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
-        if (c->done_host[cur]) break;
-        issue_chunk(cur);
-        if (two_in_flight) cur ^= 1;
-    }
-    HIP_OR_FAIL(c, hipGetLastError());
-    return STAG_OK;
+    return drive_chunks(c, issue_chunk, two_in_flight, [&]() { return pred > 0 && it_issued > pred; });
 }
 
 // The fused loop (FP64, window L >= 2): iteration j is
@@ -357,7 +399,7 @@ constexpr int kFusedMaxBlocks = 512;
 
 template <class V>
 stag_status run_fused(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtrs X, VecPtrs P, int chunk,
-                      EvRec& rec) {
+                      EvRec& rec, int pred = 0) {
     const Geom& g = c->g;
     const double mt = c->st_host->mass_term;
     const int n = c->st_host->n, base = c->st_host->base;
@@ -399,8 +441,9 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtr
         launch_dslash_cg_fused(g, ls, K.w, pbuf[0], K.r, K.Ap, &c->st->done[1], c->dpart, c->s, mt);
     }
     int it_issued = 1;
-    auto enqueue_chunk = [&]() {
-        for (int it = 0; it < chunk; ++it, ++it_issued) {
+    const int small = small_chunk(chunk, L);
+    auto enqueue_chunk = [&](int len) {
+        for (int it = 0; it < len; ++it, ++it_issued) {
             const int j = it_issued, par = j & 1;
             const FusedIterT<V> f = iter_args(j);
             hipEvent_t a;
@@ -418,8 +461,12 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtr
             }
         }
     };
-    hipGraphExec_t exec = nullptr;
-    if (c->use_graph && !c->prof_on && chunk % 2 == 0 && chunk % L == 0) {
+    const bool graphs = c->use_graph && !c->prof_on && chunk % 2 == 0 && chunk % L == 0;
+    // one captured graph per chunk length, captured from j = 1; every replay
+    // starts at j = 1 mod L and odd, like the capture
+    auto graph_for = [&](int len, hipGraphExec_t& exec) -> stag_status {
+        exec = nullptr;
+        if (!graphs) return STAG_OK;
         ChunkKey key;
         std::memset(&key, 0, sizeof(key));
         key.g = g;
@@ -440,7 +487,7 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtr
         key.lag = L;
         key.n = n;
         key.base = base;
-        key.chunk = chunk;
+        key.chunk = len;
         key.nb2 = nb2;
         key.v64 = sizeof(V) == sizeof(double2);
         key.fused = 1;
@@ -448,42 +495,64 @@ stag_status run_fused(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, VecPtr
         exec = cached_graph(c, key);
         if (!exec) {
             hipGraph_t graph = nullptr;
+            const int saved = it_issued;
+            it_issued = 1;
             HIP_OR_FAIL(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
-            enqueue_chunk();
+            enqueue_chunk(len);
             HIP_OR_FAIL(c, hipStreamEndCapture(c->s, &graph));
+            it_issued = saved;
             const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             hipGraphDestroy(graph);
             if (ie != hipSuccess) return fail(c, STAG_ERR_HIP, "hipGraphInstantiate failed");
             store_graph(c, key, exec);
-            it_issued = 1;
         }
-    }
+        return STAG_OK;
+    };
+    hipGraphExec_t exec = nullptr, exec_small = nullptr;
+    stag_status e;
+    if ((e = graph_for(chunk, exec))) return e;
+    if (pred > 0 && small < chunk && (e = graph_for(small, exec_small))) return e;
     auto issue_chunk = [&](int slot) {
-        if (exec) {
-            hipGraphLaunch(exec, c->s);
-            it_issued += chunk;
+        // the D_oe launch of iteration pred + 1 evaluates step pred (the
+        // expected stop) and sets the flag
+        const int len = (pred > 0 && it_issued + chunk > pred + 2) ? small : chunk;
+        hipGraphExec_t ex = len == chunk ? exec : exec_small;
+        if (ex) {
+            hipGraphLaunch(ex, c->s);
+            it_issued += len;
         } else {
-            enqueue_chunk();
+            enqueue_chunk(len);
         }
         // the flag the next D_oe launch would read
         hipMemcpyAsync(&c->done_host[slot], &c->st->done[it_issued & 1], sizeof(int), hipMemcpyDeviceToHost, c->s);
         hipEventRecord(c->chunk_ev[slot], c->s);
     };
-    issue_chunk(0);
-    issue_chunk(1);
-    int cur = 0;
-    for (;;) {
-        HIP_OR_FAIL(c, hipEventSynchronize(c->chunk_ev[cur]));
-        if (c->done_host[cur]) break;
-        issue_chunk(cur);
-        cur ^= 1;
-    }
+    if ((e = drive_chunks(c, issue_chunk, true, [&]() { return pred > 0 && it_issued > pred + 1; }))) return e;
     if (nsh > 0) launch_ms_flush(g, (const V*)K.r, X, P, c->st, nullptr, n, base, L, true, rows, c->s);
     HIP_OR_FAIL(c, hipGetLastError());
     return STAG_OK;
 }
 
 // Multi-shift CG in Krylov precision V (x_k always FP64).
+// A key for solves that take about the same number of iterations: the poles,
+// residues, tolerance and mass term of the state, its window, and the loop,
+// precision and operator (FNV-1a over their bytes).
+uint64_t solve_kind(const MsState* h, bool fused, bool fp64, int naik, int fmt64, int fmt32) {
+    uint64_t x = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) x = (x ^ b[i]) * 1099511628211ull;
+    };
+    mix(&h->n, sizeof h->n);
+    mix(h->shift, sizeof(double) * h->n);
+    mix(&h->tol2, sizeof h->tol2);
+    mix(&h->mass_term, sizeof h->mass_term);
+    mix(&h->lag, sizeof h->lag);
+    const int tag[5] = {fused, fp64, naik, fmt64, fmt32};
+    mix(tag, sizeof tag);
+    return x;
+}
+
 template <class V>
 stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_rational* r, double tol, int maxiter,
                        const double2* b, double2* const* x, int* ipp_out, SolveResult& res, EvRec& rec) {
@@ -510,15 +579,21 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
     }
     launch_ms_init<V>(g, b, K.r, K.p, X, P, c->st, c->qpart[0], c->s);
     res.fused = fused;
+    // the iterations of the last solve of this kind, as the chunk scheduler's
+    // estimate (a hint only: the solve runs until its own stop)
+    const uint64_t kind = solve_kind(h, fused, sizeof(V) == sizeof(double2), c->naik, ls.fmt64, ls.fmt32);
+    const auto hint = c->iter_hint.find(kind);
+    const int pred = hint == c->iter_hint.end() ? 0 : hint->second;
     if (fused)
-        e = run_fused<V>(c, ls, K, X, P, c->chunk, rec);
+        e = run_fused<V>(c, ls, K, X, P, c->chunk, rec, pred);
     else
-        e = run_iterations<V>(c, ls, K, X, P, c->chunk, rec, [](int) {});
+        e = run_iterations<V>(c, ls, K, X, P, c->chunk, rec, [](int) {}, true, false, pred);
     if (e) return e;
     HIP_OR_FAIL(c, hipMemcpyAsync(h, c->st, sizeof(MsState), hipMemcpyDeviceToHost, c->s));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
     const MsIter& f = h->fin;
     res.iters = f.iter;
+    c->iter_hint[kind] = f.iter;
     res.nonfinite = f.nonfinite;
     res.bb = f.bb;
     res.converged = 1;

@@ -331,3 +331,38 @@ def test_fused_stop_inside_a_window(maxiter):
         assert info["iters"] == maxiter
         got[fused] = np.stack([host(x) for x in xs])
     assert np.abs(got[True] - got[False]).max() <= 1e-12 * np.abs(got[False]).max()
+
+
+@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("graph", [True, False])
+def test_repeated_solves_with_the_iteration_estimate(fused, graph):
+    """A solve of a kind seen before schedules its chunks from the previous
+    iteration count (smaller chunks near the expected stop, one chunk in
+    flight past it): the solutions and iteration counts are bitwise those of
+    the first solve, and a solve that needs more iterations than the
+    estimate (left by a solve of the same kind stopped at maxiter = 10)
+    still runs to its own stop."""
+    dims = (8, 6, 4, 10)
+    rng = synth.make_rng(0, 17)
+    U = synth.random_su3_near_identity(dims, 0.4, rng)
+    lat = lattice(dims, U)
+    lat.set_fused_iteration(fused)
+    if not graph:
+        lat.set_graphs(False)
+    rat = _rat(C0_POLES)
+    b = synth.gaussian_half_vector(dims, rng)
+    runs = [_solve(lat, dims, 0.05, rat, 1e-10, b) for _ in range(3)]
+    for xs, s, info in runs[1:]:
+        assert info["iters"] == runs[0][2]["iters"]
+        assert info["iters_per_pole"] == runs[0][2]["iters_per_pole"]
+        for x, x0 in zip(xs, runs[0][0]):
+            assert np.array_equal(x, x0)
+    # a solve stopped at maxiter = 10 leaves an estimate of 10 iterations
+    bd = lat.vec_import(dev(b), 0)
+    xs10 = [lat.new_vec() for _ in rat["pole"]]
+    short = lat.multishift_solve(0.05, rat, 1e-10, 10, bd, xs10, None, true_resid=False, allow_not_converged=True)
+    assert short["iters"] == 10
+    xs, s, info = _solve(lat, dims, 0.05, rat, 1e-10, b)
+    assert info["iters"] == runs[0][2]["iters"]
+    for x, x0 in zip(xs, runs[0][0]):
+        assert np.array_equal(x, x0)
