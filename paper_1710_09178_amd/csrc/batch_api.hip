@@ -11,6 +11,8 @@
 #include <sstream>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
+#include <unordered_map>
 #include <vector>
 
 #include "batch.h"
@@ -54,6 +56,16 @@ struct stag_batch {
     double* sums = nullptr;
     int* done_host = nullptr;    // pinned [2 * n_inst]
     double* sums_host = nullptr;  // pinned [n_sys]
+    // captured iteration chunks, keyed by every launch argument (LRU)
+    struct BGraph {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec = nullptr;
+        unsigned long long used = 0;
+    };
+    std::vector<BGraph> graphs;
+    unsigned long long graph_clock = 0;
+    // iterations the last solve of each kind took (the chunk scheduler's estimate)
+    std::unordered_map<uint64_t, int> iter_hint;
     std::string err;
 };
 
@@ -190,10 +202,28 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
         P.p[k] = (V*)c->pool_p + (size_t)k * bvec_len(c);
     }
     launch_bms_init<V>(bd, b, r, p, X, P, st, c->qpart[0], c->s);
-    // a multiple of 2 and of the window: the parity and ring patterns repeat across chunks
-    const int chunk = 16;
-    auto enqueue_chunk = [&]() {
-        for (int it = 0; it < chunk; ++it) {
+    // a multiple of 2 and of the window: the parity and ring patterns repeat
+    // across chunks; near the expected stop (the last solve of this kind)
+    // chunks shrink to 8 iterations and one is in flight past it
+    const int chunk = 16, small = 8;
+    uint64_t kind = 1469598103934665603ull;
+    auto mix = [&](const void* q, size_t nb) {
+        const unsigned char* u = static_cast<const unsigned char*>(q);
+        for (size_t i = 0; i < nb; ++i) kind = (kind ^ u[i]) * 1099511628211ull;
+    };
+    mix(&n, sizeof n);
+    mix(st.shift, sizeof(double) * n);
+    mix(&st.tol2, sizeof st.tol2);
+    mix(&st.lag, sizeof st.lag);
+    mix(&st.bb_given, sizeof st.bb_given);
+    mix(s0.data(), sizeof(double) * s0.size());
+    const int fp64 = std::is_same<V, double2>::value;
+    mix(&fp64, sizeof fp64);
+    mix(&bd.link12, sizeof bd.link12);
+    const auto hint = c->iter_hint.find(kind);
+    const int pred = hint == c->iter_hint.end() ? 0 : hint->second;
+    auto enqueue_chunk = [&](int len) {
+        for (int it = 0; it < len; ++it) {
             const int par = it & 1;
             const V* rj = r + (size_t)(it % st.lag) * st.ring_stride;
             const int* gate = st.inst_done + par * c->n_inst;
@@ -203,29 +233,95 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
             launch_bms_step<V>(bd, r, Ap, p, X, P, st, c->dpart, c->qpart[par], c->qpart[par ^ 1], par, c->s);
         }
     };
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    if (use_graph) {
+    // one captured graph per chunk length and launch arguments, kept across solves
+    auto graph_for = [&](int len, hipGraphExec_t& exec) -> stag_status {
+        exec = nullptr;
+        if (!use_graph) return STAG_OK;
+        std::vector<unsigned char> key;
+        auto put = [&](const void* q, size_t nb) {
+            const unsigned char* u = static_cast<const unsigned char*>(q);
+            key.insert(key.end(), u, u + nb);
+        };
+        // (field by field where a struct may hold uninitialised padding;
+        // c->st is value-initialised with the handle)
+        put(&bd.inst, sizeof bd.inst);
+        put(&bd.tiles, sizeof bd.tiles);
+        const int bdi[5] = {bd.ntiles, bd.tile_sites, bd.nrhs, bd.link_nt, bd.link12};
+        put(bdi, sizeof bdi);
+        put(&st, sizeof st);
+        put(&links, sizeof links);
+        put(&r, sizeof r);
+        put(&p, sizeof p);
+        put(&Ap, sizeof Ap);
+        put(&w, sizeof w);
+        put(&X, sizeof X);
+        put(&P, sizeof P);
+        put(&c->dpart, sizeof c->dpart);
+        put(c->qpart, sizeof c->qpart);
+        put(&c->tps, sizeof c->tps);
+        put(&len, sizeof len);
+        put(&fp64, sizeof fp64);
+        for (auto& e : c->graphs)
+            if (e.key == key) {
+                e.used = ++c->graph_clock;
+                exec = e.exec;
+                return STAG_OK;
+            }
+        hipGraph_t graph = nullptr;
         BHIP(c, hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal));
-        enqueue_chunk();
+        enqueue_chunk(len);
         BHIP(c, hipStreamEndCapture(c->s, &graph));
-        BHIP(c, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-    }
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (ie != hipSuccess) return bfail(c, STAG_ERR_HIP, "hipGraphInstantiate failed");
+        constexpr size_t kMaxGraphs = 6;
+        if (c->graphs.size() >= kMaxGraphs) {
+            size_t lru = 0;
+            for (size_t i = 1; i < c->graphs.size(); ++i)
+                if (c->graphs[i].used < c->graphs[lru].used) lru = i;
+            hipGraphExecDestroy(c->graphs[lru].exec);
+            c->graphs.erase(c->graphs.begin() + lru);
+        }
+        stag_batch::BGraph g;
+        g.key = std::move(key);
+        g.exec = exec;
+        g.used = ++c->graph_clock;
+        c->graphs.push_back(std::move(g));
+        return STAG_OK;
+    };
+    hipGraphExec_t exec = nullptr, exec_small = nullptr;
+    stag_status ge;
+    if ((ge = graph_for(chunk, exec))) return ge;
+    if (pred > 0 && (ge = graph_for(small, exec_small))) return ge;
     int* dh = c->done_host;
+    int it_issued = 0;
     auto issue = [&](int slot) {
-        if (use_graph)
-            hipGraphLaunch(exec, c->s);
+        // the scalar launch of device iteration pred (the expected stop) sets the flags
+        const int len = (pred > 0 && it_issued + chunk > pred + 1) ? small : chunk;
+        hipGraphExec_t ex = len == chunk ? exec : exec_small;
+        if (ex)
+            hipGraphLaunch(ex, c->s);
         else
-            enqueue_chunk();
+            enqueue_chunk(len);
+        it_issued += len;
         // chunks are even: the next iteration reads the parity-0 flags
         hipMemcpyAsync(dh + slot * c->n_inst, st.inst_done, c->n_inst * sizeof(int), hipMemcpyDeviceToHost, c->s);
         hipEventRecord(c->chunk_ev[slot], c->s);
     };
-    issue(0);
-    issue(1);
-    int cur = 0;
+    auto past_estimate = [&]() { return pred > 0 && it_issued > pred; };
+    int q[2], nq = 0, next_slot = 0;
+    auto push = [&]() {
+        issue(next_slot);
+        q[nq++] = next_slot;
+        next_slot ^= 1;
+    };
+    push();
+    if (!past_estimate()) push();
     stag_status status = STAG_OK;
     for (;;) {
+        const int cur = q[0];
+        q[0] = q[1];
+        --nq;
         if (hipEventSynchronize(c->chunk_ev[cur]) != hipSuccess) {
             status = bfail(c, STAG_ERR_HIP, "batched solve failed on the device");
             break;
@@ -233,12 +329,10 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
         bool all = true;
         for (int i = 0; i < c->n_inst; ++i) all &= dh[cur * c->n_inst + i] != 0;
         if (all) break;
-        issue(cur);
-        cur ^= 1;
+        const int cap = past_estimate() ? 1 : 2;
+        while (nq < cap) push();
     }
     hipStreamSynchronize(c->s);
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
     if (status) return status;
     BHIP(c, hipGetLastError());
     std::vector<MsIter> fin(c->n_sys);
@@ -250,6 +344,7 @@ stag_status bsolve_t(stag_batch* c, int n, const double* poles, const double* ma
         if (f.nonfinite) return bfail(c, STAG_ERR_NONFINITE, "non-finite value in the batched solve");
         for (int k = 0; k < n; ++k) conv_out &= !f.active[k];
     }
+    c->iter_hint[kind] = iters_out;
     return STAG_OK;
 }
 
@@ -359,6 +454,8 @@ stag_status stag_batch_destroy(stag_batch_handle c) {
                     c->st.t_done, c->st.sigma0_term, c->st.hist, c->st.scal, c->st.w_tab, c->st.w_act, c->dpart, c->qpart[0], c->qpart[1], c->gpart, c->sums};
     for (void* b : bufs)
         if (b) hipFree(b);
+    for (auto& g : c->graphs)
+        if (g.exec) hipGraphExecDestroy(g.exec);
     if (c->done_host) hipHostFree(c->done_host);
     if (c->sums_host) hipHostFree(c->sums_host);
     hipEvent_t evs[] = {c->ev_in, c->ev_out, c->chunk_ev[0], c->chunk_ev[1]};

@@ -259,3 +259,23 @@ def test_autotune_cache_and_link_loads(tmp_path):
         assert info["true_resid"].max() < 1e-10
         got.append(host(x))
     assert np.array_equal(got[0], got[1])
+
+
+def test_repeated_batched_solves_with_the_iteration_estimate():
+    """Later solves of the same kind replay the cached chunk graphs and
+    schedule their chunks from the previous iteration count: bitwise the
+    first solve's solutions and counts, also right after a solve of the same
+    kind stopped at maxiter = 6 (an estimate far too short)."""
+    B, Us, masses, bs, bd = _setup(2, seed=4)
+    rat = {"c0": 0.0, "pole": POLES, "residue": [1.0] * len(POLES)}
+    x0, i0 = B.solve(masses, rat, bd, true_resid=False)
+    x0 = host(x0)
+    for _ in range(2):
+        x1, i1 = B.solve(masses, rat, bd, true_resid=False)
+        assert i1["iters"] == i0["iters"]
+        assert np.array_equal(host(x1), x0)
+    _, ishort = B.solve(masses, rat, bd, maxiter=6, true_resid=False, allow_not_converged=True)
+    assert ishort["iters"] == 6
+    x2, i2 = B.solve(masses, rat, bd, true_resid=False)
+    assert i2["iters"] == i0["iters"]
+    assert np.array_equal(host(x2), x0)
