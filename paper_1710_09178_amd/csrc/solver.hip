@@ -387,11 +387,11 @@ stag_status run_iterations(stag_ctx* c, const LinkSet& ls, const Krylov<V>& K, V
     return drive_chunks(c, issue_chunk, two_in_flight, [&]() { return pred > 0 && it_issued > pred; });
 }
 
-// The fused loop (FP64, window L >= 2): iteration j is
+// The fused loop (FP64 or FP32 Krylov vectors, window L >= 2): iteration j is
 //   D_oe launch j: step j-1's scalars, r_j, p_j, x_base, w = D_oe p_j
 //   D_eo launch j: Ap_j and the three dots
 //   flush after iterations j with j % L == 0 (shifted systems, steps j-L..j-1)
-// with p double-buffered by parity (K.p, c->p2).  Iteration 0 is enqueued
+// with p double-buffered by parity (K.p, K.p2).  Iteration 0 is enqueued
 // eagerly, then chunks of `chunk` iterations from j = 1 (a multiple of 2 and
 // of L, so a captured chunk replays for every later one), and once the solve
 // has stopped a final flush for the steps of its last, partial window.
@@ -564,7 +564,7 @@ stag_status ms_solve_t(stag_ctx* c, const LinkSet& ls, double mass, const stag_r
     MsState* h = c->st_host;
     int base;
     init_state(h, n, r->pole, r->residue, r->c0, mass, tol, maxiter, base);
-    // the fused loop (FP64, window >= 2; it keeps r_{j-1} and r_j in the ring
+    // the fused loop (window >= 2; it keeps r_{j-1} and r_j in the ring
     // at once): by default on grids of at most kFusedMaxBlocks Dslash blocks,
     // where an iteration is latency-bound; with on = 2 at every size
     const bool fused = c->lag >= 2 &&
