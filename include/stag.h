@@ -377,6 +377,10 @@ typedef struct {
                                      spectrum of A on its starting links (stag_check_spectrum) and
                                      returns STAG_ERR_SPECTRUM, with nothing changed, if it does not
                                      cover it */
+    int judge_model;              /* 1, with a model: at every exact kick the model's force is also
+                                     evaluated on the same links and compared with the exact force
+                                     (info->model_force_err); the exact kick then adds dt * F from a
+                                     separate force field, which changes its rounding, not the method */
 } stag_hmc_params;
 
 typedef struct {
@@ -388,6 +392,9 @@ typedef struct {
     int cg_iters_total;
     int n_solves;
     double seconds;
+    double model_force_err;       /* mean of |F_model - F| / |F| over the exact kicks (judge_model),
+                                     -1 when not judged */
+    int used_model;               /* 1 when a model stood in for the force on some kicks */
 } stag_traj_info;
 
 /* Heat bath, leapfrog integration and Metropolis test on the handle's gauge
@@ -397,6 +404,32 @@ typedef struct {
  * restored to its state at the call and the model's auxiliary field is
  * detached, so the handle still holds the chain's configuration. */
 stag_status stag_md_trajectory(stag_handle h, const stag_hmc_params* p, stag_traj_info* info);
+
+/* A chain of n_traj trajectories (indices p->traj_index, +1, ...) where the
+ * exact force is the fallback of the model and its judge: trajectories that
+ * use the model (p->surrogate with its schedule) are judged (judge_model), and
+ * after one whose judged force error exceeds max_model_err, or once the last
+ * `window` model trajectories accepted less than min_acceptance on average,
+ * the next exact_trajectories trajectories run with the exact force on every
+ * kick before the model is tried again.  Decisions use completed
+ * trajectories only, never a trajectory in progress: every trajectory is an
+ * exact, reversible RHMC update (its Metropolis test takes the exact action
+ * whichever force drove it), while the choice between the two integrators
+ * depends on the chain's history, as in any adaptive scheme.  The fallback
+ * trajectories run with exact_every 1 and without coarse_force,
+ * record_pairs or inner_iters.  infos: host [n_traj]; n_done (may be NULL):
+ * the trajectories completed (all of them unless an error stops the chain,
+ * whose status is returned).  STAG_ERR_INVALID_ARG for window < 1,
+ * exact_trajectories < 1, max_model_err <= 0 or min_acceptance outside
+ * [0, 1]. */
+typedef struct {
+    int window;
+    double min_acceptance;
+    double max_model_err;
+    int exact_trajectories;
+} stag_chain_policy;
+stag_status stag_md_chain(stag_handle h, const stag_hmc_params* p, int n_traj, const stag_chain_policy* policy,
+                          stag_traj_info* infos, int* n_done);
 
 /* ---- batched form: many lattices x right-hand sides x poles ---------------- */
 

@@ -21,6 +21,11 @@ thread_local std::string g_create_err;
 }
 
 namespace stag {
+// |a - b|^2 and |b|^2 over n reals into out2[0..1] (force.hip)
+void launch_diff_norm2(size_t n, const double* a, const double* b, double* part, double* out2, hipStream_t s);
+}  // namespace stag
+
+namespace stag {
 stag_status fail(stag_ctx* c, stag_status code, const std::string& msg) {
     if (c)
         c->err = msg;
@@ -306,7 +311,7 @@ stag_status stag_destroy(stag_handle c) {
                     c->naik_w3, c->r32, c->p32, c->p2_32, c->Ap32, c->w32,
                     c->links, c->links_backup, c->mom, c->r, c->p, c->p2, c->Ap, c->w_o, c->tmp_e, c->tmp_o, c->xi,
                     c->phi, c->pool_x, c->pool_p, c->pool_y, c->st, c->dpart, c->qpart[0], c->qpart[1],
-                    c->gpart, c->scal, c->mom_tmp, c->mom_aux};
+                    c->gpart, c->scal, c->mom_tmp, c->mom_aux, c->mom_judge};
     for (void* b : bufs)
         if (b) hipFree(b);
     if (c->st_host) hipHostFree(c->st_host);
@@ -769,8 +774,13 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         return fail(c, STAG_ERR_INVALID_ARG, "coarse_force needs exact_every >= 1 and n_steps % exact_every == 0");
     if (p->record_pairs && (!p->surrogate || p->exact_every != 1))
         return fail(c, STAG_ERR_INVALID_ARG, "record_pairs needs a model and exact_every == 1");
-    if (p->record_pairs && !c->mom_tmp) {
+    const bool judge = p->judge_model && p->surrogate && !p->no_fermions;
+    if ((p->record_pairs || judge) && !c->mom_tmp) {
         stag_status e2 = dmalloc(c, &c->mom_tmp, (size_t)64 * c->g.vh * sizeof(double));
+        if (e2) return e2;
+    }
+    if (judge && !c->mom_judge) {
+        stag_status e2 = dmalloc(c, &c->mom_judge, (size_t)64 * c->g.vh * sizeof(double));
         if (e2) return e2;
     }
     if (p->inner_iters < 0 || (p->inner_iters > 0 && !p->surrogate))
@@ -855,6 +865,8 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     // the inner scale); without a model this is the ablation.
     const double dt = p->tau / p->n_steps;
     int kick_index = 0;
+    double judge_sum = 0.0;
+    int judge_n = 0;
     const int every = p->exact_every < 1 ? 1 : p->exact_every;
     const bool sched = p->surrogate != nullptr || p->coarse_force;
     // the model's auxiliary channel: the pseudofermion force of the current
@@ -884,15 +896,28 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
         stag_status e2;
         // inner-scale model impulse h F_s, outer-scale correction hf (F - F_s)
         if (p->coarse_force && p->surrogate && every > 1 && (e2 = model_force(h - hf))) return e2;
-        if (p->record_pairs) {
+        if (p->record_pairs || judge) {
             if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom_tmp, 0.0, res,
                                          mdf)))
                 return e2;
             if ((e2 = finish_solve_status(c, res))) return e2;
             if (p->inner_iters > 0 && (e2 = truncated_aux())) return e2;
-            if (stag_surrogate_pair_count(p->surrogate) < stag_surrogate_capacity(p->surrogate) &&
+            if (p->record_pairs && stag_surrogate_pair_count(p->surrogate) < stag_surrogate_capacity(p->surrogate) &&
                 (e2 = stag_surrogate_add_pair(p->surrogate, c->mom_tmp)))
                 return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
+            if (judge) {
+                // the model on the same links (and auxiliary force) against the exact force
+                if ((e2 = stag_surrogate_force(p->surrogate, c->mom_judge, 0.0)))
+                    return fail(c, e2, std::string("surrogate: ") + stag_surrogate_last_error(p->surrogate));
+                launch_diff_norm2((size_t)64 * g.vh, c->mom_judge, c->mom_tmp, c->gpart, c->scal, c->s);
+                HIP_OR_FAIL(c, hipMemcpyAsync(c->scal_host, c->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                              c->s));
+                HIP_OR_FAIL(c, hipStreamSynchronize(c->s));
+                if (c->scal_host[1] > 0) {
+                    judge_sum += std::sqrt(c->scal_host[0] / c->scal_host[1]);
+                    ++judge_n;
+                }
+            }
             launch_axpy_real((size_t)64 * g.vh, hf, c->mom_tmp, c->mom, c->s);
         } else {
             if ((e2 = fermion_force_impl(c, p->mass, &p->r_md, p->tol_md, p->maxiter, c->phi, c->mom, hf, res, mdf)))
@@ -919,6 +944,8 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     }
     if (p->inner_iters > 0) stag_surrogate_set_aux(p->surrogate, nullptr);
     I.dH = (I.K_new + I.Sg_new + I.Sf_new) - (I.K_old + I.Sg_old + I.Sf_old);
+    I.model_force_err = judge_n > 0 ? judge_sum / judge_n : -1.0;
+    I.used_model = (ferm && p->surrogate) ? 1 : 0;
     double u = p->inject_u;
     if (u < 0.0) {
         launch_uniform(p->seed, p->traj_index, c->scal, c->s);
@@ -939,6 +966,57 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     I.n_solves = nsolve;
     I.seconds = now_s() - t0;
     if (info) *info = I;
+    return STAG_OK;
+}
+
+// A chain in which the exact force both judges the model and stands in for
+// it: model trajectories are judged at their exact kicks, and a judged force
+// error above the policy's bound, or a low acceptance over the last window of
+// model trajectories, sends the chain to the exact force on every kick for
+// exact_trajectories trajectories.  The decision for trajectory t uses the
+// results of trajectories < t only.
+stag_status stag_md_chain(stag_handle c, const stag_hmc_params* p, int n_traj, const stag_chain_policy* pol,
+                          stag_traj_info* infos, int* n_done) {
+    if (n_done) *n_done = 0;
+    stag_status e = check_common(c, true);
+    if (e) return e;
+    if (!p || !pol || (!infos && n_traj > 0) || n_traj < 0)
+        return fail(c, STAG_ERR_INVALID_ARG, "need params, policy, infos and n_traj >= 0");
+    if (pol->window < 1 || pol->exact_trajectories < 1 || !(pol->max_model_err > 0) ||
+        !(pol->min_acceptance >= 0.0 && pol->min_acceptance <= 1.0))
+        return fail(c, STAG_ERR_INVALID_ARG,
+                    "policy needs window >= 1, exact_trajectories >= 1, max_model_err > 0, 0 <= min_acceptance <= 1");
+    stag_hmc_params q = *p;
+    std::vector<int> recent;  // acceptances of the latest model trajectories
+    int exact_left = 0;
+    for (int t = 0; t < n_traj; ++t) {
+        q.traj_index = p->traj_index + (uint64_t)t;
+        const bool model = p->surrogate && exact_left == 0;
+        q.surrogate = model ? p->surrogate : nullptr;
+        q.judge_model = model ? 1 : 0;
+        q.exact_every = model ? p->exact_every : 1;
+        q.coarse_force = model ? p->coarse_force : 0;
+        q.record_pairs = model ? p->record_pairs : 0;
+        q.inner_iters = model ? p->inner_iters : 0;
+        if ((e = stag_md_trajectory(c, &q, &infos[t]))) return e;
+        if (n_done) *n_done = t + 1;
+        if (!model) {
+            if (exact_left > 0) --exact_left;
+            continue;
+        }
+        recent.push_back(infos[t].accepted);
+        if ((int)recent.size() > pol->window) recent.erase(recent.begin());
+        bool fall_back = infos[t].model_force_err > pol->max_model_err;
+        if ((int)recent.size() == pol->window) {
+            int acc = 0;
+            for (int a : recent) acc += a;
+            if ((double)acc < pol->min_acceptance * pol->window) fall_back = true;
+        }
+        if (fall_back) {
+            exact_left = pol->exact_trajectories;
+            recent.clear();
+        }
+    }
     return STAG_OK;
 }
 

@@ -37,6 +37,7 @@ struct stag_ctx {
     double* mom = nullptr;
     double* mom_tmp = nullptr;   // force staging when a trajectory records training pairs
     double* mom_aux = nullptr;   // truncated-solve force fed to a learned model
+    double* mom_judge = nullptr; // a model's force at an exact kick (judge_model)
     // FP64 Krylov workspace
     double2 *r = nullptr /* ring of kLagMax residuals */, *p = nullptr, *Ap = nullptr, *w_o = nullptr, *tmp_e = nullptr, *tmp_o = nullptr;
     double2* p2 = nullptr;   // second search direction (the fused loop double-buffers p)

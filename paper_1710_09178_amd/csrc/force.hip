@@ -380,10 +380,29 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(size_t n, const double* __rest
 
 }  // namespace
 
+// block partials of |a - b|^2 and |b|^2 over n reals, then their totals into out2[0..1]
+__global__ __launch_bounds__(kBlock) void k_diff_norm2(size_t n, const double* __restrict__ a,
+                                                       const double* __restrict__ b, double* __restrict__ part) {
+    double v[2] = {0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const double bi = b[i], d = a[i] - bi;
+        v[0] += d * d;
+        v[1] += bi * bi;
+    }
+    block_partial<2>(v, part);
+}
+
 void launch_fermion_force(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,
                           double* mom, double dt, hipStream_t s, double w1) {
     const int grid = (8 * g.vh + kBlock - 1) / kBlock;
     k_fermion_force<<<grid, kBlock, 0, s>>>(g, links, X, Y, coef, n, mom, dt, w1);
+}
+
+// part: >= 2 * 1024 doubles
+void launch_diff_norm2(size_t n, const double* a, const double* b, double* part, double* out2, hipStream_t s) {
+    constexpr int nb = 1024;
+    k_diff_norm2<<<nb, kBlock, 0, s>>>(n, a, b, part);
+    launch_finalize(part, nb, 2, out2, s);
 }
 
 void launch_naik_force3(const Geom& g, const double2* links, VecPtrs X, VecPtrs Y, const double* coef, int n,

@@ -63,14 +63,20 @@ class CHMCParams(ctypes.Structure):
                 ("surrogate", ctypes.c_void_p), ("exact_every", ctypes.c_int),
                 ("coarse_force", ctypes.c_int), ("record_pairs", ctypes.c_int), ("inner_iters", ctypes.c_int),
                 ("md_link_format", ctypes.c_int), ("spectrum_lo", ctypes.c_double),
-                ("spectrum_hi", ctypes.c_double)]
+                ("spectrum_hi", ctypes.c_double), ("judge_model", ctypes.c_int)]
 
 
 class CTrajInfo(ctypes.Structure):
     _fields_ = [("dH", ctypes.c_double), ("K_old", ctypes.c_double), ("Sg_old", ctypes.c_double),
                 ("Sf_old", ctypes.c_double), ("K_new", ctypes.c_double), ("Sg_new", ctypes.c_double),
                 ("Sf_new", ctypes.c_double), ("plaquette", ctypes.c_double), ("accepted", ctypes.c_int),
-                ("cg_iters_total", ctypes.c_int), ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double)]
+                ("cg_iters_total", ctypes.c_int), ("n_solves", ctypes.c_int), ("seconds", ctypes.c_double),
+                ("model_force_err", ctypes.c_double), ("used_model", ctypes.c_int)]
+
+
+class CChainPolicy(ctypes.Structure):
+    _fields_ = [("window", ctypes.c_int), ("min_acceptance", ctypes.c_double),
+                ("max_model_err", ctypes.c_double), ("exact_trajectories", ctypes.c_int)]
 
 
 class CBatchOpts(ctypes.Structure):
@@ -142,6 +148,8 @@ def load_library() -> ctypes.CDLL:
         "stag_philox": (S, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32), ctypes.c_size_t,
                             P, P]),
         "stag_md_trajectory": (S, [H, ctypes.POINTER(CHMCParams), ctypes.POINTER(CTrajInfo)]),
+        "stag_md_chain": (S, [H, ctypes.POINTER(CHMCParams), ctypes.c_int, ctypes.POINTER(CChainPolicy),
+                              ctypes.POINTER(CTrajInfo), ctypes.POINTER(ctypes.c_int)]),
         "stag_batch_create": (S, [ctypes.POINTER(H), I, ctypes.POINTER(ctypes.c_int), I, P]),
         "stag_batch_destroy": (S, [H]),
         "stag_batch_last_error": (ctypes.c_char_p, [H]),
@@ -455,20 +463,31 @@ class Lattice:
         self._check(self.lib.stag_random_source(self.h, int(seed), int(traj), _ptr(out)))
         return out
 
+    def _hmc_params(self, args, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md, tol_action,
+                    maxiter, seed, traj_index, inject_mom, inject_xi, inject_u, no_fermions, surrogate,
+                    exact_every, coarse_force, record_pairs, inner_iters, md_link_format, spectrum, judge_model):
+        a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
+        args.extend((a, b, c))  # the coefficient arrays live as long as the caller's list
+        return CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
+                          self._mom(inject_mom, "inject_mom", True), self._vec(inject_xi, "inject_xi", True),
+                          inject_u, int(no_fermions),
+                          surrogate.h if surrogate is not None else None, int(exact_every),
+                          int(coarse_force), int(record_pairs), int(inner_iters), int(md_link_format),
+                          *(map(float, spectrum) if spectrum is not None else (0.0, 0.0)), int(judge_model))
+
     def trajectory(self, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md=1e-10, tol_action=1e-10,
                    maxiter=100000, seed=0, traj_index=0, inject_mom=None, inject_xi=None, inject_u=-1.0,
                    no_fermions=False, surrogate=None, exact_every=1, coarse_force=False,
-                   record_pairs=False, inner_iters=0, md_link_format=0, spectrum=None, log=None) -> dict:
+                   record_pairs=False, inner_iters=0, md_link_format=0, spectrum=None, judge_model=False,
+                   log=None) -> dict:
         """One RHMC trajectory (stag_md_trajectory); returns the trajectory
         info as a dict.  log: a path or open text file that receives the info
         with the trajectory's parameters as one JSON line."""
-        a, b, c = RationalArg(r_md), RationalArg(r_action), RationalArg(r_heatbath)
-        prm = CHMCParams(beta, mass, tau, n_steps, a.c, b.c, c.c, tol_md, tol_action, maxiter, seed, traj_index,
-                         self._mom(inject_mom, "inject_mom", True), self._vec(inject_xi, "inject_xi", True),
-                         inject_u, int(no_fermions),
-                         surrogate.h if surrogate is not None else None, int(exact_every),
-                         int(coarse_force), int(record_pairs), int(inner_iters), int(md_link_format),
-                         *(map(float, spectrum) if spectrum is not None else (0.0, 0.0)))
+        keep = []
+        prm = self._hmc_params(keep, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md, tol_action,
+                               maxiter, seed, traj_index, inject_mom, inject_xi, inject_u, no_fermions, surrogate,
+                               exact_every, coarse_force, record_pairs, inner_iters, md_link_format, spectrum,
+                               judge_model)
         info = CTrajInfo()
         self._check(self.lib.stag_md_trajectory(self.h, ctypes.byref(prm), ctypes.byref(info)))
         out = {k: getattr(info, k) for k, _ in CTrajInfo._fields_}
@@ -477,6 +496,32 @@ class Lattice:
                                    mass=float(mass), tau=float(tau), n_steps=int(n_steps),
                                    exact_every=int(exact_every), model=surrogate is not None,
                                    md_link_format=int(md_link_format)))
+        return out
+
+    def chain(self, n_traj, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, window=4, min_acceptance=0.5,
+              max_model_err=0.5, exact_trajectories=2, tol_md=1e-10, tol_action=1e-10, maxiter=100000, seed=0,
+              traj_index=0, surrogate=None, exact_every=1, coarse_force=False, inner_iters=0, md_link_format=0,
+              spectrum=None, log=None) -> list:
+        """n_traj trajectories with the exact force judging the model and
+        standing in for it (stag_md_chain); returns one info dict per
+        trajectory.  log: as in trajectory(), one JSON line per trajectory."""
+        keep = []
+        prm = self._hmc_params(keep, beta, mass, tau, n_steps, r_md, r_action, r_heatbath, tol_md, tol_action,
+                               maxiter, seed, traj_index, None, None, -1.0, False, surrogate, exact_every,
+                               coarse_force, False, inner_iters, md_link_format, spectrum, True)
+        pol = CChainPolicy(int(window), float(min_acceptance), float(max_model_err), int(exact_trajectories))
+        infos = (CTrajInfo * max(int(n_traj), 1))()
+        done = ctypes.c_int()
+        code = self.lib.stag_md_chain(self.h, ctypes.byref(prm), int(n_traj), ctypes.byref(pol), infos,
+                                      ctypes.byref(done))
+        out = [{k: getattr(infos[t], k) for k, _ in CTrajInfo._fields_} for t in range(done.value)]
+        if log is not None:
+            for t, rec in enumerate(out):
+                append_jsonl(log, dict(rec, seed=int(seed), traj_index=int(traj_index) + t, beta=float(beta),
+                                       mass=float(mass), tau=float(tau), n_steps=int(n_steps),
+                                       exact_every=int(exact_every) if rec["used_model"] else 1,
+                                       model=bool(rec["used_model"]), md_link_format=int(md_link_format)))
+        self._check(code)
         return out
 
     # ---- measurement / tuning

@@ -294,6 +294,101 @@ def test_trajectory_with_truncated_inner_force():
         lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, inner_iters=10, **kw)
 
 
+def test_judged_trajectory_reports_the_model_force_error():
+    """judge_model: at the exact kick of a one-step trajectory (kick 0 on the
+    starting links; kick 1 is the model's) the reported error is
+    |F_model - F| / |F| of the model's and the exact force on those links,
+    recomputed here from the same injected source; a zero model gives 1."""
+    dims = (4, 4, 2, 4)
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(708, 0))
+    r_f = synth.load_rational("xm050_n8_m0.1")
+    r_h = synth.load_rational("xp025_n8_m0.1")
+    lat = lattice(dims, U0)
+    sur = stag.Surrogate(lat, 1)
+    sur.set_params(_flat(_params(6)))
+    xi, mom0 = lat.random_source(11, 0), lat.random_momentum(11, 0)
+    kw = dict(seed=3, traj_index=1, inject_mom=mom0, inject_xi=xi, inject_u=0.0, exact_every=2)
+    t = lat.trajectory(5.4, 0.1, 0.5, 1, r_f, r_f, r_h, surrogate=sur, judge_model=True, **kw)
+    assert t["used_model"] == 1
+    lat.set_gauge(dev(U0))
+    phi = lat.new_vec()
+    lat.multishift_solve(0.1, r_h, 1e-10, 100000, xi, sum_out=phi)
+    F, Fm = lat.new_mom(), lat.new_mom()
+    lat.fermion_force(0.1, r_f, 1e-10, 100000, phi, F, 0.0)
+    sur.force(Fm)
+    f, fm = host(F), host(Fm)
+    exp = np.sqrt(((fm - f) ** 2).sum() / (f ** 2).sum())
+    log(f"  judged model force error {t['model_force_err']:.6e} (host {exp:.6e})")
+    assert 0.0 < exp and abs(t["model_force_err"] - exp) < 1e-9 * exp
+    # without the judge the trajectory is the same update up to the kick's rounding
+    lat.set_gauge(dev(U0))
+    u = lat.trajectory(5.4, 0.1, 0.5, 1, r_f, r_f, r_h, surrogate=sur, **kw)
+    assert u["model_force_err"] == -1.0 and abs(u["dH"] - t["dH"]) < 1e-9 * max(1.0, abs(t["dH"]))
+    zero = stag.Surrogate(lat, 1)
+    zero.set_params(np.zeros(zero.n_params, dtype=np.float32))
+    lat.set_gauge(dev(U0))
+    z = lat.trajectory(5.4, 0.1, 0.5, 2, r_f, r_f, r_h, surrogate=zero, judge_model=True, **kw)
+    assert z["model_force_err"] == 1.0
+    lat.set_gauge(dev(U0))
+    e = lat.trajectory(5.4, 0.1, 0.5, 1, r_f, r_f, r_h, judge_model=True, **kw)
+    assert e["used_model"] == 0 and e["model_force_err"] == -1.0
+
+
+def _chain_reference(lat, U0, pattern, args, kw, sur):
+    """The chain's trajectories replayed one by one with the given schedule."""
+    lat.set_gauge(dev(U0))
+    out = []
+    for t, use in enumerate(pattern):
+        extra = dict(surrogate=sur, exact_every=2, judge_model=True) if use else {}
+        out.append(lat.trajectory(*args, seed=kw["seed"], traj_index=kw["traj_index"] + t, **extra))
+    return out, host(lat.get_gauge())
+
+
+def test_chain_falls_back_to_the_exact_force():
+    """stag_md_chain: a model whose judged error exceeds the bound hands the
+    next exact_trajectories trajectories to the exact force; a model whose
+    trajectories are all rejected does so once the acceptance window fills;
+    every trajectory equals the one-by-one call with the same schedule."""
+    dims = (4, 4, 2, 4)
+    U0 = synth.random_su3_near_identity(dims, 0.4, synth.make_rng(708, 1))
+    r_f = synth.load_rational("xm050_n8_m0.1")
+    r_h = synth.load_rational("xp025_n8_m0.1")
+    lat = lattice(dims, U0)
+    args = (5.4, 0.1, 0.5, 4, r_f, r_f, r_h)
+    kw = dict(seed=7, traj_index=20)
+    zero = stag.Surrogate(lat, 1)
+    zero.set_params(np.zeros(zero.n_params, dtype=np.float32))
+    # the zero model's judged error is 1 > 0.5: model, exact, exact, model, ...
+    got = lat.chain(7, *args, surrogate=zero, exact_every=2, max_model_err=0.5, min_acceptance=0.0,
+                    exact_trajectories=2, **kw)
+    Ug = host(lat.get_gauge())
+    assert [g["used_model"] for g in got] == [1, 0, 0, 1, 0, 0, 1]
+    assert all((g["model_force_err"] == 1.0) == bool(g["used_model"]) for g in got)
+    ref, Ur = _chain_reference(lat, U0, [1, 0, 0, 1, 0, 0, 1], args, kw, zero)
+    assert [g["dH"] for g in got] == [r["dH"] for r in ref]
+    assert [g["accepted"] for g in got] == [r["accepted"] for r in ref]
+    assert np.array_equal(Ug, Ur)
+    # a wild model (large constant force): rejected, window 2 of acceptance 0
+    wild = stag.Surrogate(lat, 1)
+    p = {k: np.zeros_like(v) for k, v in _params(0).items()}
+    p["b3"][:6] = 40.0
+    wild.set_params(_flat(p))
+    lat.set_gauge(dev(U0))
+    got = lat.chain(7, *args, surrogate=wild, exact_every=2, max_model_err=1e30, min_acceptance=0.5, window=2,
+                    exact_trajectories=2, **kw)
+    assert [g["used_model"] for g in got] == [1, 1, 0, 0, 1, 1, 0]
+    assert all(g["accepted"] == 0 for g in got if g["used_model"])
+    # no model: plain RHMC, trajectory indices counting up
+    lat.set_gauge(dev(U0))
+    plain = lat.chain(3, *args, **kw)
+    ref, _ = _chain_reference(lat, U0, [0, 0, 0], args, kw, None)
+    assert [g["dH"] for g in plain] == [r["dH"] for r in ref] and not any(g["used_model"] for g in plain)
+    with pytest.raises(stag.StagError):
+        lat.chain(2, *args, surrogate=zero, window=0, **kw)
+    with pytest.raises(stag.StagError):
+        lat.chain(2, *args, surrogate=zero, max_model_err=0.0, **kw)
+
+
 def test_model_error_paths():
     lat = lattice(DIMS, synth.random_su3_near_identity(DIMS, 0.3, synth.make_rng(707, 0)))
     sur = stag.Surrogate(lat, 1)
