@@ -1043,12 +1043,15 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     pseudofermions: exact force on every kick, and for exact_every in (2, 4)
     a two-time-scale leapfrog with the exact force on the outer scale and on
     the inner scale (a) nothing (the ablation), (b) the truncated-solve force
-    alone, (c) the trained model (which also sees the truncated-solve force).
+    alone, (c) the trained model (which also sees the truncated-solve force);
+    then the model's chain once more under stag_md_chain, the exact force
+    judging the model at its exact kicks and taking over on a policy.
     Accept/reject always uses the exact action."""
     import numpy as np
     import torch
 
     import synth
+    from paper_1710_09178_amd import stag
     from paper_1710_09178_amd.stag import Lattice, Surrogate
     dims = (16, 16, 16, 8)
     beta, mass, tau, n_steps = 5.4, 0.02, 1.0, 20
@@ -1107,6 +1110,10 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
     lat.set_fused_iteration(True)
     # precision form in the trajectory: MD force solves with FP32 Krylov vectors
     md = {"fp32_links18": timed_chain(md_link_format=2), "fp32_fp16links12": timed_chain(md_link_format=3)}
+    # every solve of the trajectory with FP64 12-real links (row 2 rebuilt; exact to rounding)
+    lat.set_link_format(stag.LINKS_F64_12)
+    md["fp64_links12_all_solves"] = timed_chain()
+    lat.set_link_format(stag.LINKS_F64_18)
     for v in md.values():
         v["speedup_vs_fp64"] = round(out["sec_per_trajectory"]["sec_per_traj"] / v["sec_per_traj"], 3)
     out["md_precision_forms"] = md
@@ -1183,6 +1190,24 @@ def rhmc(with_model=True, n_exact=10, n_pairs=2000, n_traj=24, train_seconds=25.
             chains[f"ablation_no_inner_force_exact_every_{every}"] = chain(**ms)
         chains[f"inner_truncated_solve_exact_every_{every}"] = chain(surrogate=ident, inner_iters=inner_iters, **ms)
         chains[f"inner_learned_model_exact_every_{every}"] = chain(surrogate=sur, inner_iters=inner_iters, **ms)
+    # the exact force as the model's judge and fallback: the learned chain of
+    # the largest E once more, judged at its exact kicks, under a policy that
+    # hands trajectories to the exact force when the model errs or stalls
+    every = max(every_list)
+    policy = dict(window=8, min_acceptance=0.25, max_model_err=0.05, exact_trajectories=4)
+    log(f"judged chain of {n_traj} trajectories: exact_every={every}, policy {policy}")
+    lat.set_gauge(U_start)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = lat.chain(n_traj, beta, mass, tau, chain_steps, r_f, r_a, r_h, traj_index=10 ** 6, surrogate=sur,
+                    inner_iters=inner_iters, exact_every=every, coarse_force=True, **policy, **kw)
+    torch.cuda.synchronize()
+    judged = summary(res, (time.perf_counter() - t1) / n_traj)
+    errs = [r["model_force_err"] for r in res if r["used_model"]]
+    judged.update(policy=policy, model_trajectories=len(errs), fallback_trajectories=n_traj - len(errs),
+                  judged_model_force_err_mean=round(float(np.mean(errs)), 5) if errs else None,
+                  judged_model_force_err_max=round(float(np.max(errs)), 5) if errs else None)
+    chains[f"judged_learned_model_chain_exact_every_{every}"] = judged
     for k, v in chains.items():
         v["speedup_vs_exact"] = round(chains["exact"]["sec_per_traj"] / v["sec_per_traj"], 3)
     out["learned_force_rhmc"] = {

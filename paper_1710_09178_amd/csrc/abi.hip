@@ -871,8 +871,13 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     const bool sched = p->surrogate != nullptr || p->coarse_force;
     // the model's auxiliary channel: the pseudofermion force of the current
     // links from the multi-shift solve of r_md stopped after inner_iters
-    // iterations (a deterministic function of the links and phi)
+    // iterations (a deterministic function of the links and phi), so it is
+    // solved once per link field (link_version counts this trajectory's link
+    // updates)
+    int link_version = 0, aux_version = -1;
     auto truncated_aux = [&]() -> stag_status {
+        if (aux_version == link_version) return STAG_OK;
+        aux_version = link_version;
         SolveResult rt;
         stag_status e2 = fermion_force_impl(c, p->mass, &p->r_md, 0.0, p->inner_iters, c->phi, c->mom_aux, 0.0, rt);
         if (e2) return e2;
@@ -931,6 +936,7 @@ stag_status stag_md_trajectory(stag_handle c, const stag_hmc_params* p, stag_tra
     for (int step = 0; step < p->n_steps; ++step) {
         launch_link_update(g, c->links, c->mom, dt, c->s);
         links_changed(c);
+        ++link_version;
         if ((e = kick(step < p->n_steps - 1 ? dt : 0.5 * dt))) return e;
     }
     // step 3: Metropolis on the rational action

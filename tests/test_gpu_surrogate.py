@@ -287,6 +287,12 @@ def test_trajectory_with_truncated_inner_force():
     assert np.isfinite(b["dH"]) and b["dH"] != a["dH"]
     # 5 kicks, exact on 0, 2, 4; the model on every kick: 5 truncated solves
     assert b["n_solves"] == a["n_solves"] + 5
+    # judging the model at the exact kicks reuses their solves
+    lat.set_gauge(dev(U0))
+    j = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, coarse_force=True, exact_every=2, surrogate=ident,
+                       inner_iters=10, judge_model=True, **kw)
+    assert j["n_solves"] == b["n_solves"] and j["cg_iters_total"] == b["cg_iters_total"]
+    assert abs(j["dH"] - b["dH"]) < 1e-9 * max(1.0, abs(b["dH"])) and 0.0 < j["model_force_err"] < np.inf
     lat.set_gauge(dev(U0))
     rec = lat.trajectory(5.4, 0.1, 0.5, 4, r_f, r_f, r_h, surrogate=ident, record_pairs=True, inner_iters=10, **kw)
     assert ident.pairs == 2 and np.isfinite(rec["dH"])
