@@ -110,3 +110,39 @@ def test_product_package_does_not_use_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Size and field offsets of every struct the binding mirrors, compiled
+    from include/stag.h by the host C compiler, against the ctypes
+    structures (a field added to one side only would shift every later one)."""
+    import shutil
+
+    from paper_1710_09178_amd import stag
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"stag_rational": stag.CRational, "stag_solve_info": stag.CSolveInfo,
+             "stag_mixed_opts": stag.CMixedOpts, "stag_hmc_params": stag.CHMCParams,
+             "stag_traj_info": stag.CTrajInfo, "stag_chain_policy": stag.CChainPolicy,
+             "stag_batch_opts": stag.CBatchOpts, "stag_batch_info": stag.CBatchInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "stag.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
