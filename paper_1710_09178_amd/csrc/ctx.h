@@ -59,7 +59,7 @@ struct stag_ctx {
     int* done_host = nullptr;            // pinned [2]
     bool has_gauge = false;
     int tps = 4;                         // threads per site in the Dslash
-    int chunk = 16;                      // iterations enqueued between convergence polls
+    int chunk = 64;                      // iterations enqueued between convergence polls
     int lag = 8;                         // shift-update window of the multi-shift solver
     int use_graph = 1;                   // replay iteration chunks from captured hipGraphs
     int fused = 1;                       // FP64 solves fold the base update into the D_oe launch
