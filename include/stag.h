@@ -417,7 +417,8 @@ stag_status stag_md_trajectory(stag_handle h, const stag_hmc_params* p, stag_tra
  * whichever force drove it), while the choice between the two integrators
  * depends on the chain's history, as in any adaptive scheme.  The fallback
  * trajectories run with exact_every 1 and without coarse_force,
- * record_pairs or inner_iters.  infos: host [n_traj]; n_done (may be NULL):
+ * record_pairs or inner_iters; without a model (p->surrogate NULL) every
+ * trajectory runs with p's own schedule.  infos: host [n_traj]; n_done (may be NULL):
  * the trajectories completed (all of them unless an error stops the chain,
  * whose status is returned).  STAG_ERR_INVALID_ARG for window < 1,
  * exact_trajectories < 1, max_model_err <= 0 or min_acceptance outside

@@ -998,12 +998,14 @@ stag_status stag_md_chain(stag_handle c, const stag_hmc_params* p, int n_traj, c
     for (int t = 0; t < n_traj; ++t) {
         q.traj_index = p->traj_index + (uint64_t)t;
         const bool model = p->surrogate && exact_left == 0;
-        q.surrogate = model ? p->surrogate : nullptr;
-        q.judge_model = model ? 1 : 0;
-        q.exact_every = model ? p->exact_every : 1;
-        q.coarse_force = model ? p->coarse_force : 0;
-        q.record_pairs = model ? p->record_pairs : 0;
-        q.inner_iters = model ? p->inner_iters : 0;
+        if (p->surrogate) {  // without a model every trajectory keeps p's schedule
+            q.surrogate = model ? p->surrogate : nullptr;
+            q.judge_model = model ? 1 : 0;
+            q.exact_every = model ? p->exact_every : 1;
+            q.coarse_force = model ? p->coarse_force : 0;
+            q.record_pairs = model ? p->record_pairs : 0;
+            q.inner_iters = model ? p->inner_iters : 0;
+        }
         if ((e = stag_md_trajectory(c, &q, &infos[t]))) return e;
         if (n_done) *n_done = t + 1;
         if (!model) {

@@ -389,6 +389,13 @@ def test_chain_falls_back_to_the_exact_force():
     plain = lat.chain(3, *args, **kw)
     ref, _ = _chain_reference(lat, U0, [0, 0, 0], args, kw, None)
     assert [g["dH"] for g in plain] == [r["dH"] for r in ref] and not any(g["used_model"] for g in plain)
+    # without a model the chain keeps the given schedule (here the two-time-scale ablation)
+    lat.set_gauge(dev(U0))
+    abl = lat.chain(2, *args, coarse_force=True, exact_every=2, **kw)
+    lat.set_gauge(dev(U0))
+    ref = [lat.trajectory(*args, seed=kw["seed"], traj_index=kw["traj_index"] + t, coarse_force=True,
+                          exact_every=2) for t in range(2)]
+    assert [g["dH"] for g in abl] == [r["dH"] for r in ref] and abl[0]["dH"] != plain[0]["dH"]
     with pytest.raises(stag.StagError):
         lat.chain(2, *args, surrogate=zero, window=0, **kw)
     with pytest.raises(stag.StagError):
